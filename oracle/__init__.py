@@ -1,0 +1,215 @@
+"""Float64 CPU oracle for the Doppler / ionospheric correction path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this module.  The product library
+(``paper_2508_04951_amd``) never imports it, and this module never imports the
+product library: the two share no code.
+
+The arithmetic lives in ``rc_oracle.c`` (plain C, float64), which follows the
+paper (arXiv 2508.04951) equation by equation:
+
+* Eq (1)-(2): Doppler dilation factor and the dilated signal S(alpha t);
+* Eq (17) with App. C: windowed Whittaker-Shannon (sinc) resampling;
+* Eq (3) / App. A: ionospheric group delay tau(f) = K2 / (c f^2);
+* Eq (15) / Eq (16): FFT phase distortion / correction.
+
+This file only marshals numpy arrays into that library (built with gcc).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rc_oracle.c")
+_SO = os.path.join(_HERE, "librc_oracle.so")
+
+WINDOWS = {"kaiser": 0, "rect": 1, "paper": 2}
+DIRECTIONS = {"correct": 0, "distort": 1}
+C_LIGHT = 299792458.0
+TECU = 1e16
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile rc_oracle.c into librc_oracle.so (gcc, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
+    p = ctypes.c_void_p
+    lib.rco_alpha_from_vr.restype = d
+    lib.rco_alpha_from_vr.argtypes = [d]
+    lib.rco_k2_per_tec.restype = d
+    lib.rco_k2_per_tec.argtypes = []
+    lib.rco_bessel_i0.restype = d
+    lib.rco_bessel_i0.argtypes = [d]
+    lib.rco_kaiser.restype = d
+    lib.rco_kaiser.argtypes = [d, d]
+    lib.rco_sinc.restype = d
+    lib.rco_sinc.argtypes = [d]
+    lib.rco_bin_frequency.restype = d
+    lib.rco_bin_frequency.argtypes = [i64, i64, d, d]
+    lib.rco_num_threads.restype = i32
+    lib.rco_num_threads.argtypes = []
+    lib.rco_doppler.restype = i32
+    lib.rco_doppler.argtypes = [p, i64, p, i64, d, i32, i32, d]
+    lib.rco_doppler_at.restype = i32
+    lib.rco_doppler_at.argtypes = [p, i64, p, i64, p, d, i32, i32, d]
+    lib.rco_dft.restype = i32
+    lib.rco_dft.argtypes = [p, p, i64, i32]
+    lib.rco_fft.restype = i32
+    lib.rco_fft.argtypes = [p, p, i64, i32]
+    lib.rco_iono_response.restype = i32
+    lib.rco_iono_response.argtypes = [i64, d, d, d, i32, p]
+    lib.rco_ionosphere.restype = i32
+    lib.rco_ionosphere.argtypes = [p, p, i64, d, d, d, i32, i32]
+    lib.rco_pulse.restype = i32
+    lib.rco_pulse.argtypes = [p, i64, p, i64, d, d, d, d, i32, i32, i32, i32, i32, d, i32]
+    _lib = lib
+    return lib
+
+
+def _c128(x) -> np.ndarray:
+    """Exact upcast of the samples (e.g. the complex64 the GPU sees) to complex128."""
+    return np.ascontiguousarray(np.asarray(x), dtype=np.complex128)
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise ValueError(f"oracle {what} rejected its arguments (code {rc})")
+
+
+def num_threads() -> int:
+    return int(_load().rco_num_threads())
+
+
+def alpha_from_vr(v_r: float) -> float:
+    """Eq (1): alpha = (1 + v_r/c)/(1 - v_r/c), v_r positive when approaching."""
+    return float(_load().rco_alpha_from_vr(float(v_r)))
+
+
+def k2_per_tec() -> float:
+    """Eq (3): K2/E = e^2/(8 pi^2 m_e eps0) in m^3 s^-2 (CODATA 2022)."""
+    return float(_load().rco_k2_per_tec())
+
+
+def bessel_i0(z: float) -> float:
+    return float(_load().rco_bessel_i0(float(z)))
+
+
+def kaiser(x: float, beta: float) -> float:
+    return float(_load().rco_kaiser(float(x), float(beta)))
+
+
+def sinc(u: float) -> float:
+    return float(_load().rco_sinc(float(u)))
+
+
+def bin_frequency(k: int, n: int, fs: float, carrier: float) -> float:
+    return float(_load().rco_bin_frequency(int(k), int(n), float(fs), float(carrier)))
+
+
+def doppler(x, alpha: float, half_width: int = 64, window: str = "kaiser", beta: float = 8.0,
+            n_out: int | None = None) -> np.ndarray:
+    """Eq (2)/(17): y[m] = S(alpha m) by the windowed sinc sum (half_width 0 = full sum)."""
+    xin = _c128(x)
+    n_out = xin.size if n_out is None else int(n_out)
+    y = np.zeros(n_out, dtype=np.complex128)
+    rc = _load().rco_doppler(_ptr(xin), xin.size, _ptr(y), n_out, float(alpha), int(half_width),
+                             WINDOWS[window], float(beta))
+    _check(rc, "doppler")
+    return y
+
+
+def doppler_at(x, idx, alpha: float, half_width: int = 64, window: str = "kaiser",
+               beta: float = 8.0) -> np.ndarray:
+    """The resampling sum evaluated only at output indices ``idx``."""
+    xin = _c128(x)
+    ii = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    y = np.zeros(ii.size, dtype=np.complex128)
+    rc = _load().rco_doppler_at(_ptr(xin), xin.size, _ptr(ii), ii.size, _ptr(y), float(alpha),
+                                int(half_width), WINDOWS[window], float(beta))
+    _check(rc, "doppler_at")
+    return y
+
+
+def dft(x, sign: int = -1) -> np.ndarray:
+    """Naive O(N^2) DFT with exact (k n mod N) angles."""
+    xin = _c128(x)
+    X = np.empty_like(xin)
+    _check(_load().rco_dft(_ptr(xin), _ptr(X), xin.size, int(sign)), "dft")
+    return X
+
+
+def fft(x, sign: int = -1) -> np.ndarray:
+    """Float64 FFT of any length (radix 2, Bluestein otherwise), unnormalised."""
+    xin = _c128(x)
+    X = np.empty_like(xin)
+    _check(_load().rco_fft(_ptr(xin), _ptr(X), xin.size, int(sign)), "fft")
+    return X
+
+
+def iono_response(n: int, fs: float, carrier: float, tec: float,
+                  direction: str = "correct") -> np.ndarray:
+    """Per-bin factor of Eq (16) (correct) or Eq (15) (distort)."""
+    H = np.empty(int(n), dtype=np.complex128)
+    rc = _load().rco_iono_response(int(n), float(fs), float(carrier), float(tec),
+                                   DIRECTIONS[direction], _ptr(H))
+    _check(rc, "iono_response")
+    return H
+
+
+def ionosphere(x, fs: float, carrier: float, tec: float, direction: str = "correct",
+               naive: bool | None = None) -> np.ndarray:
+    """Eq (15)/(16): IDFT(DFT(x) * H).  ``naive`` defaults to the O(N^2) DFT for N <= 4096."""
+    xin = _c128(x)
+    if naive is None:
+        naive = xin.size <= 4096
+    y = np.empty_like(xin)
+    rc = _load().rco_ionosphere(_ptr(xin), _ptr(y), xin.size, float(fs), float(carrier),
+                                float(tec), DIRECTIONS[direction], int(bool(naive)))
+    _check(rc, "ionosphere")
+    return y
+
+
+def correct_pulse(x, fs: float, alpha: float, tec: float, carrier: float, *, n_out: int | None = None,
+                  doppler_on: bool = True, iono_on: bool = True, direction: str = "correct",
+                  half_width: int = 64, window: str = "kaiser", beta: float = 8.0,
+                  naive: bool = False) -> np.ndarray:
+    """One batch element: Doppler resampling first, then the ionospheric operator."""
+    xin = _c128(x)
+    n_out = xin.size if n_out is None else int(n_out)
+    y = np.empty(n_out, dtype=np.complex128)
+    rc = _load().rco_pulse(_ptr(xin), xin.size, _ptr(y), n_out, float(fs), float(alpha), float(tec),
+                           float(carrier), int(doppler_on), int(iono_on), DIRECTIONS[direction],
+                           int(half_width), WINDOWS[window], float(beta), int(bool(naive)))
+    _check(rc, "pulse")
+    return y
+
+
+def doppler_bank(x, alphas, half_width: int = 64, window: str = "kaiser", beta: float = 8.0,
+                 n_out: int | None = None) -> np.ndarray:
+    """Doppler resampling of one pulse for every hypothesis alpha_h: shape (H, n_out)."""
+    return np.stack([doppler(x, a, half_width, window, beta, n_out) for a in alphas])

@@ -1,0 +1,148 @@
+"""Pins of the float64 oracle's ionospheric operator and transforms against facts the
+paper and the mathematics fix (no GPU).
+
+Delay model: Eq (3) with App. A (tau(f) = K2/(c f^2), K2 = e^2 E/(8 pi^2 m_e eps0));
+operator: Eq (15) (distortion, +) and Eq (16) (correction, -); Fourier convention of
+Sec. II-B (g_hat(f) = int g(t) exp(-2 pi i t f) dt, so a delay t0 multiplies by
+exp(-2 pi i t0 f)).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.constants as sc
+
+import waveforms as wf
+
+FS = 10e6
+FC = 450e6
+
+
+def _phi(tec):
+    """4 pi K2 / c with K2 from scipy's CODATA constants (independent of the oracle)."""
+    k2 = sc.e ** 2 / (8 * math.pi ** 2 * sc.m_e * sc.epsilon_0) * tec
+    return 4 * math.pi * k2 / sc.c
+
+
+def test_k2_constant_vs_scipy(orc):
+    ref = sc.e ** 2 / (8 * math.pi ** 2 * sc.m_e * sc.epsilon_0)
+    assert orc.k2_per_tec() == pytest.approx(ref, rel=1e-13)
+    assert orc.k2_per_tec() == pytest.approx(40.308, rel=1e-4)  # the textbook 40.3 m^3/s^2
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 100, 1000])
+def test_naive_dft_vs_numpy(orc, n):
+    rng = wf.rng_for(21, n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    X = orc.dft(x)
+    np.testing.assert_allclose(X, np.fft.fft(x), rtol=0, atol=1e-12 * max(1, np.abs(X).max()))
+    np.testing.assert_allclose(orc.dft(x, +1), np.fft.ifft(x) * n, rtol=0,
+                               atol=1e-12 * max(1, np.abs(X).max()))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 12, 64, 97, 1000, 4096, 3 * 1024])
+def test_fft_vs_dft_and_numpy(orc, n):
+    rng = wf.rng_for(22, n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    X = orc.fft(x)
+    scale = max(1.0, np.abs(X).max())
+    np.testing.assert_allclose(X, np.fft.fft(x), rtol=0, atol=1e-12 * scale)
+    if n <= 1000:
+        np.testing.assert_allclose(X, orc.dft(x), rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(orc.fft(x, +1), np.fft.ifft(x) * n, rtol=0, atol=1e-12 * scale)
+
+
+def test_parseval(orc):
+    x = wf.bandlimited_noise(1000, wf.rng_for(23, 0)).astype(np.complex128)
+    X = orc.fft(x)
+    assert np.sum(np.abs(x) ** 2) == pytest.approx(np.sum(np.abs(X) ** 2) / x.size, rel=1e-13)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 4096, 4097])
+def test_bin_frequency_is_numpy_fftfreq(orc, n):
+    ks = sorted({0, 1, n // 2, (n + 1) // 2, n - 1} & set(range(n)))
+    ref = FC + FS * np.fft.fftfreq(n)
+    for k in ks:
+        assert orc.bin_frequency(k, n, FS, FC) == pytest.approx(ref[k], rel=1e-15)
+
+
+@pytest.mark.parametrize("n,k0", [(4096, 0), (4096, 5), (4096, 2048), (4096, 4093), (1000, 501), (97, 48)])
+@pytest.mark.parametrize("direction,sign", [("correct", -1.0), ("distort", +1.0)])
+def test_single_bin_tone_gets_exact_phase(orc, n, k0, direction, sign):
+    """A tone on bin k0 passes through Eq (15)/(16) as y = exp(+/- i 4 pi K2/(c f_k0)) x,
+    f_k0 the RF frequency of that bin (negative and Nyquist bins included)."""
+    tec = 50 * wf.TECU
+    x = np.exp(2j * np.pi * k0 * np.arange(n) / n)
+    f = FC + FS * np.fft.fftfreq(n)[k0]
+    expected = np.exp(1j * sign * _phi(tec) / f) * x
+    y = orc.ionosphere(x, FS, FC, tec, direction)
+    np.testing.assert_allclose(y, expected, rtol=0, atol=1e-11)
+
+
+def test_zero_frequency_bin_is_left_alone(orc):
+    """With the carrier at 0 (RF-sampled data) the DC bin has f = 0; its response is 1."""
+    n = 64
+    x = np.ones(n, dtype=np.complex128)
+    y = orc.ionosphere(x, 2.048e9, 0.0, 1e18, "correct")
+    np.testing.assert_allclose(y, x, atol=1e-13)
+
+
+def test_distort_then_correct_is_identity(orc):
+    x = wf.bandlimited_noise(4096, wf.rng_for(24, 0)).astype(np.complex128)
+    tec = 100 * wf.TECU
+    back = orc.ionosphere(orc.ionosphere(x, FS, FC, tec, "distort"), FS, FC, tec, "correct")
+    assert np.linalg.norm(back - x) / np.linalg.norm(x) < 1e-13
+
+
+def test_norm_is_preserved(orc):
+    x = wf.bandlimited_noise(3000, wf.rng_for(25, 0)).astype(np.complex128)
+    y = orc.ionosphere(x, FS, FC, 73 * wf.TECU, "correct")
+    assert np.linalg.norm(y) == pytest.approx(np.linalg.norm(x), rel=1e-13)
+
+
+def test_zero_tec_is_identity(orc):
+    x = wf.bandlimited_noise(512, wf.rng_for(26, 0)).astype(np.complex128)
+    np.testing.assert_allclose(orc.ionosphere(x, FS, FC, 0.0), x, atol=1e-14)
+
+
+def test_tec_is_additive(orc):
+    x = wf.bandlimited_noise(2048, wf.rng_for(27, 0)).astype(np.complex128)
+    e1, e2 = 20 * wf.TECU, 35 * wf.TECU
+    two = orc.ionosphere(orc.ionosphere(x, FS, FC, e1), FS, FC, e2)
+    one = orc.ionosphere(x, FS, FC, e1 + e2)
+    # the phases are ~2000 rad, whose float64 spacing is 4.5e-13 rad
+    assert np.linalg.norm(two - one) / np.linalg.norm(one) < 2e-12
+
+
+@pytest.mark.parametrize("f1", [0.0, 2e6, -3e6])
+def test_distortion_delays_envelope_by_two_way_group_delay(orc, f1):
+    """Eq (3) and the two-way factor: a narrowband Gaussian pulse at RF frequency
+    f = carrier + f1 comes out of Eq (15) delayed by 2 tau(f) = 2 K2/(c f^2)
+    (6.6 samples at 50 TECU, 450 MHz, 10 MHz sampling)."""
+    n, tec = 4096, 50 * wf.TECU
+    k = np.arange(n)
+    x = np.exp(-0.5 * ((k - 1500.0) / 120.0) ** 2) * np.exp(2j * np.pi * f1 / FS * k)
+    y = orc.ionosphere(x, FS, FC, tec, "distort", naive=False)
+    k2 = sc.e ** 2 / (8 * math.pi ** 2 * sc.m_e * sc.epsilon_0) * tec
+    expected = 2 * k2 / (sc.c * (FC + f1) ** 2) * FS
+    shift = np.sum(k * np.abs(y) ** 2) / np.sum(np.abs(y) ** 2) - 1500.0
+    assert shift == pytest.approx(expected, rel=2e-3)
+
+
+def test_naive_and_fast_transforms_agree(orc):
+    x = wf.bandlimited_noise(1536, wf.rng_for(28, 0)).astype(np.complex128)
+    a = orc.ionosphere(x, FS, FC, 42 * wf.TECU, naive=True)
+    b = orc.ionosphere(x, FS, FC, 42 * wf.TECU, naive=False)
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-12
+
+
+def test_pulse_is_doppler_then_ionosphere(orc):
+    """Batch reading: Doppler first, then the ionosphere on the resampled samples.  The two
+    orders differ by far more than the parity tolerance, so the order is part of the contract."""
+    x = wf.bandlimited_noise(2048, wf.rng_for(29, 0))
+    a, tec = orc.alpha_from_vr(7500.0), 80 * wf.TECU
+    got = orc.correct_pulse(x, FS, a, tec, FC, half_width=64)
+    ref = orc.ionosphere(orc.doppler(x, a, 64), FS, FC, tec, naive=False)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-13
+    swapped = orc.doppler(orc.ionosphere(x, FS, FC, tec, naive=False), a, 64)
+    assert np.linalg.norm(swapped - ref) / np.linalg.norm(ref) > 1e-3
