@@ -1,0 +1,226 @@
+"""Throughput benchmark of the correction path on one MI355X.
+
+Workload (N=1): the batch of 1024 pulses x 65536 complex64 samples of band-limited Gaussian
+noise (passband 0.8 fs), each with its own range rate v_r ~ U[-8, 8] km/s and TEC
+E ~ U[5, 100] TECU, corrected in one correct_pulse_batch call: Kaiser-windowed sinc
+resampling (H = 64, beta = 8) to S(alpha t), then the FFT ionospheric correction (Eq 16)
+at carrier 450 MHz, fs = 10 MHz.  Inputs are resident in HBM before the timed region.
+
+One step = one correct_pulse_batch call over the whole batch.  The JSON line carries the
+whole-job corrected samples/s, the roofline of the dominant kernel (timed with HIP events on
+its launch stream over the timed steps), the plain per-pulse path for comparison, and the
+float64 oracle timed on the host cores over a bounded sample of the same workload (which also
+checks the GPU result of those pulses against it).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from fractions import Fraction
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import waveforms as wf  # noqa: E402
+
+METRIC = "corrected complex samples/s at ≤1e-5 rel err; p99 pulse latency vs plain path"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3          # published vector fp32 (counts packed FMA)
+FP32_NONPACKED_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 flop x 2.4 GHz, packed fp32 disabled
+BYTES_PER_SAMPLE_PASS = 16        # complex64 read once + written once
+
+
+def alpha_exact(v):
+    c = 299792458
+    return float(Fraction(c + Fraction(float(v))) / Fraction(c - Fraction(float(v))))
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(pulses: int):
+    c = wf.C2
+    n = c["n"]
+    v, e = wf.c2_params(pulses)
+    x = np.empty(pulses * n, np.complex64)
+    for p in range(pulses):
+        x[p * n:(p + 1) * n] = wf.c2_pulse(p)
+    desc = [dict(off_in=p * n, n_in=n, off_out=p * n, n_out=n, fs=c["fs"], alpha=alpha_exact(v[p]), tec=e[p],
+                 carrier=c["carrier"]) for p in range(pulses)]
+    return x, desc
+
+
+def roofline_for(kernel: str, avg_ms: float, samples: int, half_width: int, passes_per_kernel: float):
+    """Algorithmic work of one launch of `kernel` divided by its average duration."""
+    if kernel == "k_sinc_fast" or kernel == "k_sinc_direct":
+        flops = 8.0 * half_width * samples  # 2H taps x (2 FMA = 4 flop) per output sample
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        return {"kernel": kernel, "bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "frac_of_nonpacked_peak": round(achieved / FP32_NONPACKED_TFLOPS, 4),
+                "algorithmic_per_launch": flops, "avg_launch_ms": round(avg_ms, 4), "traffic": None}
+    bytes_ = BYTES_PER_SAMPLE_PASS * samples * passes_per_kernel
+    achieved = bytes_ / (avg_ms * 1e-3) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_per_launch": bytes_,
+            "avg_launch_ms": round(avg_ms, 4), "traffic": None}
+
+
+def cpu_baseline(x, desc, y_gpu, seconds: float):
+    """The float64 oracle on a bounded sample of pulses; returns (baseline dict, max rel err)."""
+    import oracle
+
+    oracle.build()
+    c = wf.C2
+    n = c["n"]
+    errs = []
+    t_total, done = 0.0, 0
+    p = 0
+    while done < len(desc) and (t_total < seconds or done < 2):
+        d = desc[p]
+        xs = x[d["off_in"]:d["off_in"] + n]
+        t0 = time.perf_counter()
+        ref = oracle.correct_pulse(xs, d["fs"], d["alpha"], d["tec"], d["carrier"], half_width=c["half_width"],
+                                   beta=c["beta"])
+        t_total += time.perf_counter() - t0
+        yg = y_gpu[d["off_out"]:d["off_out"] + n]
+        errs.append(float(np.linalg.norm(yg - ref) / np.linalg.norm(ref)))
+        done += 1
+        p = (p + 97) % len(desc)  # spread the sample over the batch
+    return {"value": round(done * n / t_total, 1), "unit": "samples/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"{done} of {len(desc)} pulses x {n} samples (every 97th pulse), "
+                                        f"{t_total:.1f} s"}, max(errs)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pulses", type=int, default=wf.C2["pulses"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path (asked for "
+              f"--gpus {args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2508_04951_amd as rc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    c = wf.C2
+    n = c["n"]
+    P = args.pulses
+    log(f"[bench] generating {P} x {n} band-limited noise pulses")
+    x, desc = make_workload(P)
+    samples = P * n
+    xd = torch.from_numpy(x).to(dev)
+    yd = torch.empty_like(xd)
+    ctx = rc.Context(0)
+    sinc = rc.Sinc(c["half_width"], "kaiser", c["beta"])
+
+    def step():
+        ctx.correct_pulse_batch(xd, yd, desc, sinc)
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_read()  # clear
+    ctx.profile(True)
+    log(f"[bench] timing {args.steps} steps")
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_per_step = t0.elapsed_time(t1) / args.steps
+    ctx.profile(False)
+    kt = ctx.profile_read()
+    kernels = {k: {"avg_ms": round(ms / cnt, 4), "launches_per_step": cnt / args.steps,
+                   "share": round(ms / (ms_per_step * args.steps), 4)}
+               for k, (ms, cnt) in kt.items() if cnt}
+    value = samples / (ms_per_step * 1e-3)
+    log(f"[bench] {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GS/s; kernels {kernels}")
+
+    # dominant kernel roofline
+    dom = max(kt, key=lambda k: kt[k][0])
+    dom_ms, dom_cnt = kt[dom]
+    per_launch_samples = samples * args.steps / dom_cnt
+    roof = roofline_for(dom, dom_ms / dom_cnt, int(per_launch_samples), c["half_width"], 1.0)
+
+    # the plain path: per pulse, correct_doppler then correct_ionosphere, one at a time
+    plain = None
+    if not args.no_plain:
+        log("[bench] plain per-pulse path")
+        lat = []
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in desc]
+        tmp = torch.empty(n, dtype=torch.complex64, device=dev)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for d, (a, b) in zip(desc, ev):
+            a.record()
+            ctx.correct_doppler(xd[d["off_in"]:d["off_in"] + n], d["alpha"], sinc, out=tmp)
+            ctx.correct_ionosphere(tmp, d["fs"], d["carrier"], d["tec"], "correct",
+                                   out=yd[d["off_out"]:d["off_out"] + n])
+            b.record()
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - w0
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        plain = {"samples_per_s": round(samples / plain_s, 1), "ms_per_batch": round(plain_s * 1e3, 3),
+                 "pulse_latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
+                 "pulse_latency_ms_p99": round(float(np.percentile(lat, 99)), 4)}
+        step()  # restore the batch result in yd
+        torch.cuda.synchronize()
+
+    cpu, rel_err = None, None
+    if not args.no_cpu_baseline:
+        log("[bench] oracle CPU baseline")
+        y_host = yd.cpu().numpy()
+        cpu, rel_err = cpu_baseline(x, desc, y_host, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch {P} pulses x {n} complex64 band-limited noise, Kaiser sinc H=64 beta=8, "
+                               f"v_r~U[-8,8] km/s, iono E~U[5,100] TECU at 450 MHz, fs 10 MHz",
+                   "pulses": P, "samples_per_pulse": n, "half_width": c["half_width"], "beta": c["beta"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "rel_err_max_sampled": rel_err,
+        "hbm_frac_of_step": round(BYTES_PER_SAMPLE_PASS * value / (HBM_PEAK_GBS * 1e9), 4),
+        "kernels": kernels,
+        "batch_latency_ms": round(ms_per_step, 4),
+        "plain_path": plain,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * rc.h -- C ABI of the MI355X (gfx950) Doppler and ionospheric correction library
+ * (librc.so).  It implements the correction of sampled arbitrary waveforms of
+ * Vickers, Mack & Osaretin (arXiv 2508.04951):
+ *
+ *   - Doppler dilation, Eq (1)-(2): S(alpha t) with alpha = (1 + v_r/c)/(1 - v_r/c),
+ *     v_r positive when the target approaches, computed by windowed
+ *     Whittaker-Shannon (sinc) resampling, Eq (17), Sec. III-B and App. C;
+ *   - ionospheric dispersion, Eq (3), Eq (15) (distortion) and Eq (16) (correction):
+ *     y = IDFT( DFT(x) * exp(-/+ i 4 pi K2 / (c f_k)) ), K2 = e^2 E / (8 pi^2 m_e eps0).
+ *
+ * Conventions shared by every entry point
+ *   - Sample buffers are DEVICE pointers (HIP global memory) owned by the caller, holding
+ *     interleaved complex64 samples (rc_c64, the layout of torch.complex64).  The library
+ *     never frees or keeps them past the call's stream work.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Compute calls
+ *     only enqueue work and return; results are ready when the stream reaches them.
+ *   - Errors are status codes; no C++ exception crosses the ABI.  RC_ERR_INVALID_ARG is
+ *     returned before any work is enqueued; rc_last_error() gives the reason.  A fault in
+ *     enqueued work surfaces as RC_ERR_DEVICE from a later call or from rc_sync().
+ *   - A context is bound to one HIP device.  Calls on one context are serialised by an
+ *     internal mutex, so several host threads may share it.
+ *   - Time is in input-sample units: output m samples the input at t = alpha * m, and
+ *     x[n] = 0 outside [0, n_in).  The arithmetic is float32 with float64 sample
+ *     positions alpha * m, float64 window coefficients and a float64 dispersive phase.
+ */
+#ifndef RC_H
+#define RC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Interleaved complex64, identical to torch.complex64 / std::complex<float>. */
+typedef struct {
+    float re, im;
+} rc_c64;
+
+typedef enum {
+    RC_OK = 0,
+    RC_ERR_INVALID_ARG = 1,   /* bad pointer, size, parameter or overlap; nothing enqueued */
+    RC_ERR_UNSUPPORTED = 2,   /* a valid request this build cannot serve */
+    RC_ERR_OUT_OF_MEMORY = 3, /* workspace or table allocation failed */
+    RC_ERR_DEVICE = 4,        /* a HIP runtime call or a kernel failed */
+    RC_ERR_BUSY = 5           /* reserved for admission control */
+} rc_status;
+
+/* Sinc taper (rc_sinc.window). */
+enum {
+    RC_WIN_KAISER = 0, /* 2H taps n = floor(t)-H+1 .. floor(t)+H, weight sinc(t-n) K((t-n)/H),
+                          K(x) = I0(beta sqrt(1-x^2)) / I0(beta) */
+    RC_WIN_RECT = 1,   /* the same 2H taps, weight sinc(t-n) */
+    RC_WIN_PAPER = 2   /* 2H+1 taps centred on the nearest input sample, no taper
+                          (the odd N_window of App. C, Fig. 10) */
+};
+
+/* Ionospheric operator direction. */
+enum {
+    RC_CORRECT = 0, /* Eq (16): phase exp(-i 4 pi K2 / (c f)) removes the two-way delay */
+    RC_DISTORT = 1  /* Eq (15): phase exp(+i 4 pi K2 / (c f)) applies it */
+};
+
+/* rc_pulse.flags */
+enum {
+    RC_DO_DOPPLER = 1u, /* resample to S(alpha t) first */
+    RC_DO_IONO = 2u     /* then apply the ionospheric operator to the n_out samples */
+};
+
+typedef struct rc_context_s *rc_context;
+
+/* Resampling kernel.  half_width H >= 1 selects 2H taps (2H+1 for RC_WIN_PAPER);
+ * H = 0 selects the full, unwindowed Whittaker-Shannon sum over every input sample
+ * (Eq 17 on the finite record).  kaiser_beta >= 0 is used by RC_WIN_KAISER only. */
+typedef struct {
+    int32_t half_width;
+    int32_t window;
+    double kaiser_beta;
+} rc_sinc;
+
+/* One pulse of a batch.  Offsets and lengths count complex samples inside the packed
+ * input / output buffers passed to correct_pulse_batch.
+ *   fs_hz          sample rate (Hz), > 0
+ *   alpha          Doppler factor (> 0; use rc_alpha_from_vr); ignored without RC_DO_DOPPLER
+ *   tec_el_per_m2  one-way path TEC E in electrons/m^2 (1 TECU = 1e16); >= 0
+ *   carrier_hz     RF frequency of baseband 0 Hz (f_k = carrier + fs * fftfreq(n_out)[k])
+ *   flags          RC_DO_DOPPLER | RC_DO_IONO; without RC_DO_DOPPLER n_out must equal n_in
+ *   direction      RC_CORRECT or RC_DISTORT */
+typedef struct {
+    int64_t off_in, n_in, off_out, n_out;
+    double fs_hz, alpha, tec_el_per_m2, carrier_hz;
+    uint32_t flags;
+    int32_t direction;
+} rc_pulse;
+
+/* Create a context on HIP device `hip_device` (device tables are built here).
+ * *out receives the handle.  RC_ERR_INVALID_ARG for a NULL out or a bad device. */
+rc_status rc_create(int hip_device, rc_context *out);
+
+/* Synchronise the device, then free every table and workspace of the context. */
+rc_status rc_destroy(rc_context ctx);
+
+/* Static, human-readable name of a status code. */
+const char *rc_status_string(rc_status status);
+
+/* Text of the last error recorded on ctx ("" if none).  Valid until the next call on ctx. */
+const char *rc_last_error(rc_context ctx);
+
+/* Eq (1): alpha = (1 + v_r/c)/(1 - v_r/c) = 1 + 2 v_r / (c - v_r); NaN unless |v_r| < c. */
+double rc_alpha_from_vr(double v_r_mps);
+
+/* Eq (3): K2 / E = e^2 / (8 pi^2 m_e eps0) in m^3 s^-2 (CODATA 2022 constants). */
+double rc_k2_per_tec(void);
+
+/* Block the host until `stream` has drained; report any device error as RC_ERR_DEVICE. */
+rc_status rc_sync(rc_context ctx, void *stream);
+
+/* Doppler resampling, Eq (2) with Eq (17):
+ *   y[m] = sum_n x[n] h(alpha m - n),  m = 0 .. n_out-1,
+ * h the kernel selected by *k.  An output whose position alpha*m is an exact integer is
+ * that input sample (zero past the end).  x: n_in samples, y: n_out samples, both device
+ * pointers that must not overlap.  fs_hz (> 0) documents the time base; the result does
+ * not depend on it.  alpha must be finite and > 0. */
+rc_status correct_doppler(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 *y,
+                          int64_t n_out, double fs_hz, double alpha, const rc_sinc *k,
+                          void *stream);
+
+/* Ionospheric operator, Eq (15) / Eq (16), on one pulse of n samples:
+ *   y = IDFT_n( DFT_n(x) * exp(s i 4 pi K2 / (c f_k)) ),  s = -1 (RC_CORRECT) or +1,
+ *   f_k = carrier_hz + fs_hz * fftfreq(n)[k]; bins with f_k == 0 keep their value.
+ * DFT unnormalised, IDFT scaled by 1/n, both circular over the n given samples.
+ * n must be a power of two (this build); y may equal x (in place) but must not
+ * partially overlap it. */
+rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n,
+                             double fs_hz, double carrier_hz, double tec_el_per_m2,
+                             int32_t direction, void *stream);
+
+/* A batch of pulses with their own alpha, TEC, carrier and lengths, in packed buffers:
+ * pulse i reads x_packed[off_in .. off_in+n_in) and writes y_packed[off_out .. off_out+n_out),
+ * Doppler first, then the ionosphere on the resampled samples (the order matters: the
+ * two operators do not commute).  `pulses` is a HOST array of `count` descriptors, read
+ * during the call only.  x_len / y_len are the buffer lengths in samples; every range must
+ * lie inside its buffer, output ranges must not overlap each other, and the two buffers
+ * must not overlap.  Every pulse uses the kernel *k.  The result of each pulse does not
+ * depend on the other pulses of the batch. */
+rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_len,
+                              rc_c64 *y_packed, int64_t y_len, const rc_pulse *pulses,
+                              int32_t count, const rc_sinc *k, void *stream);
+
+/* Kernel timing for benchmarks.  While enabled, every kernel the context launches is
+ * bracketed by a pair of HIP events recorded on the launch stream.  rc_profile_read waits for
+ * the recorded events, adds their spans to per-kernel totals, and returns (then clears) the
+ * total milliseconds and launch count of one kernel: "k_sinc_fast", "k_sinc_direct",
+ * "k_fft_strided_fwd", "k_fft_rows_iono" or "k_fft_strided_inv".  Unknown names give
+ * RC_ERR_INVALID_ARG.  Timing adds two event records per launch and no synchronisation. */
+rc_status rc_profile_enable(rc_context ctx, int enable);
+rc_status rc_profile_read(rc_context ctx, const char *kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RC_H */

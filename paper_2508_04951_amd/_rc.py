@@ -1,0 +1,269 @@
+"""ctypes binding of librc.so (include/rc.h).
+
+Argument marshalling only: every step of the correction runs in the HIP kernels of the
+library.  torch provides device memory and the stream (``tensor.data_ptr()`` and
+``torch.cuda.current_stream().cuda_stream``, which are HIP objects on ROCm).  There is no
+CPU fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librc.so")
+
+RC_OK, RC_ERR_INVALID_ARG, RC_ERR_UNSUPPORTED, RC_ERR_OUT_OF_MEMORY, RC_ERR_DEVICE, RC_ERR_BUSY = range(6)
+WINDOWS = {"kaiser": 0, "rect": 1, "paper": 2}
+DIRECTIONS = {"correct": 0, "distort": 1}
+DO_DOPPLER, DO_IONO = 1, 2
+
+# exported symbols of include/rc.h
+SYMBOLS = (
+    "rc_create", "rc_destroy", "rc_status_string", "rc_last_error", "rc_alpha_from_vr",
+    "rc_k2_per_tec", "rc_sync", "correct_doppler", "correct_ionosphere", "correct_pulse_batch",
+    "rc_profile_enable", "rc_profile_read",
+)
+KERNELS = ("k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono", "k_fft_strided_inv")
+
+
+class RcSinc(ctypes.Structure):
+    _fields_ = [("half_width", ctypes.c_int32), ("window", ctypes.c_int32), ("kaiser_beta", ctypes.c_double)]
+
+
+class RcPulse(ctypes.Structure):
+    _fields_ = [
+        ("off_in", ctypes.c_int64), ("n_in", ctypes.c_int64), ("off_out", ctypes.c_int64),
+        ("n_out", ctypes.c_int64), ("fs_hz", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("tec_el_per_m2", ctypes.c_double), ("carrier_hz", ctypes.c_double),
+        ("flags", ctypes.c_uint32), ("direction", ctypes.c_int32),
+    ]
+
+
+class RcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load librc.so (built by ``python -m paper_2508_04951_amd.build``)."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2508_04951_amd.build`")
+        lib = ctypes.CDLL(path)
+        c_i32, c_i64, c_d, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+        lib.rc_create.argtypes = [ctypes.c_int, ctypes.POINTER(p)]
+        lib.rc_create.restype = c_i32
+        lib.rc_destroy.argtypes = [p]
+        lib.rc_destroy.restype = c_i32
+        lib.rc_status_string.argtypes = [c_i32]
+        lib.rc_status_string.restype = ctypes.c_char_p
+        lib.rc_last_error.argtypes = [p]
+        lib.rc_last_error.restype = ctypes.c_char_p
+        lib.rc_alpha_from_vr.argtypes = [c_d]
+        lib.rc_alpha_from_vr.restype = c_d
+        lib.rc_k2_per_tec.argtypes = []
+        lib.rc_k2_per_tec.restype = c_d
+        lib.rc_sync.argtypes = [p, p]
+        lib.rc_sync.restype = c_i32
+        lib.correct_doppler.argtypes = [p, p, c_i64, p, c_i64, c_d, c_d, ctypes.POINTER(RcSinc), p]
+        lib.correct_doppler.restype = c_i32
+        lib.correct_ionosphere.argtypes = [p, p, p, c_i64, c_d, c_d, c_d, c_i32, p]
+        lib.correct_ionosphere.restype = c_i32
+        lib.correct_pulse_batch.argtypes = [p, p, c_i64, p, c_i64, ctypes.POINTER(RcPulse), c_i32,
+                                            ctypes.POINTER(RcSinc), p]
+        lib.correct_pulse_batch.restype = c_i32
+        lib.rc_profile_enable.argtypes = [p, ctypes.c_int]
+        lib.rc_profile_enable.restype = c_i32
+        lib.rc_profile_read.argtypes = [p, ctypes.c_char_p, ctypes.POINTER(c_d), ctypes.POINTER(c_i64)]
+        lib.rc_profile_read.restype = c_i32
+        _lib = lib
+        return lib
+
+
+def alpha_from_vr(v_r: float) -> float:
+    """Eq (1): alpha = (1 + v_r/c)/(1 - v_r/c), v_r positive when approaching (librc)."""
+    return float(load_library().rc_alpha_from_vr(float(v_r)))
+
+
+def k2_per_tec() -> float:
+    """Eq (3): K2/E = e^2/(8 pi^2 m_e eps0) in m^3 s^-2 (librc)."""
+    return float(load_library().rc_k2_per_tec())
+
+
+@dataclass
+class Sinc:
+    """Resampling kernel: half_width H (0 = full sum), window name, Kaiser beta."""
+    half_width: int = 64
+    window: str = "kaiser"
+    beta: float = 8.0
+
+    def c(self) -> RcSinc:
+        if self.window not in WINDOWS:
+            raise ValueError(f"unknown window {self.window!r}")
+        return RcSinc(int(self.half_width), WINDOWS[self.window], float(self.beta))
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _check_samples(t, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.complex64:
+        raise TypeError(f"{name} must be complex64, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """An rc_context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load_library()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        st = self._lib.rc_create(self.device, ctypes.byref(h))
+        if st != RC_OK:
+            raise RcError(st, f"rc_create({device}) failed: {self._lib.rc_status_string(st).decode()}")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.rc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _raise(self, st: int, what: str):
+        msg = self._lib.rc_last_error(self._h).decode()
+        name = self._lib.rc_status_string(st).decode()
+        if st == RC_ERR_INVALID_ARG:
+            raise ValueError(f"{what}: {name}: {msg}")
+        raise RcError(st, f"{what}: {name}: {msg}")
+
+    def _stream(self, stream=None) -> int:
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return int(s.cuda_stream)
+
+    def sync(self, stream=None):
+        st = self._lib.rc_sync(self._h, self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "rc_sync")
+
+    def profile(self, enable: bool = True):
+        """Bracket every kernel launch with HIP events on its stream (for benchmarks)."""
+        st = self._lib.rc_profile_enable(self._h, int(bool(enable)))
+        if st != RC_OK:
+            self._raise(st, "rc_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{kernel: (total_ms, launches)} since the last read (waits for the recorded events)."""
+        out = {}
+        for name in KERNELS:
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            st = self._lib.rc_profile_read(self._h, name.encode(), ctypes.byref(ms), ctypes.byref(n))
+            if st != RC_OK:
+                self._raise(st, "rc_profile_read")
+            out[name] = (ms.value, n.value)
+        return out
+
+    def correct_doppler(self, x, alpha: float, sinc: Sinc | None = None, n_out: int | None = None,
+                        fs: float = 1.0, out=None, stream=None):
+        """y[m] = sum_n x[n] h(alpha m - n) (Eq 2 / Eq 17) for m < n_out."""
+        torch = _torch()
+        _check_samples(x, "x")
+        n_out = x.numel() if n_out is None else int(n_out)
+        if out is None:
+            out = torch.empty(n_out, dtype=torch.complex64, device=x.device)
+        _check_samples(out, "out")
+        if out.numel() < n_out:
+            raise ValueError("out is shorter than n_out")
+        k = (sinc or Sinc()).c()
+        st = self._lib.correct_doppler(self._h, x.data_ptr(), x.numel(), out.data_ptr(), n_out, float(fs),
+                                       float(alpha), ctypes.byref(k), self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "correct_doppler")
+        return out
+
+    def correct_ionosphere(self, x, fs: float, carrier: float, tec: float, direction: str = "correct",
+                           out=None, stream=None):
+        """y = IDFT(DFT(x) exp(-/+ i 4 pi K2 / (c f_k))) (Eq 16 / Eq 15).  out may be x."""
+        torch = _torch()
+        _check_samples(x, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        _check_samples(out, "out")
+        if out.numel() != x.numel():
+            raise ValueError("out must have as many samples as x")
+        if direction not in DIRECTIONS:
+            raise ValueError(f"direction must be one of {list(DIRECTIONS)}")
+        st = self._lib.correct_ionosphere(self._h, x.data_ptr(), out.data_ptr(), x.numel(), float(fs),
+                                          float(carrier), float(tec), DIRECTIONS[direction],
+                                          self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "correct_ionosphere")
+        return out
+
+    def correct_pulse_batch(self, x_packed, y_packed, pulses, sinc: Sinc | None = None, stream=None):
+        """Per-pulse Doppler then ionosphere over packed buffers; `pulses` is a sequence of
+        dicts with keys off_in, n_in, off_out, n_out, fs, alpha, tec, carrier and optional
+        flags (default Doppler|iono) and direction ("correct")."""
+        _check_samples(x_packed, "x_packed")
+        _check_samples(y_packed, "y_packed")
+        arr = pulse_array(pulses)
+        k = (sinc or Sinc()).c()
+        st = self._lib.correct_pulse_batch(self._h, x_packed.data_ptr(), x_packed.numel(), y_packed.data_ptr(),
+                                           y_packed.numel(), arr, len(arr), ctypes.byref(k),
+                                           self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "correct_pulse_batch")
+        return y_packed
+
+
+def pulse_array(pulses) -> ctypes.Array:
+    """Pack pulse dicts into a contiguous rc_pulse array."""
+    arr = (RcPulse * len(pulses))()
+    for i, p in enumerate(pulses):
+        d = p.get("direction", "correct")
+        arr[i] = RcPulse(int(p["off_in"]), int(p["n_in"]), int(p["off_out"]), int(p["n_out"]),
+                         float(p["fs"]), float(p.get("alpha", 1.0)), float(p.get("tec", 0.0)),
+                         float(p.get("carrier", 0.0)), int(p.get("flags", DO_DOPPLER | DO_IONO)),
+                         DIRECTIONS[d] if isinstance(d, str) else int(d))
+    return arr
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    """Process-wide default context for a device."""
+    ctx = _contexts.get(device)
+    if ctx is None:
+        ctx = _contexts[device] = Context(device)
+    return ctx

@@ -1,0 +1,515 @@
+// fft.hip -- ionospheric operator of Eq (15)/(16) for gfx950:
+//   y = IDFT( DFT(x) * exp(s i 4 pi K2 / (c f_k)) ),  f_k = carrier + fs * fftfreq(n)[k].
+//
+// An n-point transform is split into levels L_0 x ... x L_{d-1} (row-major, last level
+// contiguous, <= 4096 points; strided levels <= 256 points):
+//   forward strided passes (i = 0 .. d-2): length-L_i DFT along level i, then the twiddle
+//     exp(-2 pi i k_i n' / nsub_i) with n' the flat position inside the lower levels;
+//   one contiguous pass: forward DFT of each row, the dispersive phase of its bins (float64
+//     argument reduced modulo 2 pi, float32 sincos), inverse DFT;
+//   inverse strided passes (i = d-2 .. 0): conjugate twiddle, inverse DFT, 1/n in the last.
+// The frequency of a bin never leaves the digit-reversed order of the levels, so no
+// reordering pass exists.  Every pass loads a 4096-sample tile into LDS with coalesced
+// accesses, runs Stockham radix-16/8/4/2 stages (twiddles from a float64-built table) and
+// writes the tile back to the same place: every pass after the first runs in place on y.
+#include <cmath>
+#include <vector>
+
+#include "rc_internal.h"
+
+namespace rc {
+
+namespace {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// z * (S i), S = -1 or +1
+template <int S> __device__ __forceinline__ float2 mul_si(float2 z)
+{
+    return S < 0 ? make_float2(z.y, -z.x) : make_float2(-z.y, z.x);
+}
+
+template <int S> __device__ __forceinline__ void dft2(float2 *v)
+{
+    const float2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+
+template <int S> __device__ __forceinline__ void dft4v(float2 &v0, float2 &v1, float2 &v2, float2 &v3)
+{
+    const float2 t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = mul_si<S>(csub(v1, v3));
+    v0 = cadd(t0, t2);
+    v2 = csub(t0, t2);
+    v1 = cadd(t1, t3);
+    v3 = csub(t1, t3);
+}
+
+template <int S> __device__ __forceinline__ void dft4(float2 *v) { dft4v<S>(v[0], v[1], v[2], v[3]); }
+
+template <int S> __device__ __forceinline__ void dft8(float2 *v)
+{
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4v<S>(e0, e1, e2, e3);
+    dft4v<S>(o0, o1, o2, o3);
+    const float r = 0.70710678118654752f;
+    o1 = cmul(o1, make_float2(r, S * r));   // W8^1
+    o2 = mul_si<S>(o2);                      // W8^2
+    o3 = cmul(o3, make_float2(-r, S * r));  // W8^3
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+}
+
+template <int S> __device__ __forceinline__ void dft16(float2 *v)
+{
+    // n = 4 n1 + n2, k = k1 + 4 k2:  X[k] = sum_n2 W16^(n2 k1) W4^(n2 k2) sum_n1 x[n] W4^(n1 k1)
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+        dft4v<S>(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);  // v[n2 + 4 k1]
+    const float c1 = 0.92387953251128674f, s1 = 0.38268343236508977f, c2 = 0.70710678118654752f;
+    v[5] = cmul(v[5], make_float2(c1, S * s1));     // W^1
+    v[9] = cmul(v[9], make_float2(c2, S * c2));     // W^2
+    v[13] = cmul(v[13], make_float2(s1, S * c1));   // W^3
+    v[6] = cmul(v[6], make_float2(c2, S * c2));     // W^2
+    v[10] = mul_si<S>(v[10]);                       // W^4
+    v[14] = cmul(v[14], make_float2(-c2, S * c2));  // W^6
+    v[7] = cmul(v[7], make_float2(s1, S * c1));     // W^3
+    v[11] = cmul(v[11], make_float2(-c2, S * c2));  // W^6
+    v[15] = cmul(v[15], make_float2(-c1, -S * s1)); // W^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+        dft4v<S>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);  // v[4 k1 + k2] = X[k1 + 4 k2]
+    float2 t;
+#define RC_SWAP(a, b) (t = v[a], v[a] = v[b], v[b] = t)
+    RC_SWAP(1, 4); RC_SWAP(2, 8); RC_SWAP(3, 12); RC_SWAP(6, 9); RC_SWAP(7, 13); RC_SWAP(11, 14);
+#undef RC_SWAP
+}
+
+template <int R, int S> __device__ __forceinline__ void dftR(float2 *v)
+{
+    if constexpr (R == 2) dft2<S>(v);
+    else if constexpr (R == 4) dft4<S>(v);
+    else if constexpr (R == 8) dft8<S>(v);
+    else dft16<S>(v);
+}
+
+// LDS layout of a 4096-sample tile holding C lines of length L: element (c, l) at
+// c*L + l (rows, "lc") or l*C + c (columns), with one pad slot per 16 samples.
+__device__ __forceinline__ int tidx(int c, int l, int log2L, int log2C, bool lc)
+{
+    const int a = lc ? ((c << log2L) + l) : ((l << log2C) + c);
+    return a + (a >> 4);
+}
+constexpr int kLdsSlots = kFftTile + kFftTile / 16;
+
+// One Stockham radix-R stage over every line of the tile (Ns = product of earlier radices).
+template <int R, int S>
+__device__ __forceinline__ void stage(float2 *lds, int log2L, int log2C, bool lc, int Ns,
+                                      const float2 *__restrict__ tw, int tid)
+{
+    constexpr int PER = 16 / R;
+    const int log2BL = log2L - (R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4);
+    const int BL = 1 << log2BL;  // butterflies per line
+    float2 v[PER][R];
+    int cc[PER], jj[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int b = tid + p * kFftThreads;
+        int c, j;
+        if (lc) {
+            c = b >> log2BL;
+            j = b & (BL - 1);
+        } else {
+            c = b & ((1 << log2C) - 1);
+            j = b >> log2C;
+        }
+        cc[p] = c;
+        jj[p] = j;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[p][r] = lds[tidx(c, j + r * BL, log2L, log2C, lc)];
+        if (Ns > 1) {
+            const int k = j & (Ns - 1);
+            const int step = kFftTile / (Ns * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[(r * k * step) & (kFftTile - 1)];
+                if (S > 0)
+                    w.y = -w.y;
+                v[p][r] = cmul(v[p][r], w);
+            }
+        }
+        dftR<R, S>(v[p]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int k = jj[p] & (Ns - 1);
+        const int base = (jj[p] - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            lds[tidx(cc[p], base + r * Ns, log2L, log2C, lc)] = v[p][r];
+    }
+    __syncthreads();
+}
+
+// Full length-L DFT (sign S) of every line of the tile; natural order in and out.
+template <int S>
+__device__ void fft_tile(float2 *lds, int log2L, int log2C, bool lc, const float2 *__restrict__ tw,
+                         int tid)
+{
+    int Ns = 1;
+    const int rem = log2L & 3;
+    if (rem == 1) {
+        stage<2, S>(lds, log2L, log2C, lc, Ns, tw, tid);
+        Ns = 2;
+    } else if (rem == 2) {
+        stage<4, S>(lds, log2L, log2C, lc, Ns, tw, tid);
+        Ns = 4;
+    } else if (rem == 3) {
+        stage<8, S>(lds, log2L, log2C, lc, Ns, tw, tid);
+        Ns = 8;
+    }
+    for (int s = 0; s < (log2L >> 2); ++s) {
+        stage<16, S>(lds, log2L, log2C, lc, Ns, tw, tid);
+        Ns <<= 4;
+    }
+}
+
+// exp(-/+ 2 pi i q / nsub) from the split tables (q = qh * 4096 + ql).
+__device__ __forceinline__ float2 twiddle(const float2 *__restrict__ lo, const float2 *__restrict__ hi,
+                                          int64_t q, bool conj)
+{
+    float2 w = cmul(lo[q & (kFftTile - 1)], hi[q >> 12]);
+    if (conj)
+        w.y = -w.y;
+    return w;
+}
+
+struct StridedArgs {
+    const IonoJob *jobs;
+    IonoJob inl;
+    int njobs;
+    int log2L, log2C;
+    int64_t inner;          // samples below this level (line stride)
+    int64_t outer;          // number of blocks above this level
+    int64_t col_blocks;     // inner / C
+    const float2 *tw4096;
+    const float2 *tw_lo, *tw_hi;
+    int64_t nsub;           // L * inner
+    bool from_x;            // first pass reads job.x
+    float scale;            // applied after an inverse pass (1/n in the last one)
+};
+
+// Strided level: lines of length L along stride `inner`; the tile holds C adjacent lines.
+template <int S>
+__global__ void __launch_bounds__(kFftThreads) k_fft_strided(StridedArgs a)
+{
+    __shared__ float2 lds[kLdsSlots];
+    const int tid = threadIdx.x;
+    const int64_t per_pulse = a.outer * a.col_blocks;
+    const int64_t blk = blockIdx.x;
+    const int p = (int)(blk / per_pulse);
+    if (p >= a.njobs)
+        return;
+    const int64_t rem = blk - (int64_t)p * per_pulse;
+    const int64_t o = rem / a.col_blocks;
+    const int64_t cb = rem - o * a.col_blocks;
+    const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
+    const int L = 1 << a.log2L, C = 1 << a.log2C;
+    const int64_t base = o * ((int64_t)L * a.inner) + cb * C;
+    const float2 *src = a.from_x ? jb.x : jb.y;
+    for (int e = tid; e < kFftTile; e += kFftThreads) {
+        const int c = e & (C - 1), l = e >> a.log2C;
+        float2 v = src[base + (int64_t)l * a.inner + c];
+        if (S > 0) {  // inverse: conjugate twiddle before the DFT along the level
+            const int64_t q = (int64_t)l * (cb * C + c);  // < L * inner = nsub
+            v = cmul(v, twiddle(a.tw_lo, a.tw_hi, q, true));
+        }
+        lds[tidx(c, l, a.log2L, a.log2C, false)] = v;
+    }
+    __syncthreads();
+    fft_tile<S>(lds, a.log2L, a.log2C, false, a.tw4096, tid);
+    for (int e = tid; e < kFftTile; e += kFftThreads) {
+        const int c = e & (C - 1), l = e >> a.log2C;
+        float2 v = lds[tidx(c, l, a.log2L, a.log2C, false)];
+        if (S < 0) {  // forward: twiddle after the DFT, k = l, n' = column position
+            const int64_t q = (int64_t)l * (cb * C + c);
+            v = cmul(v, twiddle(a.tw_lo, a.tw_hi, q, false));
+        } else if (a.scale != 1.0f) {
+            v.x *= a.scale;
+            v.y *= a.scale;
+        }
+        jb.y[base + (int64_t)l * a.inner + c] = v;
+    }
+}
+
+struct RowArgs {
+    const IonoJob *jobs;
+    IonoJob inl;
+    int njobs;
+    int log2L, log2C;
+    int64_t rows_per_pulse;   // n / L
+    int64_t n;
+    int levels;
+    int len[kFftMaxLevels];   // level lengths (the last is L)
+    const float2 *tw4096;
+    bool from_x;
+    float scale;              // 1/n when this is the only pass, else 1
+};
+
+__device__ __forceinline__ float2 iono_phase(const IonoJob &jb, int64_t k, int64_t n)
+{
+    const int64_t kk = (k < (n + 1) / 2) ? k : k - n;
+    const double f = jb.carrier + jb.fs * (double)kk / (double)n;
+    if (f == 0.0 || jb.phase_num == 0.0)
+        return make_float2(1.f, 0.f);
+    const double ph = jb.phase_num / f;
+    // reduce modulo 2 pi in float64 (|ph| is ~1e3..1e5 rad), then float32 sincos
+    const double red = ph - 6.283185307179586477 * rint(ph * 0.15915494309189533577);
+    float s, c;
+    sincosf((float)red, &s, &c);
+    return make_float2(c, s);
+}
+
+// Contiguous level: forward DFT of each row, dispersive phase per bin, inverse DFT.
+__global__ void __launch_bounds__(kFftThreads) k_fft_rows_iono(RowArgs a)
+{
+    __shared__ float2 lds[kLdsSlots];
+    const int tid = threadIdx.x;
+    const int L = 1 << a.log2L, C = 1 << a.log2C;
+    const int64_t g0 = (int64_t)blockIdx.x * C;  // first global row of the tile
+    const int64_t total_rows = (int64_t)a.njobs * a.rows_per_pulse;
+    for (int e = tid; e < kFftTile; e += kFftThreads) {
+        const int c = e >> a.log2L, l = e & (L - 1);
+        const int64_t g = g0 + c;
+        float2 v = make_float2(0.f, 0.f);
+        if (g < total_rows) {
+            const int p = (int)(g / a.rows_per_pulse);
+            const int64_t r = g - (int64_t)p * a.rows_per_pulse;
+            const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
+            v = (a.from_x ? jb.x : jb.y)[r * L + l];
+        }
+        lds[tidx(c, l, a.log2L, a.log2C, true)] = v;
+    }
+    __syncthreads();
+    fft_tile<-1>(lds, a.log2L, a.log2C, true, a.tw4096, tid);
+    // Bin of (row r, position l): k = kout(r) + (n / L) * l, kout = digit-reversed row index.
+    // One level: rows are whole pulses (kout = 0).  Several levels: L = 4096, one row per tile.
+    int64_t kout = 0, mult = 1;
+    if (a.levels > 1 && g0 < total_rows) {
+        int64_t r = g0 % a.rows_per_pulse;
+        int64_t digits[kFftMaxLevels];
+        for (int i = a.levels - 2; i >= 0; --i) {
+            digits[i] = r % a.len[i];
+            r /= a.len[i];
+        }
+        for (int i = 0; i < a.levels - 1; ++i) {
+            kout += digits[i] * mult;
+            mult *= a.len[i];
+        }
+    }
+    for (int e = tid; e < kFftTile; e += kFftThreads) {
+        const int c = e >> a.log2L, l = e & (L - 1);
+        const int64_t g = g0 + c;
+        if (g >= total_rows)
+            continue;
+        const int p = (int)(g / a.rows_per_pulse);
+        const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
+        const int idx = tidx(c, l, a.log2L, a.log2C, true);
+        lds[idx] = cmul(lds[idx], iono_phase(jb, kout + mult * l, a.n));
+    }
+    __syncthreads();
+    fft_tile<+1>(lds, a.log2L, a.log2C, true, a.tw4096, tid);
+    for (int e = tid; e < kFftTile; e += kFftThreads) {
+        const int c = e >> a.log2L, l = e & (L - 1);
+        const int64_t g = g0 + c;
+        if (g >= total_rows)
+            continue;
+        const int p = (int)(g / a.rows_per_pulse);
+        const int64_t r = g - (int64_t)p * a.rows_per_pulse;
+        const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
+        float2 v = lds[tidx(c, l, a.log2L, a.log2C, true)];
+        v.x *= a.scale;
+        v.y *= a.scale;
+        jb.y[r * L + l] = v;
+    }
+}
+
+int ilog2(int64_t v)
+{
+    int l = 0;
+    while ((int64_t(1) << l) < v)
+        ++l;
+    return l;
+}
+
+hipError_t upload_table(const std::vector<float2> &h, float2 **dev, std::vector<void *> &allocs)
+{
+    hipError_t e = hipMalloc(dev, h.size() * sizeof(float2));
+    if (e != hipSuccess)
+        return e;
+    allocs.push_back(*dev);
+    return hipMemcpy(*dev, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice);
+}
+
+// exp(-2 pi i q / m) for q = 0 .. count-1 with q*step exact, rounded once to float32.
+std::vector<float2> twiddle_table(int64_t count, int64_t step, int64_t m)
+{
+    std::vector<float2> t((size_t)count);
+    for (int64_t q = 0; q < count; ++q) {
+        const int64_t r = (q * step) % m;
+        const double a = -2.0 * kPi * (double)r / (double)m;
+        t[(size_t)q] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    return t;
+}
+
+}  // namespace
+
+hipError_t make_base_twiddles(float2 **dev)
+{
+    std::vector<void *> unused;
+    return upload_table(twiddle_table(kFftTile, 1, kFftTile), dev, unused);
+}
+
+hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs)
+{
+    plan = FftPlan{};
+    plan.n = n;
+    const int p = ilog2(n);
+    if ((int64_t(1) << p) != n)
+        return hipErrorInvalidValue;
+    if (p <= 12) {
+        plan.levels = 1;
+        plan.len[0] = (int)n;
+    } else {
+        int rest = p - 12;
+        int d = 0;
+        while (rest > 0) {
+            const int s = rest < 8 ? rest : 8;
+            plan.len[d++] = 1 << s;
+            rest -= s;
+        }
+        if (d + 1 > kFftMaxLevels)
+            return hipErrorInvalidValue;
+        plan.len[d++] = kFftTile;
+        plan.levels = d;
+    }
+    for (int i = 0; i < plan.levels; ++i)
+        plan.log2len[i] = ilog2(plan.len[i]);
+    int64_t inner = n;
+    for (int i = 0; i + 1 < plan.levels; ++i) {
+        inner /= plan.len[i];
+        const int64_t nsub = (int64_t)plan.len[i] * inner;
+        hipError_t e = upload_table(twiddle_table(kFftTile, 1, nsub), &plan.tw_lo[i], allocs);
+        if (e != hipSuccess)
+            return e;
+        const int64_t nhi = (nsub + kFftTile - 1) / kFftTile;
+        e = upload_table(twiddle_table(nhi, kFftTile, nsub), &plan.tw_hi[i], allocs);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
+                       const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof)
+{
+    if (njobs <= 0)
+        return hipSuccess;
+    const IonoJob inl = job_inline ? *job_inline : IonoJob{};
+    const int d = plan.levels;
+    const float inv_n = (float)(1.0 / (double)plan.n);
+    int64_t inner[kFftMaxLevels], outer[kFftMaxLevels];
+    {
+        int64_t below = plan.n, above = 1;
+        for (int i = 0; i < d; ++i) {
+            below /= plan.len[i];
+            inner[i] = below;
+            outer[i] = above;
+            above *= plan.len[i];
+        }
+    }
+    auto strided = [&](int i, bool inverse) -> hipError_t {
+        StridedArgs a{};
+        a.jobs = jobs_dev;
+        a.inl = inl;
+        a.njobs = njobs;
+        a.log2L = plan.log2len[i];
+        a.log2C = ilog2(kFftTile) - plan.log2len[i];
+        a.inner = inner[i];
+        a.outer = outer[i];
+        a.col_blocks = inner[i] >> a.log2C;
+        a.tw4096 = tw4096;
+        a.tw_lo = plan.tw_lo[i];
+        a.tw_hi = plan.tw_hi[i];
+        a.nsub = (int64_t)plan.len[i] * inner[i];
+        a.from_x = (!inverse && i == 0);
+        a.scale = (inverse && i == 0) ? inv_n : 1.0f;
+        const int64_t blocks = (int64_t)njobs * a.outer * a.col_blocks;
+        if (blocks > 0x7fffffff)
+            return hipErrorInvalidValue;
+        if (prof)
+            prof->begin(inverse ? kKFftStridedInv : kKFftStridedFwd, s);
+        if (inverse)
+            hipLaunchKernelGGL(k_fft_strided<+1>, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_fft_strided<-1>, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (prof)
+            prof->end(s);
+        return e;
+    };
+    for (int i = 0; i + 1 < d; ++i) {
+        hipError_t e = strided(i, false);
+        if (e != hipSuccess)
+            return e;
+    }
+    {
+        RowArgs a{};
+        a.jobs = jobs_dev;
+        a.inl = inl;
+        a.njobs = njobs;
+        a.log2L = plan.log2len[d - 1];
+        a.log2C = ilog2(kFftTile) - a.log2L;
+        a.rows_per_pulse = plan.n >> a.log2L;
+        a.n = plan.n;
+        a.levels = d;
+        for (int i = 0; i < kFftMaxLevels; ++i)
+            a.len[i] = plan.len[i];
+        a.tw4096 = tw4096;
+        a.from_x = (d == 1);
+        a.scale = (d == 1) ? inv_n : 1.0f;
+        const int64_t rows = (int64_t)njobs * a.rows_per_pulse;
+        const int64_t blocks = (rows + (1 << a.log2C) - 1) >> a.log2C;
+        if (blocks > 0x7fffffff)
+            return hipErrorInvalidValue;
+        if (prof)
+            prof->begin(kKFftRowsIono, s);
+        hipLaunchKernelGGL(k_fft_rows_iono, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (prof)
+            prof->end(s);
+        if (e != hipSuccess)
+            return e;
+    }
+    for (int i = d - 2; i >= 0; --i) {
+        hipError_t e = strided(i, true);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace rc

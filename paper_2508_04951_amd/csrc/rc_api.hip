@@ -1,0 +1,572 @@
+// rc_api.hip -- the extern "C" entry points of librc.so declared in include/rc.h:
+// argument validation, the per-device context, and dispatch to the HIP kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rc_internal.h"
+
+namespace {
+
+using rc::FftPlan;
+using rc::IonoJob;
+using rc::SincJob;
+
+rc_status fail(rc_context ctx, rc_status st, const std::string &why)
+{
+    if (ctx)
+        ctx->last_error = why;
+    return st;
+}
+
+rc_status device_fail(rc_context ctx, hipError_t e, const char *where)
+{
+    return fail(ctx, RC_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool overlaps(const void *a, int64_t abytes, const void *b, int64_t bbytes)
+{
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+rc_status check_sinc(rc_context ctx, const rc_sinc *k)
+{
+    if (!k)
+        return fail(ctx, RC_ERR_INVALID_ARG, "sinc kernel descriptor is NULL");
+    if (k->half_width < 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "half_width must be >= 0");
+    if (k->window != RC_WIN_KAISER && k->window != RC_WIN_RECT && k->window != RC_WIN_PAPER)
+        return fail(ctx, RC_ERR_INVALID_ARG, "unknown window");
+    if (k->window == RC_WIN_KAISER && !(k->kaiser_beta >= 0.0 && k->kaiser_beta <= 40.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "kaiser_beta must be in [0, 40]");
+    return RC_OK;
+}
+
+// Current device of the calling thread set to the context's device for the call.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            prev = -1;
+        if (prev != dev)
+            (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
+            (void)hipSetDevice(prev);
+    }
+};
+
+// Stage `bytes` of descriptors to the device on `s`.  The staging buffers are reused by the
+// next batch call only after the work that reads them has completed (event `desc_done`).
+rc_status stage_descriptors(rc_context ctx, const void *host, size_t bytes, hipStream_t s,
+                            const void **dev_out)
+{
+    hipError_t e;
+    if (ctx->desc_pending) {
+        e = hipEventSynchronize(ctx->desc_done);
+        if (e != hipSuccess)
+            return device_fail(ctx, e, "waiting for the previous batch");
+        ctx->desc_pending = false;
+    }
+    if (bytes > ctx->desc_cap) {
+        size_t cap = 1 << 16;
+        while (cap < bytes)
+            cap <<= 1;
+        if (ctx->desc_host)
+            (void)hipHostFree(ctx->desc_host);
+        if (ctx->desc_dev)
+            (void)hipFree(ctx->desc_dev);
+        ctx->desc_host = nullptr;
+        ctx->desc_dev = nullptr;
+        ctx->desc_cap = 0;
+        if (hipHostMalloc(&ctx->desc_host, cap, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&ctx->desc_dev, cap) != hipSuccess)
+            return fail(ctx, RC_ERR_OUT_OF_MEMORY, "descriptor staging allocation failed");
+        ctx->desc_cap = cap;
+    }
+    std::memcpy(ctx->desc_host, host, bytes);
+    e = hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "descriptor upload");
+    *dev_out = ctx->desc_dev;
+    return RC_OK;
+}
+
+rc_status mark_descriptors_used(rc_context ctx, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(ctx->desc_done, s);
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "descriptor event");
+    ctx->desc_pending = true;
+    return RC_OK;
+}
+
+rc_status get_plan(rc_context ctx, int64_t n, const FftPlan **out)
+{
+    auto it = ctx->plans.find(n);
+    if (it == ctx->plans.end()) {
+        FftPlan plan;
+        hipError_t e = rc::build_fft_plan(n, plan, ctx->allocs);
+        if (e == hipErrorInvalidValue)
+            return fail(ctx, RC_ERR_UNSUPPORTED, "transform length " + std::to_string(n) + " not supported");
+        if (e != hipSuccess)
+            return device_fail(ctx, e, "building FFT tables");
+        it = ctx->plans.emplace(n, plan).first;
+    }
+    *out = &it->second;
+    return RC_OK;
+}
+
+double phase_numerator(double tec, int32_t direction)
+{
+    const double k2 = rc_k2_per_tec() * tec;
+    const double s = (direction == RC_DISTORT) ? 1.0 : -1.0;
+    return s * 4.0 * rc::kPi * k2 / rc::kC;
+}
+
+rc::Profiler *prof_of(rc_context ctx) { return ctx->prof.on ? &ctx->prof : nullptr; }
+
+int64_t taps_per_output(const rc_sinc &k, int64_t n_in)
+{
+    if (k.half_width == 0)
+        return n_in;
+    return k.window == RC_WIN_PAPER ? 2 * (int64_t)k.half_width + 1 : 2 * (int64_t)k.half_width;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rc_status_string(rc_status status)
+{
+    switch (status) {
+    case RC_OK: return "RC_OK";
+    case RC_ERR_INVALID_ARG: return "RC_ERR_INVALID_ARG";
+    case RC_ERR_UNSUPPORTED: return "RC_ERR_UNSUPPORTED";
+    case RC_ERR_OUT_OF_MEMORY: return "RC_ERR_OUT_OF_MEMORY";
+    case RC_ERR_DEVICE: return "RC_ERR_DEVICE";
+    case RC_ERR_BUSY: return "RC_ERR_BUSY";
+    }
+    return "RC_ERR_UNKNOWN";
+}
+
+double rc_alpha_from_vr(double v_r_mps)
+{
+    if (!(std::fabs(v_r_mps) < rc::kC))
+        return NAN;
+    // (1 + v/c)/(1 - v/c).  For |v| < c/4 it is evaluated as 1 + 2v/(c - v), which keeps
+    // alpha - 1 at full relative precision; closer to c the plain quotient avoids the
+    // cancellation of 1 + 2v/(c - v).
+    if (std::fabs(v_r_mps) < 0.25 * rc::kC)
+        return 1.0 + 2.0 * v_r_mps / (rc::kC - v_r_mps);
+    return (rc::kC + v_r_mps) / (rc::kC - v_r_mps);
+}
+
+double rc_k2_per_tec(void)
+{
+    return rc::kECharge * rc::kECharge / (8.0 * rc::kPi * rc::kPi * rc::kMe * rc::kEps0);
+}
+
+rc_status rc_create(int hip_device, rc_context *out)
+{
+    if (!out)
+        return RC_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count)
+        return RC_ERR_INVALID_ARG;
+    rc_context ctx = new (std::nothrow) rc_context_s();
+    if (!ctx)
+        return RC_ERR_OUT_OF_MEMORY;
+    ctx->device = hip_device;
+    DeviceGuard g(hip_device);
+    hipError_t e = rc::make_base_twiddles(&ctx->tw4096);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&ctx->desc_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (ctx->tw4096)
+            (void)hipFree(ctx->tw4096);
+        delete ctx;
+        return RC_ERR_DEVICE;
+    }
+    *out = ctx;
+    return RC_OK;
+}
+
+rc_status rc_destroy(rc_context ctx)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    rc_status st = RC_OK;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        DeviceGuard g(ctx->device);
+        if (hipDeviceSynchronize() != hipSuccess)
+            st = RC_ERR_DEVICE;
+        for (void *p : ctx->allocs)
+            (void)hipFree(p);
+        if (ctx->tw4096)
+            (void)hipFree(ctx->tw4096);
+        if (ctx->desc_dev)
+            (void)hipFree(ctx->desc_dev);
+        if (ctx->desc_host)
+            (void)hipHostFree(ctx->desc_host);
+        if (ctx->desc_done)
+            (void)hipEventDestroy(ctx->desc_done);
+        ctx->prof.release();
+    }
+    delete ctx;
+    return st;
+}
+
+const char *rc_last_error(rc_context ctx)
+{
+    return ctx ? ctx->last_error.c_str() : "NULL context";
+}
+
+rc_status rc_sync(rc_context ctx, void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "rc_sync");
+    return RC_OK;
+}
+
+rc_status correct_doppler(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 *y, int64_t n_out,
+                          double fs_hz, double alpha, const rc_sinc *k, void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    rc_status st = check_sinc(ctx, k);
+    if (st != RC_OK)
+        return st;
+    if (!x || !y)
+        return fail(ctx, RC_ERR_INVALID_ARG, "NULL sample pointer");
+    if (n_in <= 0 || n_out <= 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "n_in and n_out must be > 0");
+    if (!(std::isfinite(fs_hz) && fs_hz > 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "fs_hz must be finite and > 0");
+    if (!(std::isfinite(alpha) && alpha > 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "alpha must be finite and > 0");
+    if (overlaps(x, n_in * 8, y, n_out * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "x and y overlap");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const SincJob job{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y), n_in, n_out, alpha};
+    const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
+    hipError_t e;
+    if (rc::sinc_fast_eligible(alpha, *k))
+        e = rc::launch_sinc_fast(nullptr, &job, 1, n_out, k->half_width, kp, s, prof_of(ctx));
+    else
+        e = rc::launch_sinc_direct(nullptr, &job, 1, n_out, *k, kp, taps_per_output(*k, n_in), s, prof_of(ctx));
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "correct_doppler launch");
+    return RC_OK;
+}
+
+rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n, double fs_hz,
+                             double carrier_hz, double tec_el_per_m2, int32_t direction, void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    if (!x || !y)
+        return fail(ctx, RC_ERR_INVALID_ARG, "NULL sample pointer");
+    if (n <= 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "n must be > 0");
+    if (!(std::isfinite(fs_hz) && fs_hz > 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "fs_hz must be finite and > 0");
+    if (!std::isfinite(carrier_hz))
+        return fail(ctx, RC_ERR_INVALID_ARG, "carrier_hz must be finite");
+    if (!(std::isfinite(tec_el_per_m2) && tec_el_per_m2 >= 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "tec must be finite and >= 0");
+    if (direction != RC_CORRECT && direction != RC_DISTORT)
+        return fail(ctx, RC_ERR_INVALID_ARG, "direction must be RC_CORRECT or RC_DISTORT");
+    if (x != y && overlaps(x, n * 8, y, n * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "x and y partially overlap");
+    if (!is_pow2(n))
+        return fail(ctx, RC_ERR_UNSUPPORTED, "n must be a power of two in this build");
+    DeviceGuard g(ctx->device);
+    const FftPlan *plan = nullptr;
+    rc_status st = get_plan(ctx, n, &plan);
+    if (st != RC_OK)
+        return st;
+    const IonoJob job{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y),
+                      phase_numerator(tec_el_per_m2, direction), carrier_hz, fs_hz};
+    hipError_t e = rc::launch_iono(*plan, ctx->tw4096, nullptr, &job, 1, static_cast<hipStream_t>(stream),
+                                   prof_of(ctx));
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "correct_ionosphere launch");
+    return RC_OK;
+}
+
+rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_len, rc_c64 *y_packed,
+                              int64_t y_len, const rc_pulse *pulses, int32_t count, const rc_sinc *k,
+                              void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    rc_status st = check_sinc(ctx, k);
+    if (st != RC_OK)
+        return st;
+    if (count < 0 || (count > 0 && (!pulses || !x_packed || !y_packed)))
+        return fail(ctx, RC_ERR_INVALID_ARG, "NULL pointer or negative count");
+    if (count == 0)
+        return RC_OK;
+    if (x_len <= 0 || y_len <= 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "buffer lengths must be > 0");
+    if (overlaps(x_packed, x_len * 8, y_packed, y_len * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "input and output buffers overlap");
+    // validate every pulse; output ranges must be pairwise disjoint
+    std::vector<std::pair<int64_t, int64_t>> outs;
+    outs.reserve((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        const rc_pulse &p = pulses[i];
+        const std::string at = "pulse " + std::to_string(i) + ": ";
+        if (p.n_in <= 0 || p.n_out <= 0 || p.off_in < 0 || p.off_out < 0 || p.off_in > x_len - p.n_in ||
+            p.off_out > y_len - p.n_out)
+            return fail(ctx, RC_ERR_INVALID_ARG, at + "range outside its buffer");
+        if ((p.flags & ~(uint32_t)(RC_DO_DOPPLER | RC_DO_IONO)) != 0)
+            return fail(ctx, RC_ERR_INVALID_ARG, at + "unknown flag bits");
+        if (!(std::isfinite(p.fs_hz) && p.fs_hz > 0.0))
+            return fail(ctx, RC_ERR_INVALID_ARG, at + "fs_hz must be finite and > 0");
+        if ((p.flags & RC_DO_DOPPLER) && !(std::isfinite(p.alpha) && p.alpha > 0.0))
+            return fail(ctx, RC_ERR_INVALID_ARG, at + "alpha must be finite and > 0");
+        if (!(p.flags & RC_DO_DOPPLER) && p.n_out != p.n_in)
+            return fail(ctx, RC_ERR_INVALID_ARG, at + "n_out must equal n_in without RC_DO_DOPPLER");
+        if (p.flags & RC_DO_IONO) {
+            if (!(std::isfinite(p.tec_el_per_m2) && p.tec_el_per_m2 >= 0.0) || !std::isfinite(p.carrier_hz))
+                return fail(ctx, RC_ERR_INVALID_ARG, at + "tec must be finite and >= 0, carrier finite");
+            if (p.direction != RC_CORRECT && p.direction != RC_DISTORT)
+                return fail(ctx, RC_ERR_INVALID_ARG, at + "bad direction");
+            if (!is_pow2(p.n_out))
+                return fail(ctx, RC_ERR_UNSUPPORTED, at + "iono length must be a power of two in this build");
+        }
+        outs.emplace_back(p.off_out, p.off_out + p.n_out);
+    }
+    std::sort(outs.begin(), outs.end());
+    for (size_t i = 1; i < outs.size(); ++i)
+        if (outs[i].first < outs[i - 1].second)
+            return fail(ctx, RC_ERR_INVALID_ARG, "output ranges overlap");
+
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const float2 *xb = reinterpret_cast<const float2 *>(x_packed);
+    float2 *yb = reinterpret_cast<float2 *>(y_packed);
+
+    // Group the work: fast-path Doppler jobs, generic Doppler jobs, plain copies, and the
+    // ionospheric jobs by transform length (one launch sequence per length).
+    std::vector<SincJob> fast, direct;
+    int64_t fast_max = 0, direct_max = 0, direct_taps = 0;
+    std::map<int64_t, std::vector<IonoJob>> iono;
+    std::vector<int32_t> copies;
+    for (int32_t i = 0; i < count; ++i) {
+        const rc_pulse &p = pulses[i];
+        if (p.flags & RC_DO_DOPPLER) {
+            const SincJob j{xb + p.off_in, yb + p.off_out, p.n_in, p.n_out, p.alpha};
+            if (rc::sinc_fast_eligible(p.alpha, *k)) {
+                fast.push_back(j);
+                fast_max = std::max(fast_max, p.n_out);
+            } else {
+                direct.push_back(j);
+                direct_max = std::max(direct_max, p.n_out);
+                direct_taps = std::max(direct_taps, taps_per_output(*k, p.n_in));
+            }
+        } else if (!(p.flags & RC_DO_IONO)) {
+            copies.push_back(i);
+        }
+        if (p.flags & RC_DO_IONO) {
+            const float2 *src = (p.flags & RC_DO_DOPPLER) ? yb + p.off_out : xb + p.off_in;
+            iono[p.n_out].push_back(IonoJob{src, yb + p.off_out, phase_numerator(p.tec_el_per_m2, p.direction),
+                                            p.carrier_hz, p.fs_hz});
+        }
+    }
+    if (fast.size() > 65535 || direct.size() > 65535)
+        return fail(ctx, RC_ERR_UNSUPPORTED, "more than 65535 pulses of one kind in a batch");
+    for (auto &kv : iono) {
+        const FftPlan *plan = nullptr;
+        st = get_plan(ctx, kv.first, &plan);
+        if (st != RC_OK)
+            return st;
+    }
+
+    // one descriptor upload: [fast | direct | iono groups...]
+    std::vector<char> blob;
+    auto append = [&](const void *p, size_t bytes) {
+        const size_t off = (blob.size() + 15) & ~(size_t)15;
+        blob.resize(off + bytes);
+        std::memcpy(blob.data() + off, p, bytes);
+        return off;
+    };
+    const size_t off_fast = fast.empty() ? 0 : append(fast.data(), fast.size() * sizeof(SincJob));
+    const size_t off_direct = direct.empty() ? 0 : append(direct.data(), direct.size() * sizeof(SincJob));
+    std::vector<size_t> off_iono;
+    for (auto &kv : iono)
+        off_iono.push_back(append(kv.second.data(), kv.second.size() * sizeof(IonoJob)));
+    const void *dev = nullptr;
+    if (!blob.empty()) {
+        st = stage_descriptors(ctx, blob.data(), blob.size(), s, &dev);
+        if (st != RC_OK)
+            return st;
+    }
+    const char *devc = static_cast<const char *>(dev);
+    hipError_t e = hipSuccess;
+    for (int32_t i : copies) {
+        const rc_pulse &p = pulses[i];
+        e = hipMemcpyAsync(yb + p.off_out, xb + p.off_in, (size_t)p.n_in * 8, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return device_fail(ctx, e, "copy");
+    }
+    const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
+    if (!fast.empty())
+        e = rc::launch_sinc_fast(reinterpret_cast<const SincJob *>(devc + off_fast), nullptr, (int)fast.size(),
+                                 fast_max, k->half_width, kp, s, prof_of(ctx));
+    if (e == hipSuccess && !direct.empty())
+        e = rc::launch_sinc_direct(reinterpret_cast<const SincJob *>(devc + off_direct), nullptr,
+                                   (int)direct.size(), direct_max, *k, kp, direct_taps, s, prof_of(ctx));
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "batch Doppler launch");
+    size_t gi = 0;
+    for (auto &kv : iono) {
+        const FftPlan *plan = nullptr;
+        st = get_plan(ctx, kv.first, &plan);
+        if (st != RC_OK)
+            return st;
+        const IonoJob *jd = reinterpret_cast<const IonoJob *>(devc + off_iono[gi++]);
+        // at most 65535 pulses per launch keeps every grid dimension in range
+        for (size_t b = 0; b < kv.second.size(); b += 65535) {
+            const int nj = (int)std::min<size_t>(65535, kv.second.size() - b);
+            e = rc::launch_iono(*plan, ctx->tw4096, jd + b, nullptr, nj, s, prof_of(ctx));
+            if (e != hipSuccess)
+                return device_fail(ctx, e, "batch ionosphere launch");
+        }
+    }
+    if (!blob.empty())
+        return mark_descriptors_used(ctx, s);
+    return RC_OK;
+}
+
+rc_status rc_profile_enable(rc_context ctx, int enable)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->prof.on = enable != 0;
+    return RC_OK;
+}
+
+rc_status rc_profile_read(rc_context ctx, const char *kernel, double *total_ms, int64_t *launches)
+{
+    if (!ctx || !kernel || !total_ms || !launches)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    int grp = -1;
+    for (int i = 0; i < rc::kKGroups; ++i)
+        if (std::strcmp(kernel, rc::kKernelNames[i]) == 0)
+            grp = i;
+    if (grp < 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, std::string("unknown kernel name ") + kernel);
+    hipError_t e = ctx->prof.collect();
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "rc_profile_read");
+    *total_ms = ctx->prof.total_ms[grp];
+    *launches = ctx->prof.launches[grp];
+    ctx->prof.total_ms[grp] = 0.0;
+    ctx->prof.launches[grp] = 0;
+    return RC_OK;
+}
+
+}  // extern "C"
+
+namespace rc {
+
+const char *const kKernelNames[kKGroups] = {"k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd",
+                                            "k_fft_rows_iono", "k_fft_strided_inv"};
+
+hipEvent_t Profiler::take()
+{
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+void Profiler::begin(int group, hipStream_t s)
+{
+    open_group = group;
+    open_a = take();
+    if (open_a)
+        (void)hipEventRecord(open_a, s);
+}
+
+void Profiler::end(hipStream_t s)
+{
+    hipEvent_t b = take();
+    if (open_a && b && hipEventRecord(b, s) == hipSuccess) {
+        spans.push_back(Span{open_group, open_a, b});
+    } else {
+        if (open_a)
+            pool.push_back(open_a);
+        if (b)
+            pool.push_back(b);
+    }
+    open_a = nullptr;
+    open_group = -1;
+}
+
+hipError_t Profiler::collect()
+{
+    hipError_t first = hipSuccess;
+    for (const Span &sp : spans) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(sp.b);
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, sp.a, sp.b);
+        if (e == hipSuccess) {
+            total_ms[sp.group] += ms;
+            launches[sp.group] += 1;
+        } else if (first == hipSuccess) {
+            first = e;
+        }
+        pool.push_back(sp.a);
+        pool.push_back(sp.b);
+    }
+    spans.clear();
+    return first;
+}
+
+void Profiler::release()
+{
+    (void)collect();
+    for (hipEvent_t e : pool)
+        (void)hipEventDestroy(e);
+    pool.clear();
+}
+
+}  // namespace rc

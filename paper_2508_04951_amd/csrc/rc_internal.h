@@ -1,0 +1,145 @@
+// rc_internal.h -- types shared by the HIP sources of librc.so (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rc.h"
+
+namespace rc {
+
+// Optional kernel timing: while `on`, each launch is bracketed by two HIP events on its stream.
+enum KernelGroup { kKSincFast = 0, kKSincDirect, kKFftStridedFwd, kKFftRowsIono, kKFftStridedInv, kKGroups };
+extern const char *const kKernelNames[kKGroups];
+
+struct Profiler {
+    bool on = false;
+    struct Span {
+        int group;
+        hipEvent_t a, b;
+    };
+    std::vector<Span> spans;
+    std::vector<hipEvent_t> pool;
+    double total_ms[kKGroups] = {0};
+    int64_t launches[kKGroups] = {0};
+    int open_group = -1;
+    hipEvent_t open_a = nullptr;
+    hipEvent_t take();
+    void begin(int group, hipStream_t s);
+    void end(hipStream_t s);
+    hipError_t collect();  // wait for recorded spans and accumulate them
+    void release();
+};
+
+// Physical constants: c exact (SI); e exact (2019 SI); m_e and eps0 CODATA 2022.
+constexpr double kC = 299792458.0;
+constexpr double kECharge = 1.602176634e-19;
+constexpr double kMe = 9.1093837139e-31;
+constexpr double kEps0 = 8.8541878188e-12;
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------------------
+// Doppler resampling
+// ---------------------------------------------------------------------------------------
+
+// Kaiser taper as a power series in s = 1 - x^2:  K(x) = sum_j c[j] s^j,  |x| < 1.
+// From I0(z) = sum_j (z^2/4)^j / (j!)^2 with z^2 = beta^2 s, divided by I0(beta).
+// All terms are positive for s in [0, 1], so the Horner sum has no cancellation.
+struct KaiserPoly {
+    int n;          // number of terms
+    double c[56];   // c[j] = (beta^2/4)^j / (j!)^2 / I0(beta)
+};
+
+// One resampling job (one pulse).  Pointers are device addresses.
+struct SincJob {
+    const float2 *x;
+    float2 *y;
+    int64_t n_in;
+    int64_t n_out;
+    double alpha;
+};
+
+// Tile geometry of the windowed fast path: each wave owns 256 consecutive outputs
+// (4 per lane); a 256-thread workgroup owns 1024.
+constexpr int kSincLanesOut = 4;
+constexpr int kSincWaveOut = 64 * kSincLanesOut;
+constexpr int kSincWgOut = 4 * kSincWaveOut;
+// |alpha - 1| bound of the fast path: keeps the per-tile sample-position drift
+// |alpha-1| * 127.5 below 0.013 samples, where the quadratic-in-drift weights are
+// accurate to ~1e-7 per tap.
+constexpr double kSincFastMaxEps = 1.0e-4;
+
+bool sinc_fast_eligible(double alpha, const rc_sinc &k);
+KaiserPoly make_kaiser_poly(double beta);
+size_t sinc_fast_lds_bytes(int half_width);
+
+// Launchers (return the hipError_t of the launch).
+hipError_t launch_sinc_fast(const SincJob *jobs_dev, const SincJob *job_inline, int njobs,
+                            int64_t max_out, int half_width, const KaiserPoly &kp,
+                            hipStream_t s, Profiler *prof);
+hipError_t launch_sinc_direct(const SincJob *jobs_dev, const SincJob *job_inline, int njobs,
+                              int64_t max_out, const rc_sinc &k, const KaiserPoly &kp,
+                              int64_t max_taps, hipStream_t s, Profiler *prof);
+
+// ---------------------------------------------------------------------------------------
+// FFT / ionosphere
+// ---------------------------------------------------------------------------------------
+
+// Every FFT pass works on a tile of 4096 complex samples (32 KiB of LDS) with 256 threads.
+constexpr int kFftTile = 4096;
+constexpr int kFftThreads = 256;
+constexpr int kFftMaxLevels = 4;
+
+// Per-pulse ionospheric parameters.  phase_num = s * 4 pi K2 / c (rad Hz), s = -1 for
+// correction (Eq 16) and +1 for distortion (Eq 15); f_k = carrier + fs * kk / n.
+struct IonoJob {
+    const float2 *x;  // input of the first pass (may equal y)
+    float2 *y;        // output; every later pass runs in place on y
+    double phase_num;
+    double carrier;
+    double fs;
+};
+
+// Decomposition of an n-point transform into levels L_0 x L_1 x ... x L_{d-1}
+// (row-major, L_{d-1} contiguous).  Strided levels are <= 256 long, the last <= 4096.
+struct FftPlan {
+    int64_t n = 0;
+    int levels = 0;
+    int len[kFftMaxLevels] = {0, 0, 0, 0};
+    int log2len[kFftMaxLevels] = {0, 0, 0, 0};
+    // Twiddle tables for the strided levels i < levels-1: exp(-2 pi i q / nsub_i),
+    // nsub_i = L_i * prod_{j>i} L_j, split as q = qh * 4096 + ql.
+    float2 *tw_lo[kFftMaxLevels] = {nullptr, nullptr, nullptr, nullptr};  // 4096 entries
+    float2 *tw_hi[kFftMaxLevels] = {nullptr, nullptr, nullptr, nullptr};  // nsub/4096 entries
+};
+
+hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs);
+hipError_t make_base_twiddles(float2 **dev);  // exp(-2 pi i q / 4096), q < 4096
+
+// Full ionospheric operator for njobs pulses of the same length plan.n.
+hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
+                       const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof);
+
+}  // namespace rc
+
+// The context behind the opaque rc_context handle.
+struct rc_context_s {
+    int device = 0;
+    std::mutex mu;
+    std::string last_error;
+    float2 *tw4096 = nullptr;                  // base twiddles exp(-2 pi i q / 4096)
+    std::map<int64_t, rc::FftPlan> plans;      // by transform length
+    std::vector<void *> allocs;                // every device allocation owned
+    // descriptor staging for batches: pinned host + device, guarded by `desc_done`
+    void *desc_host = nullptr;
+    void *desc_dev = nullptr;
+    size_t desc_cap = 0;
+    hipEvent_t desc_done = nullptr;
+    bool desc_pending = false;
+    rc::Profiler prof;
+};

@@ -1,0 +1,313 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 oracle on the same
+seeded complex64 inputs.
+
+Tolerance: relative L2 error <= 1e-5 per pulse for the float32 paths (the accuracy bar of
+the correction path; the float32 kernels land near 1e-7).  Exact special cases (alpha = 1,
+integer alpha) are compared bit for bit.  Every alpha is the correctly rounded
+(c + v)/(c - v), computed here with exact rationals and handed to both sides.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import waveforms as wf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+C = 299792458
+
+
+def alpha_exact(v):
+    return float(Fraction(C + Fraction(v)) / Fraction(C - Fraction(v)))
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2508_04951_amd as rc
+
+    return rc.Context(0)
+
+
+def dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).to("cuda")
+
+
+def host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def sinc(hw, window="kaiser", beta=8.0):
+    import paper_2508_04951_amd as rc
+
+    return rc.Sinc(hw, window, beta)
+
+
+# --- Doppler --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,hw,window", [(65536, 64, "kaiser"), (5000, 20, "paper"), (300, 0, "kaiser"),
+                                         (777, 16, "rect")])
+def test_doppler_alpha_one_is_bit_exact(torch, ctx, n, hw, window):
+    x = wf.bandlimited_noise(n, wf.rng_for(101, n))
+    y = host(ctx.correct_doppler(dev(torch, x), 1.0, sinc(hw, window)))
+    assert np.array_equal(y, x)
+
+
+@pytest.mark.parametrize("alpha", [2.0, 3.0])
+def test_doppler_integer_alpha_is_bit_exact(torch, ctx, alpha):
+    x = wf.bandlimited_noise(999, wf.rng_for(102, 0))
+    y = host(ctx.correct_doppler(dev(torch, x), alpha, sinc(16)))
+    a = int(alpha)
+    exp = np.zeros(999, np.complex64)
+    exp[: 998 // a + 1] = x[::a]
+    assert np.array_equal(y, exp)
+
+
+ALPHAS = [alpha_exact(8000.0), alpha_exact(-8000.0), alpha_exact(7500.0), 1 + 1e-6, 1 - 3e-7, 1.3, 0.77]
+SINCS = [(64, "kaiser", 8.0), (8, "kaiser", 5.0), (16, "rect", 0.0), (20, "paper", 0.0), (0, "kaiser", 8.0)]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 1000, 1025, 4096, 5000])
+@pytest.mark.parametrize("sk", SINCS, ids=lambda s: f"{s[1]}{s[0]}")
+def test_doppler_parity_grid(torch, ctx, orc, n, sk):
+    hw, window, beta = sk
+    x = wf.bandlimited_noise(n, wf.rng_for(103, n)) if n > 8 else \
+        (wf.rng_for(103, n).standard_normal(n) + 1j).astype(np.complex64)
+    xd = dev(torch, x)
+    for alpha in ALPHAS:
+        for n_out in sorted({n, n + 37, max(1, n // 2)}):
+            y = host(ctx.correct_doppler(xd, alpha, sinc(hw, window, beta), n_out=n_out))
+            ref = orc.doppler(x, alpha, hw, window, beta, n_out=n_out)
+            err = rel_l2(y, ref)
+            assert err <= TOL, (n, n_out, alpha, sk, err)
+
+
+@pytest.mark.parametrize("v", [8000.0, -8000.0, 5000.0, -2500.0, 1e-3, -7.7])
+@pytest.mark.parametrize("hw", [64, 128])
+def test_doppler_fast_path_at_pulse_length(torch, ctx, orc, v, hw):
+    """The windowed fast path at the batch pulse length 65536 (and a ragged tail)."""
+    x = wf.c2_pulse(3)
+    alpha = alpha_exact(v)
+    for n_out in (65536, 65536 - 333):
+        y = host(ctx.correct_doppler(dev(torch, x), alpha, sinc(hw), n_out=n_out))
+        ref = orc.doppler(x, alpha, hw, "kaiser", 8.0, n_out=n_out)
+        assert rel_l2(y, ref) <= TOL
+        assert np.max(np.abs(y - ref)) <= 20 * TOL * np.sqrt(np.mean(np.abs(ref) ** 2))
+
+
+def test_doppler_long_pulse_sampled(torch, ctx, orc):
+    """2^24 samples at +/-8 km/s (895 samples of accumulated shift, float64 positions):
+    sampled outputs, including the far end, against the oracle."""
+    n = 1 << 24
+    x = wf.bandlimited_noise(n, wf.rng_for(104, 0))
+    xd = dev(torch, x)
+    idx = np.concatenate([np.arange(0, 2000), np.arange(n - 4000, n),
+                          wf.rng_for(104, 1).integers(0, n, 4000)])
+    for v in (8000.0, -8000.0):
+        alpha = alpha_exact(v)
+        y = host(ctx.correct_doppler(xd, alpha, sinc(128)))
+        ref = orc.doppler_at(x, idx, alpha, 128, "kaiser", 8.0)
+        assert rel_l2(y[idx], ref) <= TOL
+
+
+# --- Ionosphere -----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 32, 256, 1024, 4096, 8192, 65536, 1 << 20])
+@pytest.mark.parametrize("direction", ["correct", "distort"])
+def test_iono_parity(torch, ctx, orc, n, direction):
+    x = wf.bandlimited_noise(n, wf.rng_for(105, n)) if n > 2 else np.array([1 + 2j, -0.5j][:n], np.complex64)
+    for tec_tecu, fc, fs in [(50.0, 450e6, 10e6), (100.0, 450e6, 10e6), (5.0, 150e6, 10e6), (0.0, 450e6, 10e6),
+                             (100.0, 0.0, 2.048e9)]:
+        y = host(ctx.correct_ionosphere(dev(torch, x), fs, fc, tec_tecu * wf.TECU, direction))
+        ref = orc.ionosphere(x, fs, fc, tec_tecu * wf.TECU, direction, naive=False)
+        err = rel_l2(y, ref)
+        assert err <= TOL, (n, direction, tec_tecu, fc, err)
+
+
+def test_iono_in_place(torch, ctx, orc):
+    x = wf.bandlimited_noise(65536, wf.rng_for(106, 0))
+    xd = dev(torch, x)
+    ctx.correct_ionosphere(xd, 10e6, 450e6, 70 * wf.TECU, "correct", out=xd)
+    ref = orc.ionosphere(x, 10e6, 450e6, 70 * wf.TECU, "correct", naive=False)
+    assert rel_l2(host(xd), ref) <= TOL
+
+
+def test_iono_round_trip_and_norm_at_2_24(torch, ctx):
+    """Full long-dwell length: distort then correct returns the input; the operator is unitary."""
+    n = 1 << 24
+    x = wf.bandlimited_noise(n, wf.rng_for(107, 0))
+    xd = dev(torch, x)
+    d = ctx.correct_ionosphere(xd, 10e6, 450e6, 100 * wf.TECU, "distort")
+    dn = host(d)
+    back = host(ctx.correct_ionosphere(d, 10e6, 450e6, 100 * wf.TECU, "correct"))
+    assert rel_l2(back, x) <= TOL
+    assert np.linalg.norm(dn.astype(np.complex128)) == pytest.approx(np.linalg.norm(x.astype(np.complex128)), rel=1e-5)
+
+
+def test_iono_sampled_bins_at_2_22(torch, ctx, orc):
+    """2^22 samples against the oracle's float64 FFT path."""
+    n = 1 << 22
+    x = wf.bandlimited_noise(n, wf.rng_for(108, 0))
+    y = host(ctx.correct_ionosphere(dev(torch, x), 10e6, 450e6, 60 * wf.TECU, "correct"))
+    ref = orc.ionosphere(x, 10e6, 450e6, 60 * wf.TECU, "correct", naive=False)
+    assert rel_l2(y, ref) <= TOL
+
+
+# --- Whole path -----------------------------------------------------------------------------
+
+def test_c1_single_lfm_pulse(torch, ctx, orc):
+    """Single LFM pulse, N = 4096, fs = 10 MHz, B = 5 MHz, v_r = +7.5 km/s, full sinc,
+    then ionospheric correction at 50 TECU, carrier 450 MHz."""
+    import paper_2508_04951_amd as rc
+
+    c = wf.C1
+    x = wf.lfm(c["n"], c["fs"], c["bandwidth"])
+    alpha = alpha_exact(c["v_r"])
+    ref = orc.correct_pulse(x, c["fs"], alpha, c["tec"], c["carrier"], half_width=0, naive=True)
+    xd = dev(torch, x)
+    r = ctx.correct_doppler(xd, alpha, rc.Sinc(0))
+    y1 = host(ctx.correct_ionosphere(r, c["fs"], c["carrier"], c["tec"], "correct"))
+    assert rel_l2(y1, ref) <= TOL
+    yd = torch.empty_like(xd)
+    ctx.correct_pulse_batch(xd, yd, [dict(off_in=0, n_in=4096, off_out=0, n_out=4096, fs=c["fs"], alpha=alpha,
+                                          tec=c["tec"], carrier=c["carrier"])], rc.Sinc(0))
+    assert np.array_equal(host(yd), y1)
+
+
+def _ragged_batch():
+    """Pulses of mixed length, alpha, TEC, flags and direction, packed with gaps."""
+    rng = wf.rng_for(109, 0)
+    specs = [(65536, 3), (4096, 3), (8192, 1), (1000, 1), (65536, 2), (256, 3), (1 << 17, 3), (4096, 2),
+             (3000, 1), (16, 3)]
+    pulses, xs = [], []
+    off_in = off_out = 5
+    for i, (n, flags) in enumerate(specs):
+        x = wf.bandlimited_noise(n, wf.rng_for(109, i + 1))
+        v = rng.uniform(-8000, 8000) if i != 7 else 1.2e6  # one pulse off the fast path
+        p = dict(off_in=off_in, n_in=n, off_out=off_out, n_out=n, fs=10e6, alpha=alpha_exact(v),
+                 tec=rng.uniform(5, 100) * wf.TECU, carrier=450e6, flags=flags,
+                 direction="distort" if i % 4 == 3 else "correct")
+        pulses.append(p)
+        xs.append(x)
+        off_in += n + 3
+        off_out += n + 11
+    return pulses, xs, off_in, off_out
+
+
+def test_batch_matches_oracle_and_single_calls(torch, ctx, orc):
+    import paper_2508_04951_amd as rc
+
+    pulses, xs, x_len, y_len = _ragged_batch()
+    xp = np.zeros(x_len, np.complex64)
+    for p, x in zip(pulses, xs):
+        xp[p["off_in"]:p["off_in"] + p["n_in"]] = x
+    xd = dev(torch, xp)
+    yd = torch.full((y_len,), complex("nan"), dtype=torch.complex64, device="cuda")
+    ctx.correct_pulse_batch(xd, yd, pulses, rc.Sinc(64))
+    yb = host(yd)
+    for i, (p, x) in enumerate(zip(pulses, xs)):
+        got = yb[p["off_out"]:p["off_out"] + p["n_out"]]
+        assert not np.isnan(got).any(), i
+        ref = orc.correct_pulse(x, p["fs"], p["alpha"], p["tec"], p["carrier"], n_out=p["n_out"],
+                                doppler_on=bool(p["flags"] & 1), iono_on=bool(p["flags"] & 2),
+                                direction=p["direction"], half_width=64)
+        assert rel_l2(got, ref) <= TOL, (i, rel_l2(got, ref))
+        # the same pulse alone, through the single-pulse entry points: bit-identical
+        xi = dev(torch, x)
+        r = ctx.correct_doppler(xi, p["alpha"], rc.Sinc(64)) if p["flags"] & 1 else xi
+        if p["flags"] & 2:
+            r = ctx.correct_ionosphere(r, p["fs"], p["carrier"], p["tec"], p["direction"])
+        assert np.array_equal(host(r), got), i
+    gaps = np.ones(y_len, bool)
+    for p in pulses:
+        gaps[p["off_out"]:p["off_out"] + p["n_out"]] = False
+    assert np.isnan(yb[gaps]).all()  # nothing written outside the pulses
+
+
+def test_batch_c2_full_size_sampled(torch, ctx, orc):
+    """The full batch workload (1024 pulses x 65536, Kaiser H = 64, beta = 8) in one call;
+    four seeded pulses compared in full against the oracle, all pulses finite."""
+    import paper_2508_04951_amd as rc
+
+    c = wf.C2
+    n, P = c["n"], c["pulses"]
+    v, e = wf.c2_params()
+    x = np.empty(P * n, np.complex64)
+    for p in range(P):
+        x[p * n:(p + 1) * n] = wf.c2_pulse(p)
+    pulses = [dict(off_in=p * n, n_in=n, off_out=p * n, n_out=n, fs=c["fs"], alpha=alpha_exact(v[p]),
+                   tec=e[p], carrier=c["carrier"]) for p in range(P)]
+    xd = dev(torch, x)
+    yd = torch.empty_like(xd)
+    ctx.correct_pulse_batch(xd, yd, pulses, rc.Sinc(64, "kaiser", 8.0))
+    y = host(yd)
+    assert np.isfinite(y.view(np.float32)).all()
+    for p in (0, 1, 511, 1023):
+        ref = orc.correct_pulse(x[p * n:(p + 1) * n], c["fs"], pulses[p]["alpha"], e[p], c["carrier"],
+                                half_width=64, beta=8.0)
+        assert rel_l2(y[p * n:(p + 1) * n], ref) <= TOL, p
+
+
+def test_repeat_runs_are_bit_identical(torch, ctx):
+    import paper_2508_04951_amd as rc
+
+    x = dev(torch, wf.c2_pulse(7))
+    a = alpha_exact(-6543.0)
+    y1 = host(ctx.correct_ionosphere(ctx.correct_doppler(x, a, rc.Sinc(64)), 10e6, 450e6, 30 * wf.TECU))
+    y2 = host(ctx.correct_ionosphere(ctx.correct_doppler(x, a, rc.Sinc(64)), 10e6, 450e6, 30 * wf.TECU))
+    assert np.array_equal(y1, y2)
+
+
+# --- Argument validation ---------------------------------------------------------------------
+
+def test_invalid_arguments_are_rejected(torch, ctx):
+    import paper_2508_04951_amd as rc
+
+    x = torch.zeros(64, dtype=torch.complex64, device="cuda")
+    y = torch.zeros(64, dtype=torch.complex64, device="cuda")
+    with pytest.raises(ValueError):
+        ctx.correct_doppler(x, 0.0)
+    with pytest.raises(ValueError):
+        ctx.correct_doppler(x, float("nan"))
+    with pytest.raises(ValueError):
+        ctx.correct_doppler(x, 1.0, rc.Sinc(-1))
+    with pytest.raises(ValueError):
+        ctx.correct_doppler(x, 1.0, fs=0.0)
+    with pytest.raises(ValueError):
+        ctx.correct_doppler(x, 1.0, out=x)  # x and y overlap
+    with pytest.raises(ValueError):
+        ctx.correct_ionosphere(x, 10e6, 450e6, -1.0)
+    with pytest.raises(ValueError):
+        ctx.correct_ionosphere(x[1:], 10e6, 450e6, 1e17, out=x[:-1])  # partial overlap
+    with pytest.raises(rc.RcError) as ei:
+        ctx.correct_ionosphere(x[:48], 10e6, 450e6, 1e17)
+    assert ei.value.status == 2  # RC_ERR_UNSUPPORTED (not a power of two)
+    ok = dict(off_in=0, n_in=32, off_out=0, n_out=32, fs=10e6, alpha=1.0, tec=1e17, carrier=450e6)
+    with pytest.raises(ValueError):
+        ctx.correct_pulse_batch(x, y, [dict(ok, off_in=40)])  # past the end of x
+    with pytest.raises(ValueError):
+        ctx.correct_pulse_batch(x, y, [ok, dict(ok, off_out=16)])  # overlapping outputs
+    with pytest.raises(ValueError):
+        ctx.correct_pulse_batch(x, x, [ok])  # in-place batch
+    with pytest.raises(ValueError):
+        ctx.correct_pulse_batch(x, y, [dict(ok, flags=2, n_out=16)])  # length change without Doppler
+    ctx.correct_pulse_batch(x, y, [ok])
+    ctx.sync()
