@@ -205,8 +205,8 @@ k_sinc_direct(const SincJob *__restrict__ jobs, SincJob inl, int H, int window, 
         const double t = __dmul_rn(jb.alpha, (double)m);
         const double f = floor(t);
         if (t == f) {
-            mode = 1;
-            if (f < (double)jb.n_in) {
+            mode = 1;  // only lane 0 of the group carries the sample into the reduction
+            if (sub == 0 && f < (double)jb.n_in) {
                 const float2 v = jb.x[(int64_t)f];
                 re = v.x;
                 im = v.y;
