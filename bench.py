@@ -59,7 +59,7 @@ def make_workload(pulses: int):
 
 def roofline_for(kernel: str, avg_ms: float, samples: int, half_width: int, passes_per_kernel: float):
     """Algorithmic work of one launch of `kernel` divided by its average duration."""
-    if kernel == "k_sinc_fast" or kernel == "k_sinc_direct":
+    if kernel in ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct"):
         flops = 8.0 * half_width * samples  # 2H taps x (2 FMA = 4 flop) per output sample
         achieved = flops / (avg_ms * 1e-3) / 1e12
         return {"kernel": kernel, "bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--engine", choices=["auto", "valu", "direct"], default="auto",
+                    help="resampling engine (auto: matrix cores where eligible)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -131,6 +133,7 @@ def main():
     yd = torch.empty_like(xd)
     ctx = rc.Context(0)
     sinc = rc.Sinc(c["half_width"], "kaiser", c["beta"])
+    ctx.set_sinc_engine(args.engine)
 
     def step():
         ctx.correct_pulse_batch(xd, yd, desc, sinc)
@@ -210,7 +213,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"batch {P} pulses x {n} complex64 band-limited noise, Kaiser sinc H=64 beta=8, "
                                f"v_r~U[-8,8] km/s, iono E~U[5,100] TECU at 450 MHz, fs 10 MHz",
-                   "pulses": P, "samples_per_pulse": n, "half_width": c["half_width"], "beta": c["beta"]},
+                   "pulses": P, "samples_per_pulse": n, "half_width": c["half_width"], "beta": c["beta"],
+                   "sinc_engine": args.engine},
         "roofline": roof,
         "cpu_baseline": cpu,
         "rel_err_max_sampled": rel_err,

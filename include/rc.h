@@ -148,11 +148,23 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
                               rc_c64 *y_packed, int64_t y_len, const rc_pulse *pulses,
                               int32_t count, const rc_sinc *k, void *stream);
 
+/* Resampling engine (rc_set_sinc_engine).  Every engine computes the same sum of Eq (17):
+ *   RC_SINC_AUTO   matrix cores for the Kaiser taper at H = 64 or 128 and |alpha - 1| <= 6e-5,
+ *                  else the vector tile kernel (Kaiser, H <= 256, |alpha - 1| <= 1e-4), else the
+ *                  direct float64 sum;
+ *   RC_SINC_VALU   never the matrix cores;
+ *   RC_SINC_DIRECT always the direct float64 sum (reference-speed path). */
+enum { RC_SINC_AUTO = 0, RC_SINC_VALU = 1, RC_SINC_DIRECT = 2 };
+
+/* Select the resampling engine of the context's later calls; RC_ERR_INVALID_ARG for an
+ * unknown engine.  The default is RC_SINC_AUTO. */
+rc_status rc_set_sinc_engine(rc_context ctx, int32_t engine);
+
 /* Kernel timing for benchmarks.  While enabled, every kernel the context launches is
  * bracketed by a pair of HIP events recorded on the launch stream.  rc_profile_read waits for
  * the recorded events, adds their spans to per-kernel totals, and returns (then clears) the
- * total milliseconds and launch count of one kernel: "k_sinc_fast", "k_sinc_direct",
- * "k_fft_strided_fwd", "k_fft_rows_iono" or "k_fft_strided_inv".  Unknown names give
+ * total milliseconds and launch count of one kernel: "k_sinc_mfma", "k_sinc_fast",
+ * "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono" or "k_fft_strided_inv".  Unknown names give
  * RC_ERR_INVALID_ARG.  Timing adds two event records per launch and no synchronisation. */
 rc_status rc_profile_enable(rc_context ctx, int enable);
 rc_status rc_profile_read(rc_context ctx, const char *kernel, double *total_ms, int64_t *launches);

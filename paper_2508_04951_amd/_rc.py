@@ -24,9 +24,11 @@ DO_DOPPLER, DO_IONO = 1, 2
 SYMBOLS = (
     "rc_create", "rc_destroy", "rc_status_string", "rc_last_error", "rc_alpha_from_vr",
     "rc_k2_per_tec", "rc_sync", "correct_doppler", "correct_ionosphere", "correct_pulse_batch",
-    "rc_profile_enable", "rc_profile_read",
+    "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine",
 )
-KERNELS = ("k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono", "k_fft_strided_inv")
+KERNELS = ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono",
+           "k_fft_strided_inv")
+SINC_ENGINES = {"auto": 0, "valu": 1, "direct": 2}
 
 
 class RcSinc(ctypes.Structure):
@@ -87,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.rc_profile_enable.restype = c_i32
         lib.rc_profile_read.argtypes = [p, ctypes.c_char_p, ctypes.POINTER(c_d), ctypes.POINTER(c_i64)]
         lib.rc_profile_read.restype = c_i32
+        lib.rc_set_sinc_engine.argtypes = [p, c_i32]
+        lib.rc_set_sinc_engine.restype = c_i32
         _lib = lib
         return lib
 
@@ -175,6 +179,13 @@ class Context:
         st = self._lib.rc_sync(self._h, self._stream(stream))
         if st != RC_OK:
             self._raise(st, "rc_sync")
+
+    def set_sinc_engine(self, engine: str = "auto"):
+        """Resampling engine for later calls: "auto" (matrix cores where eligible), "valu" or
+        "direct" (the float64 direct sum)."""
+        st = self._lib.rc_set_sinc_engine(self._h, SINC_ENGINES[engine])
+        if st != RC_OK:
+            self._raise(st, "rc_set_sinc_engine")
 
     def profile(self, enable: bool = True):
         """Bracket every kernel launch with HIP events on its stream (for benchmarks)."""

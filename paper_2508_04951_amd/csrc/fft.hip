@@ -202,29 +202,65 @@ struct StridedArgs {
     int njobs;
     int log2L, log2C;
     int64_t inner;          // samples below this level (line stride)
-    int64_t outer;          // number of blocks above this level
-    int64_t col_blocks;     // inner / C
+    int log2cb;             // log2(inner / columns per block)
+    int log2pp;             // log2(outer * inner / columns per block): blocks per pulse
     const float2 *tw4096;
     const float2 *tw_lo, *tw_hi;
-    int64_t nsub;           // L * inner
     bool from_x;            // first pass reads job.x
     float scale;            // applied after an inverse pass (1/n in the last one)
 };
 
-// Strided level: lines of length L along stride `inner`; the tile holds C adjacent lines.
+// Strided level of length L <= 16 (one radix stage): each thread owns one column and keeps
+// its L samples in registers -- no LDS, no barrier.  A block covers 256 adjacent columns.
+template <int R, int S>
+__global__ void __launch_bounds__(kFftThreads) k_fft_strided_reg(StridedArgs a)
+{
+    const int64_t blk = blockIdx.x;
+    const int p = (int)(blk >> a.log2pp);
+    const int64_t rem = blk & ((int64_t(1) << a.log2pp) - 1);
+    const int64_t o = rem >> a.log2cb;
+    const int64_t col = ((rem & ((int64_t(1) << a.log2cb) - 1)) << 8) + threadIdx.x;  // n'
+    const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
+    const int64_t base = o * (R * a.inner) + col;
+    const float2 *src = a.from_x ? jb.x : jb.y;
+    float2 v[R];
+#pragma unroll
+    for (int l = 0; l < R; ++l)
+        v[l] = src[base + l * a.inner];
+    if (S > 0) {
+#pragma unroll
+        for (int l = 1; l < R; ++l)
+            v[l] = cmul(v[l], twiddle(a.tw_lo, a.tw_hi, (int64_t)l * col, true));
+    }
+    dftR<R, S>(v);
+    if (S < 0) {
+#pragma unroll
+        for (int l = 1; l < R; ++l)
+            v[l] = cmul(v[l], twiddle(a.tw_lo, a.tw_hi, (int64_t)l * col, false));
+    } else if (a.scale != 1.0f) {
+#pragma unroll
+        for (int l = 0; l < R; ++l) {
+            v[l].x *= a.scale;
+            v[l].y *= a.scale;
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < R; ++l)
+        jb.y[base + l * a.inner] = v[l];
+}
+
+// Strided level of length 32..256: lines of length L along stride `inner`; the LDS tile holds
+// C = 4096/L adjacent columns.
 template <int S>
 __global__ void __launch_bounds__(kFftThreads) k_fft_strided(StridedArgs a)
 {
     __shared__ float2 lds[kLdsSlots];
     const int tid = threadIdx.x;
-    const int64_t per_pulse = a.outer * a.col_blocks;
     const int64_t blk = blockIdx.x;
-    const int p = (int)(blk / per_pulse);
-    if (p >= a.njobs)
-        return;
-    const int64_t rem = blk - (int64_t)p * per_pulse;
-    const int64_t o = rem / a.col_blocks;
-    const int64_t cb = rem - o * a.col_blocks;
+    const int p = (int)(blk >> a.log2pp);
+    const int64_t rem = blk & ((int64_t(1) << a.log2pp) - 1);
+    const int64_t o = rem >> a.log2cb;
+    const int64_t cb = rem & ((int64_t(1) << a.log2cb) - 1);
     const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
     const int L = 1 << a.log2L, C = 1 << a.log2C;
     const int64_t base = o * ((int64_t)L * a.inner) + cb * C;
@@ -233,7 +269,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(StridedArgs a)
         const int c = e & (C - 1), l = e >> a.log2C;
         float2 v = src[base + (int64_t)l * a.inner + c];
         if (S > 0) {  // inverse: conjugate twiddle before the DFT along the level
-            const int64_t q = (int64_t)l * (cb * C + c);  // < L * inner = nsub
+            const int64_t q = (int64_t)l * (cb * C + c);  // < L * inner
             v = cmul(v, twiddle(a.tw_lo, a.tw_hi, q, true));
         }
         lds[tidx(c, l, a.log2L, a.log2C, false)] = v;
@@ -259,7 +295,7 @@ struct RowArgs {
     IonoJob inl;
     int njobs;
     int log2L, log2C;
-    int64_t rows_per_pulse;   // n / L
+    int log2rpp;              // log2(rows per pulse) = log2(n / L)
     int64_t n;
     int levels;
     int len[kFftMaxLevels];   // level lengths (the last is L)
@@ -271,78 +307,160 @@ struct RowArgs {
 __device__ __forceinline__ float2 iono_phase(const IonoJob &jb, int64_t k, int64_t n)
 {
     const int64_t kk = (k < (n + 1) / 2) ? k : k - n;
-    const double f = jb.carrier + jb.fs * (double)kk / (double)n;
+    // n is a power of two, so kk * (1/n) is exactly kk / n
+    const double f = jb.carrier + jb.fs * (double)kk * (1.0 / (double)n);
     if (f == 0.0 || jb.phase_num == 0.0)
         return make_float2(1.f, 0.f);
-    const double ph = jb.phase_num / f;
-    // reduce modulo 2 pi in float64 (|ph| is ~1e3..1e5 rad), then float32 sincos
-    const double red = ph - 6.283185307179586477 * rint(ph * 0.15915494309189533577);
+    // 1/f from the hardware reciprocal and two Newton steps (within 2 ulp; the IEEE division
+    // sequence costs ~70 extra registers here).  The phase, in revolutions, is reduced modulo
+    // 1 in float64 (|phase| is ~1e3..1e5 rad); then the float32 sin/cos of pi * (2 r).
+    double rf = __builtin_amdgcn_rcp(f);
+    rf = fma(rf, fma(-f, rf, 1.0), rf);
+    rf = fma(rf, fma(-f, rf, 1.0), rf);
+    const double t = (jb.phase_num * rf) * 0.15915494309189533577;
+    const double r = t - rint(t);
     float s, c;
-    sincosf((float)red, &s, &c);
+    sincospif((float)(2.0 * r), &s, &c);
     return make_float2(c, s);
 }
 
-// Contiguous level: forward DFT of each row, dispersive phase per bin, inverse DFT.
-__global__ void __launch_bounds__(kFftThreads) k_fft_rows_iono(RowArgs a)
+// One radix-16 Stockham stage of a 4096-point row held as 16 samples per thread
+// (thread j owns positions j + 256 q).  Ns = 16^stage; the output leaves through LDS,
+// except for the last stage, whose outputs j + 256 q are already in place.
+// tw holds exp(-2 pi i q / 4096) followed by its conjugates: the inverse transform reads the
+// second half, so its loads are not merged with (and kept live from) the forward ones.
+template <int S>
+__device__ __forceinline__ void row_twiddle(float2 *v, int k, int step, const float2 *__restrict__ tw)
+{
+    const float2 *t = S > 0 ? tw + kFftTile : tw;
+#pragma unroll
+    for (int q = 1; q < 16; ++q)
+        v[q] = cmul(v[q], t[(q * k * step) & (kFftTile - 1)]);
+}
+
+__device__ __forceinline__ int rpad(int a) { return a + (a >> 4); }
+
+// Full 4096-point DFT of the thread-distributed row: in v[q] = x[j + 256 q], out v[q] = X[j + 256 q].
+template <int S>
+__device__ __forceinline__ void row4096(float2 *v, float2 *lds, int j, const float2 *__restrict__ tw)
+{
+    // stage 1 (Ns = 1): outputs at 16 j + q
+    dftR<16, S>(v);
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        lds[rpad(16 * j + q)] = v[q];
+    __syncthreads();
+    // stage 2 (Ns = 16): inputs j + 256 q, outputs (j / 16) * 256 + j % 16 + 16 q
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        v[q] = lds[rpad(j + 256 * q)];
+    row_twiddle<S>(v, j & 15, 16, tw);
+    dftR<16, S>(v);
+    __syncthreads();
+    const int base = ((j >> 4) << 8) + (j & 15);
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        lds[rpad(base + 16 * q)] = v[q];
+    __syncthreads();
+    // stage 3 (Ns = 256): inputs j + 256 q, outputs j + 256 q
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        v[q] = lds[rpad(j + 256 * q)];
+    row_twiddle<S>(v, j, 1, tw);
+    dftR<16, S>(v);
+    __syncthreads();  // LDS free for the next transform
+}
+
+// Contiguous level of 4096 points, one row per block: forward DFT, phase, inverse DFT.
+__global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
 {
     __shared__ float2 lds[kLdsSlots];
-    const int tid = threadIdx.x;
-    const int L = 1 << a.log2L, C = 1 << a.log2C;
-    const int64_t g0 = (int64_t)blockIdx.x * C;  // first global row of the tile
-    const int64_t total_rows = (int64_t)a.njobs * a.rows_per_pulse;
-    for (int e = tid; e < kFftTile; e += kFftThreads) {
-        const int c = e >> a.log2L, l = e & (L - 1);
-        const int64_t g = g0 + c;
-        float2 v = make_float2(0.f, 0.f);
-        if (g < total_rows) {
-            const int p = (int)(g / a.rows_per_pulse);
-            const int64_t r = g - (int64_t)p * a.rows_per_pulse;
-            const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
-            v = (a.from_x ? jb.x : jb.y)[r * L + l];
-        }
-        lds[tidx(c, l, a.log2L, a.log2C, true)] = v;
-    }
-    __syncthreads();
-    fft_tile<-1>(lds, a.log2L, a.log2C, true, a.tw4096, tid);
-    // Bin of (row r, position l): k = kout(r) + (n / L) * l, kout = digit-reversed row index.
-    // One level: rows are whole pulses (kout = 0).  Several levels: L = 4096, one row per tile.
+    const int j = threadIdx.x;
+    const int64_t g = blockIdx.x;
+    const int p = (int)(g >> a.log2rpp);
+    const int64_t r = g & ((int64_t(1) << a.log2rpp) - 1);
+    const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
+    const float2 *src = (a.from_x ? jb.x : jb.y) + (r << 12);
+    float2 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        v[q] = src[j + 256 * q];
+    row4096<-1>(v, lds, j, a.tw4096);
+    // bin of row position l: k = kout(r) + (n / 4096) l, kout = digit-reversed row index
     int64_t kout = 0, mult = 1;
-    if (a.levels > 1 && g0 < total_rows) {
-        int64_t r = g0 % a.rows_per_pulse;
+    {
+        int64_t rr = r;
         int64_t digits[kFftMaxLevels];
         for (int i = a.levels - 2; i >= 0; --i) {
-            digits[i] = r % a.len[i];
-            r /= a.len[i];
+            digits[i] = rr & (a.len[i] - 1);
+            rr >>= __ffs(a.len[i]) - 1;
         }
         for (int i = 0; i < a.levels - 1; ++i) {
             kout += digits[i] * mult;
             mult *= a.len[i];
         }
     }
+    // The spectrum is parked in this thread's own LDS slots while the float64 phase is
+    // applied one bin at a time, so the samples are not live across the phase arithmetic.
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        lds[rpad(j + 256 * q)] = v[q];
+#pragma unroll 1
+    for (int q = 0; q < 16; ++q) {
+        const int i = rpad(j + 256 * q);
+        lds[i] = cmul(lds[i], iono_phase(jb, kout + mult * (j + 256 * q), a.n));
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        v[q] = lds[rpad(j + 256 * q)];
+    __syncthreads();
+    row4096<+1>(v, lds, j, a.tw4096);
+    float2 *dst = jb.y + (r << 12);
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        dst[j + 256 * q] = make_float2(v[q].x * a.scale, v[q].y * a.scale);
+}
+
+// Single-level transform of n = L < 4096 points: the tile holds C = 4096/L whole pulses.
+__global__ void __launch_bounds__(kFftThreads) k_fft_rows_iono(RowArgs a)
+{
+    __shared__ float2 lds[kLdsSlots];
+    const int tid = threadIdx.x;
+    const int L = 1 << a.log2L, C = 1 << a.log2C;
+    const int g0 = blockIdx.x * C;  // first pulse of the tile
     for (int e = tid; e < kFftTile; e += kFftThreads) {
         const int c = e >> a.log2L, l = e & (L - 1);
-        const int64_t g = g0 + c;
-        if (g >= total_rows)
+        const int g = g0 + c;
+        float2 v = make_float2(0.f, 0.f);
+        if (g < a.njobs) {
+            const IonoJob jb = a.jobs ? a.jobs[g] : a.inl;
+            v = (a.from_x ? jb.x : jb.y)[l];
+        }
+        lds[tidx(c, l, a.log2L, a.log2C, true)] = v;
+    }
+    __syncthreads();
+    fft_tile<-1>(lds, a.log2L, a.log2C, true, a.tw4096, tid);
+    for (int e = tid; e < kFftTile; e += kFftThreads) {
+        const int c = e >> a.log2L, l = e & (L - 1);
+        const int g = g0 + c;
+        if (g >= a.njobs)
             continue;
-        const int p = (int)(g / a.rows_per_pulse);
-        const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
+        const IonoJob jb = a.jobs ? a.jobs[g] : a.inl;
         const int idx = tidx(c, l, a.log2L, a.log2C, true);
-        lds[idx] = cmul(lds[idx], iono_phase(jb, kout + mult * l, a.n));
+        lds[idx] = cmul(lds[idx], iono_phase(jb, l, a.n));
     }
     __syncthreads();
     fft_tile<+1>(lds, a.log2L, a.log2C, true, a.tw4096, tid);
     for (int e = tid; e < kFftTile; e += kFftThreads) {
         const int c = e >> a.log2L, l = e & (L - 1);
-        const int64_t g = g0 + c;
-        if (g >= total_rows)
+        const int g = g0 + c;
+        if (g >= a.njobs)
             continue;
-        const int p = (int)(g / a.rows_per_pulse);
-        const int64_t r = g - (int64_t)p * a.rows_per_pulse;
-        const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
+        const IonoJob jb = a.jobs ? a.jobs[g] : a.inl;
         float2 v = lds[tidx(c, l, a.log2L, a.log2C, true)];
         v.x *= a.scale;
         v.y *= a.scale;
-        jb.y[r * L + l] = v;
+        jb.y[l] = v;
     }
 }
 
@@ -380,7 +498,11 @@ std::vector<float2> twiddle_table(int64_t count, int64_t step, int64_t m)
 hipError_t make_base_twiddles(float2 **dev)
 {
     std::vector<void *> unused;
-    return upload_table(twiddle_table(kFftTile, 1, kFftTile), dev, unused);
+    std::vector<float2> t = twiddle_table(kFftTile, 1, kFftTile);
+    t.resize(2 * kFftTile);
+    for (int q = 0; q < kFftTile; ++q)
+        t[kFftTile + q] = make_float2(t[q].x, -t[q].y);
+    return upload_table(t, dev, unused);
 }
 
 hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs)
@@ -447,25 +569,39 @@ hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob 
         a.inl = inl;
         a.njobs = njobs;
         a.log2L = plan.log2len[i];
-        a.log2C = ilog2(kFftTile) - plan.log2len[i];
         a.inner = inner[i];
-        a.outer = outer[i];
-        a.col_blocks = inner[i] >> a.log2C;
         a.tw4096 = tw4096;
         a.tw_lo = plan.tw_lo[i];
         a.tw_hi = plan.tw_hi[i];
-        a.nsub = (int64_t)plan.len[i] * inner[i];
         a.from_x = (!inverse && i == 0);
         a.scale = (inverse && i == 0) ? inv_n : 1.0f;
-        const int64_t blocks = (int64_t)njobs * a.outer * a.col_blocks;
+        const bool reg = plan.len[i] <= 16;
+        // columns per block: 256 threads x 1 column (register kernel) or the LDS tile width
+        a.log2C = reg ? 8 : ilog2(kFftTile) - plan.log2len[i];
+        a.log2cb = ilog2(inner[i]) - a.log2C;
+        a.log2pp = ilog2(outer[i]) + a.log2cb;
+        const int64_t blocks = (int64_t)njobs << a.log2pp;
         if (blocks > 0x7fffffff)
             return hipErrorInvalidValue;
         if (prof)
             prof->begin(inverse ? kKFftStridedInv : kKFftStridedFwd, s);
-        if (inverse)
-            hipLaunchKernelGGL(k_fft_strided<+1>, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);
-        else
-            hipLaunchKernelGGL(k_fft_strided<-1>, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);
+        const dim3 grid((unsigned)blocks), blk(kFftThreads);
+        if (reg) {
+            switch (plan.len[i] * (inverse ? 1 : -1)) {
+            case -2: hipLaunchKernelGGL((k_fft_strided_reg<2, -1>), grid, blk, 0, s, a); break;
+            case -4: hipLaunchKernelGGL((k_fft_strided_reg<4, -1>), grid, blk, 0, s, a); break;
+            case -8: hipLaunchKernelGGL((k_fft_strided_reg<8, -1>), grid, blk, 0, s, a); break;
+            case -16: hipLaunchKernelGGL((k_fft_strided_reg<16, -1>), grid, blk, 0, s, a); break;
+            case 2: hipLaunchKernelGGL((k_fft_strided_reg<2, 1>), grid, blk, 0, s, a); break;
+            case 4: hipLaunchKernelGGL((k_fft_strided_reg<4, 1>), grid, blk, 0, s, a); break;
+            case 8: hipLaunchKernelGGL((k_fft_strided_reg<8, 1>), grid, blk, 0, s, a); break;
+            default: hipLaunchKernelGGL((k_fft_strided_reg<16, 1>), grid, blk, 0, s, a); break;
+            }
+        } else if (inverse) {
+            hipLaunchKernelGGL(k_fft_strided<+1>, grid, blk, 0, s, a);
+        } else {
+            hipLaunchKernelGGL(k_fft_strided<-1>, grid, blk, 0, s, a);
+        }
         const hipError_t e = hipGetLastError();
         if (prof)
             prof->end(s);
@@ -483,7 +619,7 @@ hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob 
         a.njobs = njobs;
         a.log2L = plan.log2len[d - 1];
         a.log2C = ilog2(kFftTile) - a.log2L;
-        a.rows_per_pulse = plan.n >> a.log2L;
+        a.log2rpp = ilog2(plan.n) - a.log2L;
         a.n = plan.n;
         a.levels = d;
         for (int i = 0; i < kFftMaxLevels; ++i)
@@ -491,13 +627,17 @@ hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob 
         a.tw4096 = tw4096;
         a.from_x = (d == 1);
         a.scale = (d == 1) ? inv_n : 1.0f;
-        const int64_t rows = (int64_t)njobs * a.rows_per_pulse;
-        const int64_t blocks = (rows + (1 << a.log2C) - 1) >> a.log2C;
-        if (blocks > 0x7fffffff)
-            return hipErrorInvalidValue;
         if (prof)
             prof->begin(kKFftRowsIono, s);
-        hipLaunchKernelGGL(k_fft_rows_iono, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);
+        if (a.log2L == 12) {
+            const int64_t blocks = (int64_t)njobs << a.log2rpp;
+            if (blocks > 0x7fffffff)
+                return hipErrorInvalidValue;
+            hipLaunchKernelGGL(k_fft_row4096_iono, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);
+        } else {
+            const int64_t blocks = ((int64_t)njobs + (1 << a.log2C) - 1) >> a.log2C;
+            hipLaunchKernelGGL(k_fft_rows_iono, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);
+        }
         hipError_t e = hipGetLastError();
         if (prof)
             prof->end(s);

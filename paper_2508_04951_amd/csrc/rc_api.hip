@@ -137,6 +137,19 @@ double phase_numerator(double tec, int32_t direction)
 
 rc::Profiler *prof_of(rc_context ctx) { return ctx->prof.on ? &ctx->prof : nullptr; }
 
+enum class SincPath { Mfma, Fast, Direct };
+
+SincPath sinc_path(rc_context ctx, double alpha, const rc_sinc &k)
+{
+    if (ctx->sinc_engine == RC_SINC_DIRECT)
+        return SincPath::Direct;
+    if (ctx->sinc_engine == RC_SINC_AUTO && rc::sinc_mfma_eligible(alpha, k))
+        return SincPath::Mfma;
+    if (rc::sinc_fast_eligible(alpha, k))
+        return SincPath::Fast;
+    return SincPath::Direct;
+}
+
 int64_t taps_per_output(const rc_sinc &k, int64_t n_in)
 {
     if (k.half_width == 0)
@@ -272,10 +285,16 @@ rc_status correct_doppler(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 
     const SincJob job{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y), n_in, n_out, alpha};
     const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
     hipError_t e;
-    if (rc::sinc_fast_eligible(alpha, *k))
+    switch (sinc_path(ctx, alpha, *k)) {
+    case SincPath::Mfma:
+        e = rc::launch_sinc_mfma(nullptr, &job, 1, n_out, k->half_width, kp, s, prof_of(ctx));
+        break;
+    case SincPath::Fast:
         e = rc::launch_sinc_fast(nullptr, &job, 1, n_out, k->half_width, kp, s, prof_of(ctx));
-    else
+        break;
+    default:
         e = rc::launch_sinc_direct(nullptr, &job, 1, n_out, *k, kp, taps_per_output(*k, n_in), s, prof_of(ctx));
+    }
     if (e != hipSuccess)
         return device_fail(ctx, e, "correct_doppler launch");
     return RC_OK;
@@ -376,15 +395,19 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
 
     // Group the work: fast-path Doppler jobs, generic Doppler jobs, plain copies, and the
     // ionospheric jobs by transform length (one launch sequence per length).
-    std::vector<SincJob> fast, direct;
-    int64_t fast_max = 0, direct_max = 0, direct_taps = 0;
+    std::vector<SincJob> mfma, fast, direct;
+    int64_t mfma_max = 0, fast_max = 0, direct_max = 0, direct_taps = 0;
     std::map<int64_t, std::vector<IonoJob>> iono;
     std::vector<int32_t> copies;
     for (int32_t i = 0; i < count; ++i) {
         const rc_pulse &p = pulses[i];
         if (p.flags & RC_DO_DOPPLER) {
             const SincJob j{xb + p.off_in, yb + p.off_out, p.n_in, p.n_out, p.alpha};
-            if (rc::sinc_fast_eligible(p.alpha, *k)) {
+            const SincPath path = sinc_path(ctx, p.alpha, *k);
+            if (path == SincPath::Mfma) {
+                mfma.push_back(j);
+                mfma_max = std::max(mfma_max, p.n_out);
+            } else if (path == SincPath::Fast) {
                 fast.push_back(j);
                 fast_max = std::max(fast_max, p.n_out);
             } else {
@@ -401,7 +424,7 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
                                             p.carrier_hz, p.fs_hz});
         }
     }
-    if (fast.size() > 65535 || direct.size() > 65535)
+    if (mfma.size() > 65535 || fast.size() > 65535 || direct.size() > 65535)
         return fail(ctx, RC_ERR_UNSUPPORTED, "more than 65535 pulses of one kind in a batch");
     for (auto &kv : iono) {
         const FftPlan *plan = nullptr;
@@ -418,6 +441,7 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
         std::memcpy(blob.data() + off, p, bytes);
         return off;
     };
+    const size_t off_mfma = mfma.empty() ? 0 : append(mfma.data(), mfma.size() * sizeof(SincJob));
     const size_t off_fast = fast.empty() ? 0 : append(fast.data(), fast.size() * sizeof(SincJob));
     const size_t off_direct = direct.empty() ? 0 : append(direct.data(), direct.size() * sizeof(SincJob));
     std::vector<size_t> off_iono;
@@ -438,7 +462,10 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
             return device_fail(ctx, e, "copy");
     }
     const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
-    if (!fast.empty())
+    if (!mfma.empty())
+        e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc + off_mfma), nullptr, (int)mfma.size(),
+                                 mfma_max, k->half_width, kp, s, prof_of(ctx));
+    if (e == hipSuccess && !fast.empty())
         e = rc::launch_sinc_fast(reinterpret_cast<const SincJob *>(devc + off_fast), nullptr, (int)fast.size(),
                                  fast_max, k->half_width, kp, s, prof_of(ctx));
     if (e == hipSuccess && !direct.empty())
@@ -463,6 +490,17 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
     }
     if (!blob.empty())
         return mark_descriptors_used(ctx, s);
+    return RC_OK;
+}
+
+rc_status rc_set_sinc_engine(rc_context ctx, int32_t engine)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    if (engine != RC_SINC_AUTO && engine != RC_SINC_VALU && engine != RC_SINC_DIRECT)
+        return fail(ctx, RC_ERR_INVALID_ARG, "unknown sinc engine");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->sinc_engine = engine;
     return RC_OK;
 }
 
@@ -502,7 +540,7 @@ rc_status rc_profile_read(rc_context ctx, const char *kernel, double *total_ms, 
 namespace rc {
 
 const char *const kKernelNames[kKGroups] = {"k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd",
-                                            "k_fft_rows_iono", "k_fft_strided_inv"};
+                                            "k_fft_rows_iono", "k_fft_strided_inv", "k_sinc_mfma"};
 
 hipEvent_t Profiler::take()
 {

@@ -14,7 +14,15 @@
 namespace rc {
 
 // Optional kernel timing: while `on`, each launch is bracketed by two HIP events on its stream.
-enum KernelGroup { kKSincFast = 0, kKSincDirect, kKFftStridedFwd, kKFftRowsIono, kKFftStridedInv, kKGroups };
+enum KernelGroup {
+    kKSincFast = 0,
+    kKSincDirect,
+    kKFftStridedFwd,
+    kKFftRowsIono,
+    kKFftStridedInv,
+    kKSincMfma,
+    kKGroups
+};
 extern const char *const kKernelNames[kKGroups];
 
 struct Profiler {
@@ -75,6 +83,18 @@ constexpr int kSincWgOut = 4 * kSincWaveOut;
 constexpr double kSincFastMaxEps = 1.0e-4;
 
 bool sinc_fast_eligible(double alpha, const rc_sinc &k);
+
+// Matrix-core path (Kaiser, H = 64 or 128): a 1024-output workgroup shares one cubic drift
+// polynomial, so |alpha - 1| * 511.5 must stay below ~0.031 samples.
+constexpr double kSincMfmaMaxEps = 6.0e-5;
+struct MfmaSincConst {
+    double node[4];   // Chebyshev nodes of [-1, 1]
+    double vinv[16];  // inverse Vandermonde matrix: a_r = sum_i vinv[4 r + i] h(node_i)
+};
+bool sinc_mfma_eligible(double alpha, const rc_sinc &k);
+hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, int njobs,
+                            int64_t max_out, int half_width, const KaiserPoly &kp,
+                            hipStream_t s, Profiler *prof);
 KaiserPoly make_kaiser_poly(double beta);
 size_t sinc_fast_lds_bytes(int half_width);
 
@@ -119,7 +139,7 @@ struct FftPlan {
 };
 
 hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs);
-hipError_t make_base_twiddles(float2 **dev);  // exp(-2 pi i q / 4096), q < 4096
+hipError_t make_base_twiddles(float2 **dev);  // exp(-2 pi i q / 4096), q < 4096, then conjugates
 
 // Full ionospheric operator for njobs pulses of the same length plan.n.
 hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
@@ -142,4 +162,5 @@ struct rc_context_s {
     hipEvent_t desc_done = nullptr;
     bool desc_pending = false;
     rc::Profiler prof;
+    int sinc_engine = 0;  // RC_SINC_AUTO / RC_SINC_VALU / RC_SINC_DIRECT
 };

@@ -100,17 +100,41 @@ def test_doppler_parity_grid(torch, ctx, orc, n, sk):
             assert err <= TOL, (n, n_out, alpha, sk, err)
 
 
-@pytest.mark.parametrize("v", [8000.0, -8000.0, 5000.0, -2500.0, 1e-3, -7.7])
+@pytest.fixture
+def engine(ctx, request):
+    ctx.set_sinc_engine(request.param)
+    yield request.param
+    ctx.set_sinc_engine("auto")
+
+
+@pytest.mark.parametrize("engine", ["auto", "valu"], indirect=True)
+@pytest.mark.parametrize("v", [8000.0, -8000.0, 5000.0, -2500.0, 1e-3, -7.7, 9000.0, 14000.0])
 @pytest.mark.parametrize("hw", [64, 128])
-def test_doppler_fast_path_at_pulse_length(torch, ctx, orc, v, hw):
-    """The windowed fast path at the batch pulse length 65536 (and a ragged tail)."""
+def test_doppler_fast_paths_at_pulse_length(torch, ctx, orc, engine, v, hw):
+    """The matrix-core ("auto") and vector tile kernels at the batch pulse length 65536, with a
+    ragged tail; 9 and 14 km/s leave the matrix-core range and take the vector kernel."""
     x = wf.c2_pulse(3)
     alpha = alpha_exact(v)
-    for n_out in (65536, 65536 - 333):
+    for n_out in (65536, 65536 - 333, 70000):
         y = host(ctx.correct_doppler(dev(torch, x), alpha, sinc(hw), n_out=n_out))
         ref = orc.doppler(x, alpha, hw, "kaiser", 8.0, n_out=n_out)
-        assert rel_l2(y, ref) <= TOL
+        assert rel_l2(y, ref) <= TOL, (engine, v, hw, n_out, rel_l2(y, ref))
         assert np.max(np.abs(y - ref)) <= 20 * TOL * np.sqrt(np.mean(np.abs(ref) ** 2))
+
+
+@pytest.mark.parametrize("engine", ["auto", "valu", "direct"], indirect=True)
+def test_doppler_engines_on_small_and_scaled_inputs(torch, ctx, orc, engine):
+    """Every engine on short pulses (a partial workgroup tile) and on inputs scaled far from
+    unit power (the matrix-core path rescales by powers of two before its fp16 split)."""
+    a = alpha_exact(-7000.0)
+    for n, scale in [(100, 1.0), (1023, 1.0), (1025, 3e-9), (5000, 7e5), (3000, 0.0)]:
+        x = (wf.bandlimited_noise(n, wf.rng_for(110, n)) * np.float32(scale)).astype(np.complex64)
+        y = host(ctx.correct_doppler(dev(torch, x), a, sinc(64)))
+        ref = orc.doppler(x, a, 64, "kaiser", 8.0)
+        if scale == 0.0:
+            assert not np.any(y)
+        else:
+            assert rel_l2(y, ref) <= TOL, (engine, n, scale, rel_l2(y, ref))
 
 
 def test_doppler_long_pulse_sampled(torch, ctx, orc):
