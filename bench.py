@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain elementwise copy of the same buffers (reference for "
+                         "HBM traffic counters)")
     ap.add_argument("--engine", choices=["auto", "valu", "direct"], default="auto",
                     help="resampling engine (auto: matrix cores where eligible)")
     args = ap.parse_args()
@@ -137,6 +140,14 @@ def main():
 
     def step():
         ctx.correct_pulse_batch(xd, yd, desc, sinc)
+
+    if args.copy_calibration:
+        # torch elementwise kernel: reads and writes exactly 16 B per complex sample
+        xf, yf = torch.view_as_real(xd), torch.view_as_real(yd)
+        for _ in range(3):
+            torch.mul(xf, 1.0, out=yf)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 x {xd.numel() * 8 / 2**20:.0f} MiB read + written")
 
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):

@@ -186,14 +186,61 @@ __device__ void fft_tile(float2 *lds, int log2L, int log2C, bool lc, const float
     }
 }
 
-// exp(-/+ 2 pi i q / nsub) from the split tables (q = qh * 4096 + ql).
-__device__ __forceinline__ float2 twiddle(const float2 *__restrict__ lo, const float2 *__restrict__ hi,
-                                          int64_t q, bool conj)
+// exp(S 2 pi i q / M), M = 2^log2M <= 2^24: sincospi of an exact float32 argument.
+template <int S>
+__device__ __forceinline__ float2 unit_root(int64_t q, int log2M)
 {
-    float2 w = cmul(lo[q & (kFftTile - 1)], hi[q >> 12]);
-    if (conj)
-        w.y = -w.y;
-    return w;
+    const float th = (float)(q & ((int64_t(1) << log2M) - 1)) * ldexpf(2.0f, -log2M);
+    float sn, cs;
+    sincospif(th, &sn, &cs);
+    return make_float2(cs, S * sn);
+}
+
+// v[q] *= exp(S 2 pi i q m / M) for q = 1 .. R-1 (M a power of two, M <= 2^24).  The bases
+// exp(S 2 pi i 2^t m / M), t = 0..3, come from sincospi of exact float32 arguments; every other
+// power is a product of at most four bases (error within ~5 ulp).  No table gathers: a table
+// indexed by q m scatters a wave's loads over as many cache lines as it has lanes.
+template <int R, int S>
+__device__ __forceinline__ void twiddle_powers(float2 *v, int64_t m, int log2M)
+{
+    const int64_t mask = (int64_t(1) << log2M) - 1;
+    const float scale = ldexpf(2.0f, -log2M);  // 2 / M, exact
+    float2 b[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if ((1 << t) < R) {
+            const float th = (float)((m << t) & mask) * scale;  // exact: < 2^24 times a power of two
+            float sn, cs;
+            sincospif(th, &sn, &cs);
+            b[t] = make_float2(cs, S * sn);
+        }
+    }
+    float2 w3 = make_float2(1.f, 0.f), w5 = w3, w6 = w3, w7 = w3;
+    if (R > 1) v[1] = cmul(v[1], b[0]);
+    if (R > 2) {
+        v[2] = cmul(v[2], b[1]);
+        w3 = cmul(b[0], b[1]);
+        v[3] = cmul(v[3], w3);
+    }
+    if (R > 4) {
+        v[4] = cmul(v[4], b[2]);
+        w5 = cmul(b[0], b[2]);
+        w6 = cmul(b[1], b[2]);
+        w7 = cmul(w3, b[2]);
+        v[5] = cmul(v[5], w5);
+        v[6] = cmul(v[6], w6);
+        v[7] = cmul(v[7], w7);
+    }
+    if (R > 8) {
+        v[8] = cmul(v[8], b[3]);
+        v[9] = cmul(v[9], cmul(b[0], b[3]));
+        v[10] = cmul(v[10], cmul(b[1], b[3]));
+        v[11] = cmul(v[11], cmul(w3, b[3]));
+        v[12] = cmul(v[12], cmul(b[2], b[3]));
+        v[13] = cmul(v[13], cmul(w5, b[3]));
+        v[14] = cmul(v[14], cmul(w6, b[3]));
+        v[15] = cmul(v[15], cmul(w7, b[3]));
+    }
 }
 
 struct StridedArgs {
@@ -205,7 +252,7 @@ struct StridedArgs {
     int log2cb;             // log2(inner / columns per block)
     int log2pp;             // log2(outer * inner / columns per block): blocks per pulse
     const float2 *tw4096;
-    const float2 *tw_lo, *tw_hi;
+    int log2nsub;           // log2(L * inner)
     bool from_x;            // first pass reads job.x
     float scale;            // applied after an inverse pass (1/n in the last one)
 };
@@ -227,16 +274,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided_reg(StridedArgs a)
 #pragma unroll
     for (int l = 0; l < R; ++l)
         v[l] = src[base + l * a.inner];
-    if (S > 0) {
-#pragma unroll
-        for (int l = 1; l < R; ++l)
-            v[l] = cmul(v[l], twiddle(a.tw_lo, a.tw_hi, (int64_t)l * col, true));
-    }
+    if (S > 0)
+        twiddle_powers<R, +1>(v, col, a.log2nsub);
     dftR<R, S>(v);
     if (S < 0) {
-#pragma unroll
-        for (int l = 1; l < R; ++l)
-            v[l] = cmul(v[l], twiddle(a.tw_lo, a.tw_hi, (int64_t)l * col, false));
+        twiddle_powers<R, -1>(v, col, a.log2nsub);
     } else if (a.scale != 1.0f) {
 #pragma unroll
         for (int l = 0; l < R; ++l) {
@@ -268,10 +310,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(StridedArgs a)
     for (int e = tid; e < kFftTile; e += kFftThreads) {
         const int c = e & (C - 1), l = e >> a.log2C;
         float2 v = src[base + (int64_t)l * a.inner + c];
-        if (S > 0) {  // inverse: conjugate twiddle before the DFT along the level
-            const int64_t q = (int64_t)l * (cb * C + c);  // < L * inner
-            v = cmul(v, twiddle(a.tw_lo, a.tw_hi, q, true));
-        }
+        if (S > 0)  // inverse: conjugate twiddle before the DFT along the level
+            v = cmul(v, unit_root<+1>((int64_t)l * (cb * C + c), a.log2nsub));
         lds[tidx(c, l, a.log2L, a.log2C, false)] = v;
     }
     __syncthreads();
@@ -280,8 +320,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(StridedArgs a)
         const int c = e & (C - 1), l = e >> a.log2C;
         float2 v = lds[tidx(c, l, a.log2L, a.log2C, false)];
         if (S < 0) {  // forward: twiddle after the DFT, k = l, n' = column position
-            const int64_t q = (int64_t)l * (cb * C + c);
-            v = cmul(v, twiddle(a.tw_lo, a.tw_hi, q, false));
+            v = cmul(v, unit_root<-1>((int64_t)l * (cb * C + c), a.log2nsub));
         } else if (a.scale != 1.0f) {
             v.x *= a.scale;
             v.y *= a.scale;
@@ -327,17 +366,6 @@ __device__ __forceinline__ float2 iono_phase(const IonoJob &jb, int64_t k, int64
 // One radix-16 Stockham stage of a 4096-point row held as 16 samples per thread
 // (thread j owns positions j + 256 q).  Ns = 16^stage; the output leaves through LDS,
 // except for the last stage, whose outputs j + 256 q are already in place.
-// tw holds exp(-2 pi i q / 4096) followed by its conjugates: the inverse transform reads the
-// second half, so its loads are not merged with (and kept live from) the forward ones.
-template <int S>
-__device__ __forceinline__ void row_twiddle(float2 *v, int k, int step, const float2 *__restrict__ tw)
-{
-    const float2 *t = S > 0 ? tw + kFftTile : tw;
-#pragma unroll
-    for (int q = 1; q < 16; ++q)
-        v[q] = cmul(v[q], t[(q * k * step) & (kFftTile - 1)]);
-}
-
 __device__ __forceinline__ int rpad(int a) { return a + (a >> 4); }
 
 // Full 4096-point DFT of the thread-distributed row: in v[q] = x[j + 256 q], out v[q] = X[j + 256 q].
@@ -354,7 +382,7 @@ __device__ __forceinline__ void row4096(float2 *v, float2 *lds, int j, const flo
 #pragma unroll
     for (int q = 0; q < 16; ++q)
         v[q] = lds[rpad(j + 256 * q)];
-    row_twiddle<S>(v, j & 15, 16, tw);
+    twiddle_powers<16, S>(v, 16 * (j & 15), 12);
     dftR<16, S>(v);
     __syncthreads();
     const int base = ((j >> 4) << 8) + (j & 15);
@@ -366,7 +394,7 @@ __device__ __forceinline__ void row4096(float2 *v, float2 *lds, int j, const flo
 #pragma unroll
     for (int q = 0; q < 16; ++q)
         v[q] = lds[rpad(j + 256 * q)];
-    row_twiddle<S>(v, j, 1, tw);
+    twiddle_powers<16, S>(v, j, 12);
     dftR<16, S>(v);
     __syncthreads();  // LDS free for the next transform
 }
@@ -498,11 +526,7 @@ std::vector<float2> twiddle_table(int64_t count, int64_t step, int64_t m)
 hipError_t make_base_twiddles(float2 **dev)
 {
     std::vector<void *> unused;
-    std::vector<float2> t = twiddle_table(kFftTile, 1, kFftTile);
-    t.resize(2 * kFftTile);
-    for (int q = 0; q < kFftTile; ++q)
-        t[kFftTile + q] = make_float2(t[q].x, -t[q].y);
-    return upload_table(t, dev, unused);
+    return upload_table(twiddle_table(kFftTile, 1, kFftTile), dev, unused);
 }
 
 hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs)
@@ -510,7 +534,7 @@ hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs)
     plan = FftPlan{};
     plan.n = n;
     const int p = ilog2(n);
-    if ((int64_t(1) << p) != n)
+    if ((int64_t(1) << p) != n || p > 24)  // twiddle arguments stay exact up to 2^24
         return hipErrorInvalidValue;
     if (p <= 12) {
         plan.levels = 1;
@@ -530,18 +554,6 @@ hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs)
     }
     for (int i = 0; i < plan.levels; ++i)
         plan.log2len[i] = ilog2(plan.len[i]);
-    int64_t inner = n;
-    for (int i = 0; i + 1 < plan.levels; ++i) {
-        inner /= plan.len[i];
-        const int64_t nsub = (int64_t)plan.len[i] * inner;
-        hipError_t e = upload_table(twiddle_table(kFftTile, 1, nsub), &plan.tw_lo[i], allocs);
-        if (e != hipSuccess)
-            return e;
-        const int64_t nhi = (nsub + kFftTile - 1) / kFftTile;
-        e = upload_table(twiddle_table(nhi, kFftTile, nsub), &plan.tw_hi[i], allocs);
-        if (e != hipSuccess)
-            return e;
-    }
     return hipSuccess;
 }
 
@@ -571,8 +583,7 @@ hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob 
         a.log2L = plan.log2len[i];
         a.inner = inner[i];
         a.tw4096 = tw4096;
-        a.tw_lo = plan.tw_lo[i];
-        a.tw_hi = plan.tw_hi[i];
+        a.log2nsub = plan.log2len[i] + ilog2(inner[i]);
         a.from_x = (!inverse && i == 0);
         a.scale = (inverse && i == 0) ? inv_n : 1.0f;
         const bool reg = plan.len[i] <= 16;

@@ -128,6 +128,21 @@ rc_status get_plan(rc_context ctx, int64_t n, const FftPlan **out)
     return RC_OK;
 }
 
+rc_status get_mfma_table(rc_context ctx, const rc_sinc &k, const void **out)
+{
+    const auto key = std::make_pair((int)k.half_width, k.kaiser_beta);
+    auto it = ctx->mfma_tables.find(key);
+    if (it == ctx->mfma_tables.end()) {
+        void *t = nullptr;
+        hipError_t e = rc::build_sinc_mfma_table(k.half_width, k.kaiser_beta, &t, ctx->allocs);
+        if (e != hipSuccess)
+            return device_fail(ctx, e, "building the matrix-core weight table");
+        it = ctx->mfma_tables.emplace(key, t).first;
+    }
+    *out = it->second;
+    return RC_OK;
+}
+
 double phase_numerator(double tec, int32_t direction)
 {
     const double k2 = rc_k2_per_tec() * tec;
@@ -286,9 +301,14 @@ rc_status correct_doppler(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 
     const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
     hipError_t e;
     switch (sinc_path(ctx, alpha, *k)) {
-    case SincPath::Mfma:
-        e = rc::launch_sinc_mfma(nullptr, &job, 1, n_out, k->half_width, kp, s, prof_of(ctx));
+    case SincPath::Mfma: {
+        const void *table = nullptr;
+        rc_status ts = get_mfma_table(ctx, *k, &table);
+        if (ts != RC_OK)
+            return ts;
+        e = rc::launch_sinc_mfma(nullptr, &job, 1, n_out, k->half_width, table, s, prof_of(ctx));
         break;
+    }
     case SincPath::Fast:
         e = rc::launch_sinc_fast(nullptr, &job, 1, n_out, k->half_width, kp, s, prof_of(ctx));
         break;
@@ -432,6 +452,12 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
         if (st != RC_OK)
             return st;
     }
+    const void *mfma_table = nullptr;
+    if (!mfma.empty()) {
+        st = get_mfma_table(ctx, *k, &mfma_table);
+        if (st != RC_OK)
+            return st;
+    }
 
     // one descriptor upload: [fast | direct | iono groups...]
     std::vector<char> blob;
@@ -464,7 +490,7 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
     const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
     if (!mfma.empty())
         e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc + off_mfma), nullptr, (int)mfma.size(),
-                                 mfma_max, k->half_width, kp, s, prof_of(ctx));
+                                 mfma_max, k->half_width, mfma_table, s, prof_of(ctx));
     if (e == hipSuccess && !fast.empty())
         e = rc::launch_sinc_fast(reinterpret_cast<const SincJob *>(devc + off_fast), nullptr, (int)fast.size(),
                                  fast_max, k->half_width, kp, s, prof_of(ctx));

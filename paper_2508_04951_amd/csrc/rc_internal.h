@@ -84,17 +84,20 @@ constexpr double kSincFastMaxEps = 1.0e-4;
 
 bool sinc_fast_eligible(double alpha, const rc_sinc &k);
 
-// Matrix-core path (Kaiser, H = 64 or 128): a 1024-output workgroup shares one cubic drift
-// polynomial, so |alpha - 1| * 511.5 must stay below ~0.031 samples.
+// Matrix-core path (Kaiser, H = 64 or 128): a 2048-output workgroup takes its tap weights from
+// a quartic in the drift tabulated on a grid of 129 phases, so |alpha - 1| * 1023.5 must stay
+// below ~0.061 samples.
 constexpr double kSincMfmaMaxEps = 6.0e-5;
 struct MfmaSincConst {
-    double node[4];   // Chebyshev nodes of [-1, 1]
-    double vinv[16];  // inverse Vandermonde matrix: a_r = sum_i vinv[4 r + i] h(node_i)
+    double node[5];   // Chebyshev nodes of [-1, 1]
+    double vinv[25];  // inverse Vandermonde matrix: a_r = sum_i vinv[5 r + i] h(node_i)
 };
 bool sinc_mfma_eligible(double alpha, const rc_sinc &k);
+// Device table of the B fragments for every grid phase (built once per (H, beta)).
+hipError_t build_sinc_mfma_table(int half_width, double beta, void **dev, std::vector<void *> &allocs);
 hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, int njobs,
-                            int64_t max_out, int half_width, const KaiserPoly &kp,
-                            hipStream_t s, Profiler *prof);
+                            int64_t max_out, int half_width, const void *table, hipStream_t s,
+                            Profiler *prof);
 KaiserPoly make_kaiser_poly(double beta);
 size_t sinc_fast_lds_bytes(int half_width);
 
@@ -132,14 +135,10 @@ struct FftPlan {
     int levels = 0;
     int len[kFftMaxLevels] = {0, 0, 0, 0};
     int log2len[kFftMaxLevels] = {0, 0, 0, 0};
-    // Twiddle tables for the strided levels i < levels-1: exp(-2 pi i q / nsub_i),
-    // nsub_i = L_i * prod_{j>i} L_j, split as q = qh * 4096 + ql.
-    float2 *tw_lo[kFftMaxLevels] = {nullptr, nullptr, nullptr, nullptr};  // 4096 entries
-    float2 *tw_hi[kFftMaxLevels] = {nullptr, nullptr, nullptr, nullptr};  // nsub/4096 entries
 };
 
 hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs);
-hipError_t make_base_twiddles(float2 **dev);  // exp(-2 pi i q / 4096), q < 4096, then conjugates
+hipError_t make_base_twiddles(float2 **dev);  // exp(-2 pi i q / 4096), q < 4096
 
 // Full ionospheric operator for njobs pulses of the same length plan.n.
 hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
@@ -154,6 +153,7 @@ struct rc_context_s {
     std::string last_error;
     float2 *tw4096 = nullptr;                  // base twiddles exp(-2 pi i q / 4096)
     std::map<int64_t, rc::FftPlan> plans;      // by transform length
+    std::map<std::pair<int, double>, void *> mfma_tables;  // by (half width, Kaiser beta)
     std::vector<void *> allocs;                // every device allocation owned
     // descriptor staging for batches: pinned host + device, guarded by `desc_done`
     void *desc_host = nullptr;

@@ -1,21 +1,27 @@
 // sinc_mfma.hip -- the windowed-sinc tap sum of Eq (17) (Kaiser taper, Sec. III-B) as a
 // matrix product on the gfx950 matrix cores.
 //
-// A 1024-output workgroup tile shares one integer shift S and one drift polynomial: every
-// output m of the tile sits at t = alpha m = m + S + sigma_c + D z_m with |z_m| <= 1 and
-// D = |alpha - 1| * 511.5, so its weights are h(sigma_c + D z - k) ~= sum_r a_r[k] z^r,
-// a cubic in z interpolated in float64 at four Chebyshev nodes (tap error ~1e-7 for
-// |alpha - 1| <= 6e-5).  Then
-//     y[m] = sum_r z_m^r Z_r[m],   Z_r[m] = sum_k x[m + S + k] a_r[k],  k = -H .. H,
-// and for a 256-output wave tile m = m0 + 16 i + u the contraction is a GEMM
+// A 2048-output workgroup tile shares one integer shift S: output m of the tile sits at
+// t = alpha m = m + S + sigma_m with sigma_m = sigma_c + eps (m - m_c), eps = alpha - 1, and
+// |sigma_m - sigma_c| <= |eps| * 1023.5 <= 0.0614 for |eps| <= 6e-5.  Its tap weights
+// h(sigma_m - k), k = -H .. H, are taken from a quartic in z = (sigma_m - sigma_p) / delta_max
+// around the nearest point sigma_p = p / 128 of a phase grid (|z| <= 1, delta_max = 0.0654):
+//     h(sigma_p + delta_max z - k) ~= sum_r a_{p,r}[k] z^r,
+// interpolated in float64 at five Chebyshev nodes (tap error ~3e-8).  The 129 grid phases are
+// tabulated once per (H, beta) by k_sinc_table, already split into fp16 hi/lo and laid out as
+// matrix-core B fragments.  Then
+//     y[m] = sum_r z_m^r Z_r[m],   Z_r[m] = sum_k x[m + S + k] a_{p,r}[k],
+// and for a 256-output sub-tile m = m0 + 16 i + u the contraction is a GEMM
 //     Z_r[i][u] = sum_kappa X[i][kappa] B_r[kappa][u],
 //     X[i][kappa] = x[m0 + 16 i + S - H + kappa]   (Hankel: 8-sample aligned runs per lane),
-//     B_r[kappa][u] = a_r[kappa - u - H]           (the column shift u lives in B).
+//     B_r[kappa][u] = a_{p,r}[kappa - u - H]        (the column shift u lives in B).
 // kappa runs over 2H + 16 taps rounded up to whole 32-wide MFMA steps.  Both operands are split
 // into float16 hi + lo parts after exact power-of-two scaling, and each order and component
 // accumulates hi*hi + hi*lo + lo*hi in float32 (v_mfma_f32_16x16x32_f16): about 22 bits per
-// product.  The cubic in z is applied to the four float32 accumulators per output at the end.
+// product.  The four waves each run two sub-tiles, together, against the B block copied once
+// into LDS.
 #include <cmath>
+#include <vector>
 
 #include "rc_internal.h"
 
@@ -23,11 +29,17 @@ namespace rc {
 namespace {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMfOut = 1024;       // outputs per workgroup
-constexpr int kMfOrders = 4;       // cubic in the drift
-constexpr int kCoefExp = 12;       // coefficients are scaled by 2^12 before the fp16 split
+constexpr int kMfOut = 2048;           // outputs per workgroup (one phase-grid point)
+constexpr int kMfSubs = kMfOut / 256;  // 256-output sub-tiles: two per wave
+constexpr int kMfOrders = 5;           // quartic in the drift
+constexpr int kCoefExp = 12;           // coefficients are scaled by 2^12 before the fp16 split
+constexpr double kMfHalf = 0.5 * (kMfOut - 1);  // 1023.5: half-width of the tile in outputs
+constexpr int kPhases = 128;                    // phase grid points per sample
+constexpr int kPhaseRows = kPhases + 1;         // sigma_p = p / 128, p = -64 .. 64
+constexpr double kDeltaMax = 0.0654;            // >= 6e-5 * 1023.5 + 1 / 256
 
 template <int H>
 struct MfGeom {
@@ -35,35 +47,106 @@ struct MfGeom {
     static constexpr int kext = ((2 * H + 16) + 31) / 32 * 32;
     static constexpr int ksteps = kext / 32;
     static constexpr int span = kMfOut + kext;                 // staged samples
-    static constexpr int spt = (span + 255) / 256;            // staged samples per thread
-    static constexpr int a_off = 0;                             // 4 fp16 arrays of `span`
-    static constexpr int b_off = 4 * span * 2;                  // ksteps x orders x {hi,lo} x 1 KiB
-    static constexpr int c_off = b_off + ksteps * kMfOrders * 2 * 1024;  // float a_r[k]
-    static constexpr int m_off = c_off + kMfOrders * ntap * 4;          // 4 floats: wave maxima
+    static constexpr int spp = (span + 511) / 512;            // staged sample pairs per thread
+    static constexpr int rowlen = kext + 32;                   // padded coefficient row (halves)
+    static constexpr int node_iters = (ntap + 47) / 48;       // 12 taps x 5 nodes per wave
+    static constexpr int bbytes = ksteps * kMfOrders * 2 * 1024;  // B fragments of one phase
+    // main kernel LDS: B block, then 4 fp16 arrays of `span`, then 4 floats (wave maxima)
+    static constexpr int a_off = bbytes;
+    static constexpr int m_off = a_off + ((4 * span * 2) + 15) / 16 * 16;
     static constexpr int bytes = m_off + 16;
+    // table kernel LDS: coefficient rows [order][part][rowlen]
+    static constexpr int rows_bytes = kMfOrders * 2 * rowlen * 2;
 };
 
+// The Kaiser series with a fixed number of terms NT >= kp.n (terms past kp.n are zero).
+constexpr int kMfKaiserTerms = 32;
+
+template <int NT>
 __device__ __forceinline__ double kaiser_at_m(const KaiserPoly &kp, double x)
 {
     const double s = 1.0 - x * x;
-    double acc = kp.c[kp.n - 1];
-    for (int j = kp.n - 2; j >= 0; --j)
+    double acc = kp.c[NT - 1];
+#pragma unroll
+    for (int j = NT - 2; j >= 0; --j)
         acc = fma(acc, s, kp.c[j]);
     return acc;
 }
 
+// One workgroup per grid phase p: the quartic of every tap (float64 at the five Chebyshev
+// nodes of [-delta_max, delta_max]), split into fp16 hi/lo, arranged as B fragments:
+// block (s, r, part) holds, for lane l, the 8 halves B_r[32 s + 8 (l / 16) + j][l % 16].
+template <int H, int NT>
+__global__ void __launch_bounds__(256) k_sinc_table(KaiserPoly kp, MfmaSincConst mc, unsigned char *table)
+{
+    using G = MfGeom<H>;
+    __shared__ unsigned short rows[G::rows_bytes / 2];  // fp16 bit patterns, row pos 16 + t = tap t
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const double sp = (double)((int)blockIdx.x - kPhases / 2) / kPhases;
+    const int grp = lane / 5, node = lane - 5 * grp;
+    const bool active = grp < 12;
+    const int nd = active ? node : 0;
+    const double un = sp + kDeltaMax * mc.node[nd];  // node position relative to tap 0
+    const double sn = sinpi(un);
+    const float cscale = ldexpf(1.0f, kCoefExp);
+    for (int it = 0; it < G::node_iters; ++it) {
+        const int t = 48 * it + 12 * wave + grp;
+        const int k = t - H;
+        double h = 0.0;
+        const double u = un - (double)k;
+        if (active && t < G::ntap && fabs(u) < (double)H) {
+            const double sgn = (k & 1) ? -sn : sn;
+            h = (u == 0.0 ? 1.0 : sgn / (kPi * u)) * kaiser_at_m<NT>(kp, u / (double)H);
+        }
+        double a = 0.0;
+#pragma unroll
+        for (int i = 0; i < kMfOrders; ++i)
+            a = fma(mc.vinv[nd * kMfOrders + i], __shfl(h, active ? 5 * grp + i : lane, 64), a);
+        if (active && t < G::ntap) {
+            const float c = (float)a * cscale;
+            const _Float16 ch = (_Float16)c;
+            const _Float16 cl = (_Float16)(c - (float)ch);
+            rows[(node * 2 + 0) * G::rowlen + 16 + t] = __builtin_bit_cast(unsigned short, ch);
+            rows[(node * 2 + 1) * G::rowlen + 16 + t] = __builtin_bit_cast(unsigned short, cl);
+        }
+    }
+    for (int p = tid; p < kMfOrders * 2 * G::rowlen; p += 256) {
+        const int pos = p % G::rowlen;
+        if (pos < 16 || pos >= 16 + G::ntap)
+            rows[p] = 0;
+    }
+    __syncthreads();
+    unsigned char *out = table + (size_t)blockIdx.x * G::bbytes;
+    for (int id = tid; id < G::ksteps * kMfOrders * 2 * 64; id += 256) {
+        const int l = id & 63, blk = id >> 6;  // blk = (s * orders + r) * 2 + part
+        const int part = blk & 1, r = (blk >> 1) % kMfOrders, s = (blk >> 1) / kMfOrders;
+        const int u = l & 15;
+        const int o = 16 + 32 * s + 8 * (l >> 4) - u;  // first half of the fragment in the row
+        uint4 f;
+        unsigned w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            w[j] = (unsigned)rows[(r * 2 + part) * G::rowlen + o + 2 * j] |
+                   ((unsigned)rows[(r * 2 + part) * G::rowlen + o + 2 * j + 1] << 16);
+        f.x = w[0];
+        f.y = w[1];
+        f.z = w[2];
+        f.w = w[3];
+        reinterpret_cast<uint4 *>(out + blk * 1024)[l] = f;
+    }
+}
+
 template <int H>
 __global__ void __launch_bounds__(256)
-k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, KaiserPoly kp, MfmaSincConst mc)
+k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const unsigned char *__restrict__ table)
 {
     using G = MfGeom<H>;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    unsigned char *bsm = smem;
     _Float16 *a_rh = reinterpret_cast<_Float16 *>(smem + G::a_off);
     _Float16 *a_rl = a_rh + G::span;
     _Float16 *a_ih = a_rl + G::span;
     _Float16 *a_il = a_ih + G::span;
-    unsigned char *bsm = smem + G::b_off;
-    float *coef = reinterpret_cast<float *>(smem + G::c_off);
     float *wmax = reinterpret_cast<float *>(smem + G::m_off);
 
     const SincJob jb = jobs ? jobs[blockIdx.y] : inl;
@@ -72,125 +155,102 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, KaiserPoly kp, MfmaSi
         return;  // uniform over the workgroup
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const double alpha = jb.alpha, eps = alpha - 1.0;
-    const double mcen = (double)M0 + 511.5;
+    const double mcen = (double)M0 + kMfHalf;
     const double Sd = rint(eps * mcen);
     const int64_t S = (int64_t)Sd;
-    const double sc = eps * mcen - Sd;         // sigma at the tile centre
-    double D = fabs(eps) * 511.5;
-    if (D < 1e-6)
-        D = 1e-6;
-    const int64_t lo = M0 + S - H;             // first staged sample
+    const double sc = eps * mcen - Sd;  // sigma at the tile centre, in [-1/2, 1/2]
+    int p = (int)rint(sc * kPhases);
+    p = p < -kPhases / 2 ? -kPhases / 2 : (p > kPhases / 2 ? kPhases / 2 : p);
+    const int64_t lo = M0 + S - H;      // first staged sample
 
-    // 1) stage the input span, find its largest component for the power-of-two scaling
-    float2 xv[G::spt];
+    // 1) copy this phase's B fragments into LDS (16 B per thread and step)
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(table + (size_t)(p + kPhases / 2) * G::bbytes);
+        uint4 *dst = reinterpret_cast<uint4 *>(bsm);
+        for (int i = tid; i < G::bbytes / 16; i += 256)
+            dst[i] = src[i];
+    }
+    // 2) stage the input span (two samples per thread and step), find its largest component
+    float2 xv[G::spp][2];
     float mx = 0.f;
+    const bool whole = lo >= 0 && lo + G::span <= jb.n_in;  // no sample of the span is outside x
+    const float2 *xs = jb.x + lo;
 #pragma unroll
-    for (int q = 0; q < G::spt; ++q) {
-        const int e = tid + 256 * q;
-        const int64_t pos = lo + e;
-        float2 v = make_float2(0.f, 0.f);
-        if (e < G::span && pos >= 0 && pos < jb.n_in)
-            v = jb.x[pos];
-        xv[q] = v;
-        mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    for (int q = 0; q < G::spp; ++q) {
+        const int e = 2 * tid + 512 * q;
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+            float2 v = make_float2(0.f, 0.f);
+            if (e + h2 < G::span && (whole || (lo + e + h2 >= 0 && lo + e + h2 < jb.n_in)))
+                v = xs[e + h2];
+            xv[q][h2] = v;
+            mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+        }
     }
     for (int o = 32; o > 0; o >>= 1)
         mx = fmaxf(mx, __shfl_xor(mx, o, 64));
     if (lane == 0)
         wmax[wave] = mx;
-
-    // 2) drift polynomial a_r[k] of every tap (float64 at 4 Chebyshev nodes, then V^-1)
-    {
-        double sn[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            sn[i] = sinpi(sc + D * mc.node[i]);
-        const double inv_h = 1.0 / (double)H;
-        const float cscale = ldexpf(1.0f, kCoefExp);
-        for (int t = tid; t < G::ntap; t += 256) {
-            const int k = t - H;
-            double hv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const double u = (sc + D * mc.node[i]) - (double)k;
-                double h = 0.0;
-                if (fabs(u) < (double)H) {
-                    const double s = (k & 1) ? -sn[i] : sn[i];
-                    h = (u == 0.0 ? 1.0 : s / (kPi * u)) * kaiser_at_m(kp, u * inv_h);
-                }
-                hv[i] = h;
-            }
-#pragma unroll
-            for (int r = 0; r < kMfOrders; ++r) {
-                double a = 0.0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    a = fma(mc.vinv[r * 4 + i], hv[i], a);
-                coef[r * G::ntap + t] = (float)a * cscale;
-            }
-        }
-    }
     __syncthreads();
 
-    // 3) scale and split the staged samples into fp16 hi/lo arrays
-    float wm = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    // 3) scale by a power of two (largest component in [2^10, 2^11)) and split into fp16 hi/lo
+    const float wm = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
     int xe = 0;
     if (wm > 0.f) {
         int E;
         frexpf(wm, &E);  // wm = f 2^E, f in [0.5, 1)
-        xe = 11 - E;     // scaled maximum in [2^10, 2^11)
+        xe = 11 - E;
     }
+    const float xs2 = ldexpf(1.0f, xe);
 #pragma unroll
-    for (int q = 0; q < G::spt; ++q) {
-        const int e = tid + 256 * q;
-        if (e < G::span) {
-            const float re = ldexpf(xv[q].x, xe), im = ldexpf(xv[q].y, xe);
-            const _Float16 rh = (_Float16)re, ih = (_Float16)im;
-            a_rh[e] = rh;
-            a_rl[e] = (_Float16)(re - (float)rh);
-            a_ih[e] = ih;
-            a_il[e] = (_Float16)(im - (float)ih);
+    for (int q = 0; q < G::spp; ++q) {
+        const int e = 2 * tid + 512 * q;
+        if (e < G::span) {  // span is even: a pair is either wholly inside or outside
+            const float r0 = xv[q][0].x * xs2, r1 = xv[q][1].x * xs2;
+            const float i0 = xv[q][0].y * xs2, i1 = xv[q][1].y * xs2;
+            const half2v rh = {(_Float16)r0, (_Float16)r1};
+            const half2v ih = {(_Float16)i0, (_Float16)i1};
+            const half2v rl = {(_Float16)(r0 - (float)rh[0]), (_Float16)(r1 - (float)rh[1])};
+            const half2v il = {(_Float16)(i0 - (float)ih[0]), (_Float16)(i1 - (float)ih[1])};
+            *reinterpret_cast<half2v *>(a_rh + e) = rh;
+            *reinterpret_cast<half2v *>(a_rl + e) = rl;
+            *reinterpret_cast<half2v *>(a_ih + e) = ih;
+            *reinterpret_cast<half2v *>(a_il + e) = il;
         }
-    }
-    // 4) B fragments in lane order: block (s, r, part) holds, for lane l, the 8 values
-    //    B_r[32 s + 8 (l / 16) + j][l % 16], j < 8, i.e. a_r[kappa - u] (tap index kappa - u)
-    for (int id = tid; id < G::ksteps * kMfOrders * 64; id += 256) {
-        const int l = id & 63;
-        const int r = (id >> 6) % kMfOrders;
-        const int s = (id >> 6) / kMfOrders;
-        const int u = l & 15;
-        half8 hi, lo8;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int kk = 32 * s + 8 * (l >> 4) + j - u;  // tap index 0 .. 2H
-            const float c = (kk >= 0 && kk < G::ntap) ? coef[r * G::ntap + kk] : 0.f;
-            const _Float16 ch = (_Float16)c;
-            hi[j] = ch;
-            lo8[j] = (_Float16)(c - (float)ch);
-        }
-        half8 *blk = reinterpret_cast<half8 *>(bsm + ((s * kMfOrders + r) * 2) * 1024);
-        blk[l] = hi;
-        blk[64 + l] = lo8;
     }
     __syncthreads();
 
-    const int64_t m0 = M0 + 256 * wave;
-    if (m0 >= jb.n_out)
-        return;  // no barrier follows
+    const float unscale = ldexpf(1.0f, -(xe + kCoefExp));
+    // z_m = (sigma_m - sigma_p) / delta_max = z_c + (m - mcen) eps / delta_max
+    const float zc = (float)((sc - (double)p / kPhases) / kDeltaMax);
+    const float zstep = (float)(eps / kDeltaMax);
+    const float sc32 = (float)sc;
+    const float e32 = (float)eps;
 
-    // 5) the GEMM: 8 accumulators (4 orders x re/im), 24 MFMAs per 32-tap step
-    floatx4 acc[kMfOrders][2];
+    // 4) the GEMM.  Wave w owns sub-tiles w and w + 4 and runs them together: each B fragment
+    //    is read from LDS once per 32-tap step for both, and the 60 MFMAs of a step touch 20
+    //    accumulators (2 sub-tiles x 5 orders x re/im) in an order that puts 20 independent
+    //    MFMAs between two that update the same accumulator.
+    if (M0 + 256 * wave >= jb.n_out)
+        return;  // no barrier follows; sub-tile w + 4 starts later still
+    floatx4 acc[2][kMfOrders][2];
 #pragma unroll
-    for (int r = 0; r < kMfOrders; ++r)
-        acc[r][0] = acc[r][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < kMfOrders; ++r)
+            acc[t][r][0] = acc[t][r][1] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int arow = 256 * wave + 16 * (lane & 15) + 8 * (lane >> 4);
 #pragma unroll
     for (int s = 0; s < G::ksteps; ++s) {
-        const int e = arow + 32 * s;
-        const half8 xrh = *reinterpret_cast<const half8 *>(a_rh + e);
-        const half8 xrl = *reinterpret_cast<const half8 *>(a_rl + e);
-        const half8 xih = *reinterpret_cast<const half8 *>(a_ih + e);
-        const half8 xil = *reinterpret_cast<const half8 *>(a_il + e);
+        half8 xh[2][2], xl[2][2];  // [sub-tile][re/im]
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int e = arow + 1024 * t + 32 * s;
+            xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
+            xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
+            xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
+            xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
+        }
         half8 bh[kMfOrders], bl[kMfOrders];
 #pragma unroll
         for (int r = 0; r < kMfOrders; ++r) {
@@ -199,103 +259,133 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, KaiserPoly kp, MfmaSi
             bl[r] = blk[64 + lane];
         }
 #pragma unroll
-        for (int r = 0; r < kMfOrders; ++r) {
-            acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xrh, bh[r], acc[r][0], 0, 0, 0);
-            acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xih, bh[r], acc[r][1], 0, 0, 0);
-        }
+        for (int part = 0; part < 3; ++part)  // hi*hi, hi*lo, lo*hi
 #pragma unroll
-        for (int r = 0; r < kMfOrders; ++r) {
-            acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xrh, bl[r], acc[r][0], 0, 0, 0);
-            acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xih, bl[r], acc[r][1], 0, 0, 0);
-        }
+            for (int r = 0; r < kMfOrders; ++r)
 #pragma unroll
-        for (int r = 0; r < kMfOrders; ++r) {
-            acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xrl, bh[r], acc[r][0], 0, 0, 0);
-            acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xil, bh[r], acc[r][1], 0, 0, 0);
-        }
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                            part == 2 ? xl[t][c] : xh[t][c], part == 1 ? bl[r] : bh[r], acc[t][r][c], 0, 0, 0);
     }
 
-    // 6) lane holds Z_r[row 4 (l/16) + j][col l % 16]: output m = m0 + 16 row + col
-    const float unscale = ldexpf(1.0f, -(xe + kCoefExp));
-    const double inv_d = 1.0 / D;
+    // 5) lane holds Z_r[row 4 (l/16) + j][col l % 16] of each sub-tile: output
+    //    m = M0 + 256 sub + 16 row + col.  z is linear in m; the float64 position is recomputed
+    //    only next to an exact sample instant (sigma within 1e-5 of 0), where alpha m may round
+    //    to an integer.
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int64_t m = m0 + 16 * (4 * (lane >> 4) + j) + (lane & 15);
-        if (m >= jb.n_out)
-            continue;
-        const double md = (double)m;
-        const double sig = (__dmul_rn(alpha, md) - md) - Sd;  // exact, as in the direct form
-        float2 out;
-        if (sig == 0.0) {
-            const int64_t src = m + S;
-            out = (src >= 0 && src < jb.n_in) ? jb.x[src] : make_float2(0.f, 0.f);
-        } else {
-            const float z = (float)((sig - sc) * inv_d);
-            float yr = acc[3][0][j], yi = acc[3][1][j];
+    for (int t = 0; t < 2; ++t) {
 #pragma unroll
-            for (int r = 2; r >= 0; --r) {
-                yr = fmaf(yr, z, acc[r][0][j]);
-                yi = fmaf(yi, z, acc[r][1][j]);
+        for (int j = 0; j < 4; ++j) {
+            const int off = 256 * (wave + 4 * t) + 16 * (4 * (lane >> 4) + j) + (lane & 15);  // m - M0
+            const int64_t m = M0 + off;
+            if (m >= jb.n_out)
+                continue;
+            const float dm = (float)off - (float)kMfHalf;
+            const float z = fmaf(dm, zstep, zc);
+            bool exact = false;
+            if (fabsf(fmaf(dm, e32, sc32)) < 1e-5f) {
+                const double md = (double)m;
+                exact = ((__dmul_rn(alpha, md) - md) - Sd) == 0.0;
             }
-            out = make_float2(yr * unscale, yi * unscale);
+            float2 out;
+            if (exact) {
+                const int64_t src = m + S;
+                out = (src >= 0 && src < jb.n_in) ? jb.x[src] : make_float2(0.f, 0.f);
+            } else {
+                float yr = acc[t][kMfOrders - 1][0][j], yi = acc[t][kMfOrders - 1][1][j];
+#pragma unroll
+                for (int r = kMfOrders - 2; r >= 0; --r) {
+                    yr = fmaf(yr, z, acc[t][r][0][j]);
+                    yi = fmaf(yi, z, acc[t][r][1][j]);
+                }
+                out = make_float2(yr * unscale, yi * unscale);
+            }
+            jb.y[m] = out;
         }
-        jb.y[m] = out;
     }
 }
 
-// Chebyshev nodes of [-1, 1] and the inverse of their 4x4 Vandermonde matrix.
+// Chebyshev nodes of [-1, 1] and the inverse of their Vandermonde matrix.
 MfmaSincConst make_mfma_const()
 {
+    constexpr int n = kMfOrders;
     MfmaSincConst c{};
-    double V[4][4], inv[4][8];
-    for (int i = 0; i < 4; ++i) {
-        c.node[i] = std::cos((2.0 * i + 1.0) * kPi / 8.0);
-        for (int r = 0; r < 4; ++r)
-            V[i][r] = std::pow(c.node[i], r);
+    double inv[n][2 * n];
+    for (int i = 0; i < n; ++i) {
+        c.node[i] = std::cos((2.0 * i + 1.0) * kPi / (2.0 * n));
+        for (int j = 0; j < 2 * n; ++j)
+            inv[i][j] = j < n ? std::pow(c.node[i], j) : (j - n == i ? 1.0 : 0.0);
     }
-    // Gauss-Jordan on [V | I]; V[i][r] = z_i^r, so a = V^-1 h gives p(z) = sum_r a_r z^r
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 8; ++j)
-            inv[i][j] = j < 4 ? V[i][j] : (j - 4 == i ? 1.0 : 0.0);
-    for (int p = 0; p < 4; ++p) {
+    // Gauss-Jordan on [V | I] with V[i][r] = z_i^r: a = V^-1 h gives p(z) = sum_r a_r z^r
+    for (int p = 0; p < n; ++p) {
         int piv = p;
-        for (int i = p + 1; i < 4; ++i)
+        for (int i = p + 1; i < n; ++i)
             if (std::fabs(inv[i][p]) > std::fabs(inv[piv][p]))
                 piv = i;
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < 2 * n; ++j)
             std::swap(inv[p][j], inv[piv][j]);
         const double d = inv[p][p];
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < 2 * n; ++j)
             inv[p][j] /= d;
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < n; ++i)
             if (i != p) {
                 const double f = inv[i][p];
-                for (int j = 0; j < 8; ++j)
+                for (int j = 0; j < 2 * n; ++j)
                     inv[i][j] -= f * inv[p][j];
             }
     }
-    for (int r = 0; r < 4; ++r)
-        for (int i = 0; i < 4; ++i)
-            c.vinv[r * 4 + i] = inv[r][4 + i];
+    for (int r = 0; r < n; ++r)
+        for (int i = 0; i < n; ++i)
+            c.vinv[r * n + i] = inv[r][n + i];
     return c;
 }
 
 template <int H>
-hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int64_t nblk,
-                    const KaiserPoly &kp, hipStream_t s)
+hipError_t build_table_h(const KaiserPoly &kp, void **dev, std::vector<void *> &allocs)
 {
-    static const MfmaSincConst mc = make_mfma_const();
-    static bool attr_set = false;
+    const size_t bytes = (size_t)kPhaseRows * MfGeom<H>::bbytes;
+    hipError_t e = hipMalloc(dev, bytes);
+    if (e != hipSuccess)
+        return e;
+    allocs.push_back(*dev);
+    const MfmaSincConst mc = make_mfma_const();
+    unsigned char *t = static_cast<unsigned char *>(*dev);
+    if (kp.n <= 24)
+        hipLaunchKernelGGL((k_sinc_table<H, 24>), dim3(kPhaseRows), dim3(256), 0, 0, kp, mc, t);
+    else if (kp.n <= 28)
+        hipLaunchKernelGGL((k_sinc_table<H, 28>), dim3(kPhaseRows), dim3(256), 0, 0, kp, mc, t);
+    else
+        hipLaunchKernelGGL((k_sinc_table<H, 32>), dim3(kPhaseRows), dim3(256), 0, 0, kp, mc, t);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return hipStreamSynchronize(0);
+}
+
+template <int H>
+hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int64_t nblk,
+                    const unsigned char *table, hipStream_t s)
+{
     const size_t lds = MfGeom<H>::bytes;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sinc_mfma<H>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    // the LDS limit is raised once per device (more than 64 KiB of dynamic LDS)
+    static bool attr_set[64] = {false};
+    if (dev < 0 || dev >= 64)
+        return hipErrorInvalidDevice;
+    if (!attr_set[dev]) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sinc_mfma<H>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
-        attr_set = true;
+        attr_set[dev] = true;
     }
     hipLaunchKernelGGL(k_sinc_mfma<H>, dim3((unsigned)nblk, (unsigned)njobs), dim3(256), lds, s, jobs_dev,
-                       inl, kp, mc);
+                       inl, table);
     return hipGetLastError();
 }
 
@@ -304,22 +394,35 @@ hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int6
 bool sinc_mfma_eligible(double alpha, const rc_sinc &k)
 {
     return k.window == RC_WIN_KAISER && (k.half_width == 64 || k.half_width == 128) &&
-           std::fabs(alpha - 1.0) <= kSincMfmaMaxEps;
+           std::fabs(alpha - 1.0) <= kSincMfmaMaxEps && make_kaiser_poly(k.kaiser_beta).n <= kMfKaiserTerms;
+}
+
+hipError_t build_sinc_mfma_table(int half_width, double beta, void **dev, std::vector<void *> &allocs)
+{
+    const KaiserPoly kp = make_kaiser_poly(beta);
+    if (kp.n > kMfKaiserTerms)
+        return hipErrorInvalidValue;
+    if (half_width == 64)
+        return build_table_h<64>(kp, dev, allocs);
+    if (half_width == 128)
+        return build_table_h<128>(kp, dev, allocs);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, int njobs, int64_t max_out,
-                            int half_width, const KaiserPoly &kp, hipStream_t s, Profiler *prof)
+                            int half_width, const void *table, hipStream_t s, Profiler *prof)
 {
     if (njobs <= 0 || max_out <= 0)
         return hipSuccess;
     const int64_t nblk = (max_out + kMfOut - 1) / kMfOut;
-    if (nblk > 0x7fffffff || njobs > 65535)
+    if (nblk > 0x7fffffff || njobs > 65535 || !table)
         return hipErrorInvalidValue;
     const SincJob inl = job_inline ? *job_inline : SincJob{};
+    const unsigned char *t = static_cast<const unsigned char *>(table);
     if (prof)
         prof->begin(kKSincMfma, s);
-    hipError_t e = half_width == 64 ? launch_h<64>(jobs_dev, inl, njobs, nblk, kp, s)
-                                    : launch_h<128>(jobs_dev, inl, njobs, nblk, kp, s);
+    hipError_t e = half_width == 64 ? launch_h<64>(jobs_dev, inl, njobs, nblk, t, s)
+                                    : launch_h<128>(jobs_dev, inl, njobs, nblk, t, s);
     if (prof)
         prof->end(s);
     return e;
