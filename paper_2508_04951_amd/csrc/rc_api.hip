@@ -67,48 +67,67 @@ struct DeviceGuard {
     }
 };
 
-// Stage `bytes` of descriptors to the device on `s`.  The staging buffers are reused by the
-// next batch call only after the work that reads them has completed (event `desc_done`).
-rc_status stage_descriptors(rc_context ctx, const void *host, size_t bytes, hipStream_t s,
+// Stage `bytes` of descriptors to the device on `s`, in the next slot of the context's ring, with
+// `extra` more bytes of device workspace after them (from offset align256(bytes)).  A slot is
+// reused only after the work that read it has completed, so the host may run up to
+// kDescSlots - 1 calls ahead of the device.
+rc_status stage_descriptors(rc_context ctx, const void *host, size_t bytes, size_t extra, hipStream_t s,
                             const void **dev_out)
 {
+    auto &slot = ctx->desc[ctx->desc_next];
     hipError_t e;
-    if (ctx->desc_pending) {
-        e = hipEventSynchronize(ctx->desc_done);
+    if (slot.pending) {
+        e = hipEventSynchronize(slot.done);
         if (e != hipSuccess)
-            return device_fail(ctx, e, "waiting for the previous batch");
-        ctx->desc_pending = false;
+            return device_fail(ctx, e, "waiting for an earlier call");
+        slot.pending = false;
     }
-    if (bytes > ctx->desc_cap) {
+    const size_t dev_bytes = extra ? ((bytes + 255) & ~(size_t)255) + extra : bytes;
+    auto grow = [](size_t need) {
         size_t cap = 1 << 16;
-        while (cap < bytes)
+        while (cap < need)
             cap <<= 1;
-        if (ctx->desc_host)
-            (void)hipHostFree(ctx->desc_host);
-        if (ctx->desc_dev)
-            (void)hipFree(ctx->desc_dev);
-        ctx->desc_host = nullptr;
-        ctx->desc_dev = nullptr;
-        ctx->desc_cap = 0;
-        if (hipHostMalloc(&ctx->desc_host, cap, hipHostMallocDefault) != hipSuccess ||
-            hipMalloc(&ctx->desc_dev, cap) != hipSuccess)
+        return cap;
+    };
+    if (bytes > slot.host_cap) {
+        if (slot.host)
+            (void)hipHostFree(slot.host);
+        slot.host = nullptr;
+        slot.host_cap = 0;
+        const size_t cap = grow(bytes);
+        if (hipHostMalloc(&slot.host, cap, hipHostMallocDefault) != hipSuccess)
             return fail(ctx, RC_ERR_OUT_OF_MEMORY, "descriptor staging allocation failed");
-        ctx->desc_cap = cap;
+        slot.host_cap = cap;
     }
-    std::memcpy(ctx->desc_host, host, bytes);
-    e = hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess)
-        return device_fail(ctx, e, "descriptor upload");
-    *dev_out = ctx->desc_dev;
+    if (dev_bytes > slot.dev_cap) {
+        if (slot.dev)
+            (void)hipFree(slot.dev);
+        slot.dev = nullptr;
+        slot.dev_cap = 0;
+        const size_t cap = grow(dev_bytes);
+        if (hipMalloc(&slot.dev, cap) != hipSuccess)
+            return fail(ctx, RC_ERR_OUT_OF_MEMORY, "descriptor workspace allocation failed");
+        slot.dev_cap = cap;
+    }
+    if (bytes) {
+        std::memcpy(slot.host, host, bytes);
+        e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return device_fail(ctx, e, "descriptor upload");
+    }
+    *dev_out = slot.dev;
     return RC_OK;
 }
 
+// The work that reads the slot filled by the last stage_descriptors() is now enqueued on `s`.
 rc_status mark_descriptors_used(rc_context ctx, hipStream_t s)
 {
-    hipError_t e = hipEventRecord(ctx->desc_done, s);
+    auto &slot = ctx->desc[ctx->desc_next];
+    hipError_t e = hipEventRecord(slot.done, s);
     if (e != hipSuccess)
         return device_fail(ctx, e, "descriptor event");
-    ctx->desc_pending = true;
+    slot.pending = true;
+    ctx->desc_next = (ctx->desc_next + 1) % rc_context_s::kDescSlots;
     return RC_OK;
 }
 
@@ -220,9 +239,13 @@ rc_status rc_create(int hip_device, rc_context *out)
     ctx->device = hip_device;
     DeviceGuard g(hip_device);
     hipError_t e = rc::make_base_twiddles(&ctx->tw4096);
-    if (e == hipSuccess)
-        e = hipEventCreateWithFlags(&ctx->desc_done, hipEventDisableTiming);
+    for (auto &slot : ctx->desc)
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
     if (e != hipSuccess) {
+        for (auto &slot : ctx->desc)
+            if (slot.done)
+                (void)hipEventDestroy(slot.done);
         if (ctx->tw4096)
             (void)hipFree(ctx->tw4096);
         delete ctx;
@@ -246,12 +269,14 @@ rc_status rc_destroy(rc_context ctx)
             (void)hipFree(p);
         if (ctx->tw4096)
             (void)hipFree(ctx->tw4096);
-        if (ctx->desc_dev)
-            (void)hipFree(ctx->desc_dev);
-        if (ctx->desc_host)
-            (void)hipHostFree(ctx->desc_host);
-        if (ctx->desc_done)
-            (void)hipEventDestroy(ctx->desc_done);
+        for (auto &slot : ctx->desc) {
+            if (slot.dev)
+                (void)hipFree(slot.dev);
+            if (slot.host)
+                (void)hipHostFree(slot.host);
+            if (slot.done)
+                (void)hipEventDestroy(slot.done);
+        }
         ctx->prof.release();
     }
     delete ctx;
@@ -297,7 +322,7 @@ rc_status correct_doppler(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 
         return fail(ctx, RC_ERR_INVALID_ARG, "x and y overlap");
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const SincJob job{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y), n_in, n_out, alpha};
+    const SincJob job{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y), n_in, n_out, alpha, 0};
     const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
     hipError_t e;
     switch (sinc_path(ctx, alpha, *k)) {
@@ -306,7 +331,23 @@ rc_status correct_doppler(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 
         rc_status ts = get_mfma_table(ctx, *k, &table);
         if (ts != RC_OK)
             return ts;
-        e = rc::launch_sinc_mfma(nullptr, &job, 1, n_out, k->half_width, table, s, prof_of(ctx));
+        const int64_t ntiles = (n_out + rc::kSincMfmaTile - 1) / rc::kSincMfmaTile;
+        if (!rc::sinc_mfma_uses_list(k->half_width, ntiles)) {
+            e = rc::launch_sinc_mfma(nullptr, &job, 1, n_out, ntiles, nullptr, k->half_width, table, s,
+                                     prof_of(ctx));
+            break;
+        }
+        // a long pulse: the job descriptor and the tile list go to a staging slot
+        const void *dev = nullptr;
+        ts = stage_descriptors(ctx, &job, sizeof job, rc::sinc_mfma_work_bytes(ntiles), s, &dev);
+        if (ts != RC_OK)
+            return ts;
+        char *devc = static_cast<char *>(const_cast<void *>(dev));
+        e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc), nullptr, 1, n_out, ntiles, devc + 256,
+                                 k->half_width, table, s, prof_of(ctx));
+        ts = mark_descriptors_used(ctx, s);
+        if (e == hipSuccess && ts != RC_OK)
+            return ts;
         break;
     }
     case SincPath::Fast:
@@ -422,7 +463,7 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
     for (int32_t i = 0; i < count; ++i) {
         const rc_pulse &p = pulses[i];
         if (p.flags & RC_DO_DOPPLER) {
-            const SincJob j{xb + p.off_in, yb + p.off_out, p.n_in, p.n_out, p.alpha};
+            const SincJob j{xb + p.off_in, yb + p.off_out, p.n_in, p.n_out, p.alpha, 0};
             const SincPath path = sinc_path(ctx, p.alpha, *k);
             if (path == SincPath::Mfma) {
                 mfma.push_back(j);
@@ -453,13 +494,23 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
             return st;
     }
     const void *mfma_table = nullptr;
+    int64_t mfma_tiles = 0;
+    size_t mfma_work = 0;
     if (!mfma.empty()) {
         st = get_mfma_table(ctx, *k, &mfma_table);
         if (st != RC_OK)
             return st;
+        for (SincJob &j : mfma) {
+            j.tile0 = mfma_tiles;
+            mfma_tiles += (j.n_out + rc::kSincMfmaTile - 1) / rc::kSincMfmaTile;
+        }
+        if (mfma_tiles > 0x7fffffff)
+            return fail(ctx, RC_ERR_UNSUPPORTED, "more than 2^31 - 1 matrix-core tiles in a batch");
+        if (rc::sinc_mfma_uses_list(k->half_width, mfma_tiles))
+            mfma_work = rc::sinc_mfma_work_bytes(mfma_tiles);
     }
 
-    // one descriptor upload: [fast | direct | iono groups...]
+    // one descriptor upload: [mfma | fast | direct | iono groups...], then the tile-list workspace
     std::vector<char> blob;
     auto append = [&](const void *p, size_t bytes) {
         const size_t off = (blob.size() + 15) & ~(size_t)15;
@@ -475,11 +526,23 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
         off_iono.push_back(append(kv.second.data(), kv.second.size() * sizeof(IonoJob)));
     const void *dev = nullptr;
     if (!blob.empty()) {
-        st = stage_descriptors(ctx, blob.data(), blob.size(), s, &dev);
+        st = stage_descriptors(ctx, blob.data(), blob.size(), mfma_work, s, &dev);
         if (st != RC_OK)
             return st;
     }
-    const char *devc = static_cast<const char *>(dev);
+    char *devc = static_cast<char *>(const_cast<void *>(dev));
+    void *work = mfma_work ? devc + ((blob.size() + 255) & ~(size_t)255) : nullptr;
+    // from here on the slot is in use: mark it whatever happens
+    struct SlotMark {
+        rc_context ctx;
+        hipStream_t s;
+        bool armed;
+        ~SlotMark()
+        {
+            if (armed)
+                (void)mark_descriptors_used(ctx, s);
+        }
+    } slot_mark{ctx, s, !blob.empty()};
     hipError_t e = hipSuccess;
     for (int32_t i : copies) {
         const rc_pulse &p = pulses[i];
@@ -490,7 +553,7 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
     const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
     if (!mfma.empty())
         e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc + off_mfma), nullptr, (int)mfma.size(),
-                                 mfma_max, k->half_width, mfma_table, s, prof_of(ctx));
+                                 mfma_max, mfma_tiles, work, k->half_width, mfma_table, s, prof_of(ctx));
     if (e == hipSuccess && !fast.empty())
         e = rc::launch_sinc_fast(reinterpret_cast<const SincJob *>(devc + off_fast), nullptr, (int)fast.size(),
                                  fast_max, k->half_width, kp, s, prof_of(ctx));
@@ -514,8 +577,10 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
                 return device_fail(ctx, e, "batch ionosphere launch");
         }
     }
-    if (!blob.empty())
+    if (!blob.empty()) {
+        slot_mark.armed = false;
         return mark_descriptors_used(ctx, s);
+    }
     return RC_OK;
 }
 
@@ -566,7 +631,8 @@ rc_status rc_profile_read(rc_context ctx, const char *kernel, double *total_ms, 
 namespace rc {
 
 const char *const kKernelNames[kKGroups] = {"k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd",
-                                            "k_fft_rows_iono", "k_fft_strided_inv", "k_sinc_mfma"};
+                                            "k_fft_rows_iono", "k_fft_strided_inv", "k_sinc_mfma",
+                                            "k_mf_tile_sort"};
 
 hipEvent_t Profiler::take()
 {

@@ -21,6 +21,7 @@ enum KernelGroup {
     kKFftRowsIono,
     kKFftStridedInv,
     kKSincMfma,
+    kKSincTiles,
     kKGroups
 };
 extern const char *const kKernelNames[kKGroups];
@@ -70,6 +71,7 @@ struct SincJob {
     int64_t n_in;
     int64_t n_out;
     double alpha;
+    int64_t tile0;  // matrix-core path: index of this job's first tile in the batch's tile list
 };
 
 // Tile geometry of the windowed fast path: each wave owns 256 consecutive outputs
@@ -84,10 +86,11 @@ constexpr double kSincFastMaxEps = 1.0e-4;
 
 bool sinc_fast_eligible(double alpha, const rc_sinc &k);
 
-// Matrix-core path (Kaiser, H = 64 or 128): a 2048-output workgroup takes its tap weights from
-// a quartic in the drift tabulated on a grid of 129 phases, so |alpha - 1| * 1023.5 must stay
+// Matrix-core path (Kaiser, H = 64 or 128): a 2048-output tile takes its tap weights from a
+// quartic in the drift tabulated on a grid of 129 phases, so |alpha - 1| * 1023.5 must stay
 // below ~0.061 samples.
 constexpr double kSincMfmaMaxEps = 6.0e-5;
+constexpr int kSincMfmaTile = 2048;
 struct MfmaSincConst {
     double node[5];   // Chebyshev nodes of [-1, 1]
     double vinv[25];  // inverse Vandermonde matrix: a_r = sum_i vinv[5 r + i] h(node_i)
@@ -95,9 +98,15 @@ struct MfmaSincConst {
 bool sinc_mfma_eligible(double alpha, const rc_sinc &k);
 // Device table of the B fragments for every grid phase (built once per (H, beta)).
 hipError_t build_sinc_mfma_table(int half_width, double beta, void **dev, std::vector<void *> &allocs);
+// Batches of more tiles than the resident workgroups run persistent workgroups over a tile list
+// sorted by phase; the list needs `sinc_mfma_work_bytes(ntiles)` of device workspace.
+bool sinc_mfma_uses_list(int half_width, int64_t ntiles);
+size_t sinc_mfma_work_bytes(int64_t ntiles);
+// jobs_dev (device array, tile0 set) or job_inline (one job, tile0 = 0); `work` is the workspace
+// when sinc_mfma_uses_list(), else unused.
 hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, int njobs,
-                            int64_t max_out, int half_width, const void *table, hipStream_t s,
-                            Profiler *prof);
+                            int64_t max_out, int64_t ntiles, void *work, int half_width,
+                            const void *table, hipStream_t s, Profiler *prof);
 KaiserPoly make_kaiser_poly(double beta);
 size_t sinc_fast_lds_bytes(int half_width);
 
@@ -155,12 +164,19 @@ struct rc_context_s {
     std::map<int64_t, rc::FftPlan> plans;      // by transform length
     std::map<std::pair<int, double>, void *> mfma_tables;  // by (half width, Kaiser beta)
     std::vector<void *> allocs;                // every device allocation owned
-    // descriptor staging for batches: pinned host + device, guarded by `desc_done`
-    void *desc_host = nullptr;
-    void *desc_dev = nullptr;
-    size_t desc_cap = 0;
-    hipEvent_t desc_done = nullptr;
-    bool desc_pending = false;
+    // descriptor staging: a ring of pinned host + device slots; a slot is reused only after the
+    // work that read it has completed (its event)
+    struct DescSlot {
+        void *host = nullptr;
+        void *dev = nullptr;
+        size_t host_cap = 0;
+        size_t dev_cap = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    };
+    static constexpr int kDescSlots = 4;
+    DescSlot desc[kDescSlots];
+    int desc_next = 0;
     rc::Profiler prof;
     int sinc_engine = 0;  // RC_SINC_AUTO / RC_SINC_VALU / RC_SINC_DIRECT
 };

@@ -16,10 +16,16 @@
 //     X[i][kappa] = x[m0 + 16 i + S - H + kappa]   (Hankel: 8-sample aligned runs per lane),
 //     B_r[kappa][u] = a_{p,r}[kappa - u - H]        (the column shift u lives in B).
 // kappa runs over 2H + 16 taps rounded up to whole 32-wide MFMA steps.  Both operands are split
-// into float16 hi + lo parts after exact power-of-two scaling, and each order and component
-// accumulates hi*hi + hi*lo + lo*hi in float32 (v_mfma_f32_16x16x32_f16): about 22 bits per
-// product.  The four waves each run two sub-tiles, together, against the B block copied once
-// into LDS.
+// into float16 hi + lo parts after exact power-of-two scaling.  Orders 0 and 1 accumulate
+// hi*hi + hi*lo + lo*hi in float32 (v_mfma_f32_16x16x32_f16, about 22 bits per product); the
+// higher orders, whose terms are at most a few parts in 1e3 of the output for band-limited
+// input, take hi*hi alone (11 bits).
+//
+// Batches of many tiles run persistent workgroups over a tile list sorted by phase (built on the
+// device by k_mf_tile_phase + k_mf_tile_sort): a workgroup walks a run of that list, copies a
+// phase's B block into LDS only when the phase changes, and prefetches the next tile's input
+// into registers while the matrix cores work on the current one.  Consecutive workgroup indices
+// are spread over the eight XCDs, so each XCD's L2 serves a contiguous range of phases.
 #include <cmath>
 #include <vector>
 
@@ -32,9 +38,11 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMfOut = 2048;           // outputs per workgroup (one phase-grid point)
-constexpr int kMfSubs = kMfOut / 256;  // 256-output sub-tiles: two per wave
+constexpr int kMfOut = kSincMfmaTile;  // outputs per tile (one phase-grid point)
 constexpr int kMfOrders = 5;           // quartic in the drift
+constexpr int kMfLo = 2;               // orders that also take the hi*lo and lo*hi products
+constexpr int kMfBlk = kMfOrders + kMfLo;  // 1 KiB B fragments per 32-tap step
+constexpr int kXcds = 8;               // workgroups are dealt round-robin to this many XCDs
 constexpr int kCoefExp = 12;           // coefficients are scaled by 2^12 before the fp16 split
 constexpr double kMfHalf = 0.5 * (kMfOut - 1);  // 1023.5: half-width of the tile in outputs
 constexpr int kPhases = 128;                    // phase grid points per sample
@@ -50,7 +58,7 @@ struct MfGeom {
     static constexpr int spp = (span + 511) / 512;            // staged sample pairs per thread
     static constexpr int rowlen = kext + 32;                   // padded coefficient row (halves)
     static constexpr int node_iters = (ntap + 47) / 48;       // 12 taps x 5 nodes per wave
-    static constexpr int bbytes = ksteps * kMfOrders * 2 * 1024;  // B fragments of one phase
+    static constexpr int bbytes = ksteps * kMfBlk * 1024;  // B fragments of one phase
     // main kernel LDS: B block, then 4 fp16 arrays of `span`, then 4 floats (wave maxima)
     static constexpr int a_off = bbytes;
     static constexpr int m_off = a_off + ((4 * span * 2) + 15) / 16 * 16;
@@ -74,8 +82,9 @@ __device__ __forceinline__ double kaiser_at_m(const KaiserPoly &kp, double x)
 }
 
 // One workgroup per grid phase p: the quartic of every tap (float64 at the five Chebyshev
-// nodes of [-delta_max, delta_max]), split into fp16 hi/lo, arranged as B fragments:
-// block (s, r, part) holds, for lane l, the 8 halves B_r[32 s + 8 (l / 16) + j][l % 16].
+// nodes of [-delta_max, delta_max]), split into fp16 hi/lo, arranged as B fragments: step s
+// holds the hi blocks of orders 0..4, then the lo blocks of orders 0..kMfLo-1; a block holds,
+// for lane l, the 8 halves B_r[32 s + 8 (l / 16) + j][l % 16].
 template <int H, int NT>
 __global__ void __launch_bounds__(256) k_sinc_table(KaiserPoly kp, MfmaSincConst mc, unsigned char *table)
 {
@@ -117,9 +126,10 @@ __global__ void __launch_bounds__(256) k_sinc_table(KaiserPoly kp, MfmaSincConst
     }
     __syncthreads();
     unsigned char *out = table + (size_t)blockIdx.x * G::bbytes;
-    for (int id = tid; id < G::ksteps * kMfOrders * 2 * 64; id += 256) {
-        const int l = id & 63, blk = id >> 6;  // blk = (s * orders + r) * 2 + part
-        const int part = blk & 1, r = (blk >> 1) % kMfOrders, s = (blk >> 1) / kMfOrders;
+    for (int id = tid; id < G::ksteps * kMfBlk * 64; id += 256) {
+        const int l = id & 63, blk = id >> 6;  // blk = s * kMfBlk + j
+        const int s = blk / kMfBlk, j = blk - s * kMfBlk;
+        const int part = j < kMfOrders ? 0 : 1, r = j < kMfOrders ? j : j - kMfOrders;
         const int u = l & 15;
         const int o = 16 + 32 * s + 8 * (l >> 4) - u;  // first half of the fragment in the row
         uint4 f;
@@ -136,9 +146,74 @@ __global__ void __launch_bounds__(256) k_sinc_table(KaiserPoly kp, MfmaSincConst
     }
 }
 
-template <int H>
+// Where a tile of outputs M0 .. M0 + 2047 sits in the input: shift S, offset sigma_c of its
+// centre from sample M0 + 1023.5 + S, and the nearest grid phase p / 128.
+struct MfTile {
+    double Sd;  // S as a double
+    double sc;  // sigma at the tile centre, in [-1/2, 1/2]
+    int p;      // grid phase, -64 .. 64
+};
+
+__device__ __forceinline__ MfTile mf_tile(double alpha, int64_t M0)
+{
+    const double eps = alpha - 1.0;
+    const double mcen = (double)M0 + kMfHalf;
+    MfTile t;
+    t.Sd = rint(eps * mcen);
+    t.sc = eps * mcen - t.Sd;
+    int p = (int)rint(t.sc * kPhases);
+    t.p = p < -kPhases / 2 ? -kPhases / 2 : (p > kPhases / 2 ? kPhases / 2 : p);
+    return t;
+}
+
+// Tile list, step 1: every (job, tile) writes its reference and its phase at its flat index
+// tile0 + tile.  Grid: (tile blocks of 256, jobs).
 __global__ void __launch_bounds__(256)
-k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const unsigned char *__restrict__ table)
+k_mf_tile_phase(const SincJob *__restrict__ jobs, uint2 *__restrict__ ref, unsigned char *__restrict__ phase)
+{
+    const SincJob jb = jobs[blockIdx.y];
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t * kMfOut >= jb.n_out)
+        return;
+    const MfTile tp = mf_tile(jb.alpha, t * kMfOut);
+    ref[jb.tile0 + t] = make_uint2(blockIdx.y, (unsigned)t);
+    phase[jb.tile0 + t] = (unsigned char)(tp.p + kPhases / 2);
+}
+
+// Tile list, step 2 (one workgroup): counting sort of the references by phase.  The order of
+// equal phases is arbitrary; no output depends on it.
+__global__ void __launch_bounds__(1024)
+k_mf_tile_sort(const uint2 *__restrict__ ref, const unsigned char *__restrict__ phase, int64_t ntiles,
+               uint2 *__restrict__ list)
+{
+    __shared__ unsigned cnt[kPhaseRows];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kPhaseRows; i += 1024)
+        cnt[i] = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < ntiles; i += 1024)
+        atomicAdd(&cnt[phase[i]], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        unsigned run = 0;
+        for (int i = 0; i < kPhaseRows; ++i) {
+            const unsigned c = cnt[i];
+            cnt[i] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t i = tid; i < ntiles; i += 1024)
+        list[atomicAdd(&cnt[phase[i]], 1u)] = ref[i];
+}
+
+// The resampling GEMM.  Without a list, workgroup (x, y) computes tile x of job y.  With a list,
+// the grid is persistent: workgroup b takes the run c(b) of the sorted list, where c deals
+// consecutive b to different XCDs so that an XCD holds a contiguous range of phases.
+template <int H>
+__global__ void __launch_bounds__(256, 2)
+k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restrict__ list, int64_t ntiles,
+            const unsigned char *__restrict__ table)
 {
     using G = MfGeom<H>;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -148,161 +223,213 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const unsigned char *
     _Float16 *a_ih = a_rl + G::span;
     _Float16 *a_il = a_ih + G::span;
     float *wmax = reinterpret_cast<float *>(smem + G::m_off);
-
-    const SincJob jb = jobs ? jobs[blockIdx.y] : inl;
-    const int64_t M0 = (int64_t)blockIdx.x * kMfOut;
-    if (M0 >= jb.n_out)
-        return;  // uniform over the workgroup
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const double alpha = jb.alpha, eps = alpha - 1.0;
-    const double mcen = (double)M0 + kMfHalf;
-    const double Sd = rint(eps * mcen);
-    const int64_t S = (int64_t)Sd;
-    const double sc = eps * mcen - Sd;  // sigma at the tile centre, in [-1/2, 1/2]
-    int p = (int)rint(sc * kPhases);
-    p = p < -kPhases / 2 ? -kPhases / 2 : (p > kPhases / 2 ? kPhases / 2 : p);
-    const int64_t lo = M0 + S - H;      // first staged sample
 
-    // 1) copy this phase's B fragments into LDS (16 B per thread and step)
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(table + (size_t)(p + kPhases / 2) * G::bbytes);
-        uint4 *dst = reinterpret_cast<uint4 *>(bsm);
-        for (int i = tid; i < G::bbytes / 16; i += 256)
-            dst[i] = src[i];
+    int64_t i0 = 0, i1 = 1;
+    if (list) {
+        const int64_t g = gridDim.x, b = blockIdx.x;
+        const int64_t c = g % kXcds == 0 ? (b % kXcds) * (g / kXcds) + b / kXcds : b;
+        i0 = c * ntiles / g;
+        i1 = (c + 1) * ntiles / g;
+        if (i0 >= i1)
+            return;  // uniform over the workgroup
     }
-    // 2) stage the input span (two samples per thread and step), find its largest component
+    auto tile_at = [&](int64_t i, SincJob &jb, int64_t &M0) {
+        if (list) {
+            const uint2 e = list[i];
+            jb = jobs[e.x];
+            M0 = (int64_t)e.y * kMfOut;
+        } else {
+            jb = jobs ? jobs[blockIdx.y] : inl;
+            M0 = (int64_t)blockIdx.x * kMfOut;
+        }
+    };
+    // the input span of a tile: samples lo .. lo + span - 1, two per thread and step
     float2 xv[G::spp][2];
-    float mx = 0.f;
-    const bool whole = lo >= 0 && lo + G::span <= jb.n_in;  // no sample of the span is outside x
-    const float2 *xs = jb.x + lo;
+    auto fetch = [&](const SincJob &jb, int64_t lo) {
+        const bool whole = lo >= 0 && lo + G::span <= jb.n_in;  // no sample of the span is outside x
+        const float2 *xs = jb.x + lo;
 #pragma unroll
-    for (int q = 0; q < G::spp; ++q) {
-        const int e = 2 * tid + 512 * q;
+        for (int q = 0; q < G::spp; ++q) {
+            const int e = 2 * tid + 512 * q;
 #pragma unroll
-        for (int h2 = 0; h2 < 2; ++h2) {
-            float2 v = make_float2(0.f, 0.f);
-            if (e + h2 < G::span && (whole || (lo + e + h2 >= 0 && lo + e + h2 < jb.n_in)))
-                v = xs[e + h2];
-            xv[q][h2] = v;
-            mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1)
-        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-    if (lane == 0)
-        wmax[wave] = mx;
-    __syncthreads();
-
-    // 3) scale by a power of two (largest component in [2^10, 2^11)) and split into fp16 hi/lo
-    const float wm = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
-    int xe = 0;
-    if (wm > 0.f) {
-        int E;
-        frexpf(wm, &E);  // wm = f 2^E, f in [0.5, 1)
-        xe = 11 - E;
-    }
-    const float xs2 = ldexpf(1.0f, xe);
-#pragma unroll
-    for (int q = 0; q < G::spp; ++q) {
-        const int e = 2 * tid + 512 * q;
-        if (e < G::span) {  // span is even: a pair is either wholly inside or outside
-            const float r0 = xv[q][0].x * xs2, r1 = xv[q][1].x * xs2;
-            const float i0 = xv[q][0].y * xs2, i1 = xv[q][1].y * xs2;
-            const half2v rh = {(_Float16)r0, (_Float16)r1};
-            const half2v ih = {(_Float16)i0, (_Float16)i1};
-            const half2v rl = {(_Float16)(r0 - (float)rh[0]), (_Float16)(r1 - (float)rh[1])};
-            const half2v il = {(_Float16)(i0 - (float)ih[0]), (_Float16)(i1 - (float)ih[1])};
-            *reinterpret_cast<half2v *>(a_rh + e) = rh;
-            *reinterpret_cast<half2v *>(a_rl + e) = rl;
-            *reinterpret_cast<half2v *>(a_ih + e) = ih;
-            *reinterpret_cast<half2v *>(a_il + e) = il;
-        }
-    }
-    __syncthreads();
-
-    const float unscale = ldexpf(1.0f, -(xe + kCoefExp));
-    // z_m = (sigma_m - sigma_p) / delta_max = z_c + (m - mcen) eps / delta_max
-    const float zc = (float)((sc - (double)p / kPhases) / kDeltaMax);
-    const float zstep = (float)(eps / kDeltaMax);
-    const float sc32 = (float)sc;
-    const float e32 = (float)eps;
-
-    // 4) the GEMM.  Wave w owns sub-tiles w and w + 4 and runs them together: each B fragment
-    //    is read from LDS once per 32-tap step for both, and the 60 MFMAs of a step touch 20
-    //    accumulators (2 sub-tiles x 5 orders x re/im) in an order that puts 20 independent
-    //    MFMAs between two that update the same accumulator.
-    if (M0 + 256 * wave >= jb.n_out)
-        return;  // no barrier follows; sub-tile w + 4 starts later still
-    floatx4 acc[2][kMfOrders][2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int r = 0; r < kMfOrders; ++r)
-            acc[t][r][0] = acc[t][r][1] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int arow = 256 * wave + 16 * (lane & 15) + 8 * (lane >> 4);
-#pragma unroll
-    for (int s = 0; s < G::ksteps; ++s) {
-        half8 xh[2][2], xl[2][2];  // [sub-tile][re/im]
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int e = arow + 1024 * t + 32 * s;
-            xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
-            xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
-            xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
-            xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
-        }
-        half8 bh[kMfOrders], bl[kMfOrders];
-#pragma unroll
-        for (int r = 0; r < kMfOrders; ++r) {
-            const half8 *blk = reinterpret_cast<const half8 *>(bsm + ((s * kMfOrders + r) * 2) * 1024);
-            bh[r] = blk[lane];
-            bl[r] = blk[64 + lane];
-        }
-#pragma unroll
-        for (int part = 0; part < 3; ++part)  // hi*hi, hi*lo, lo*hi
-#pragma unroll
-            for (int r = 0; r < kMfOrders; ++r)
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-                        acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                            part == 2 ? xl[t][c] : xh[t][c], part == 1 ? bl[r] : bh[r], acc[t][r][c], 0, 0, 0);
-    }
-
-    // 5) lane holds Z_r[row 4 (l/16) + j][col l % 16] of each sub-tile: output
-    //    m = M0 + 256 sub + 16 row + col.  z is linear in m; the float64 position is recomputed
-    //    only next to an exact sample instant (sigma within 1e-5 of 0), where alpha m may round
-    //    to an integer.
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int off = 256 * (wave + 4 * t) + 16 * (4 * (lane >> 4) + j) + (lane & 15);  // m - M0
-            const int64_t m = M0 + off;
-            if (m >= jb.n_out)
-                continue;
-            const float dm = (float)off - (float)kMfHalf;
-            const float z = fmaf(dm, zstep, zc);
-            bool exact = false;
-            if (fabsf(fmaf(dm, e32, sc32)) < 1e-5f) {
-                const double md = (double)m;
-                exact = ((__dmul_rn(alpha, md) - md) - Sd) == 0.0;
+            for (int h2 = 0; h2 < 2; ++h2) {
+                float2 v = make_float2(0.f, 0.f);
+                if (e + h2 < G::span && (whole || (lo + e + h2 >= 0 && lo + e + h2 < jb.n_in)))
+                    v = xs[e + h2];
+                xv[q][h2] = v;
             }
-            float2 out;
-            if (exact) {
-                const int64_t src = m + S;
-                out = (src >= 0 && src < jb.n_in) ? jb.x[src] : make_float2(0.f, 0.f);
-            } else {
-                float yr = acc[t][kMfOrders - 1][0][j], yi = acc[t][kMfOrders - 1][1][j];
+        }
+    };
+
+    SincJob jb;
+    int64_t M0;
+    tile_at(i0, jb, M0);
+    if (M0 >= jb.n_out)
+        return;  // only without a list (ragged jobs); uniform over the workgroup
+    MfTile tp = mf_tile(jb.alpha, M0);
+    fetch(jb, M0 + (int64_t)tp.Sd - H);
+    int cur_p = kPhaseRows;  // no B block in LDS yet
+
+    for (int64_t i = i0; i < i1; ++i) {
+        // 1) largest component of the fetched span
+        float mx = 0.f;
 #pragma unroll
-                for (int r = kMfOrders - 2; r >= 0; --r) {
-                    yr = fmaf(yr, z, acc[t][r][0][j]);
-                    yi = fmaf(yi, z, acc[t][r][1][j]);
+        for (int q = 0; q < G::spp; ++q)
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2)
+                mx = fmaxf(mx, fmaxf(fabsf(xv[q][h2].x), fabsf(xv[q][h2].y)));
+        for (int o = 32; o > 0; o >>= 1)
+            mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0)
+            wmax[wave] = mx;
+        __syncthreads();  // every wave is done with the previous tile's A and B
+
+        // 2) this phase's B fragments, unless they are in LDS already (uniform branch)
+        if (tp.p != cur_p) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(table + (size_t)(tp.p + kPhases / 2) * G::bbytes);
+            uint4 *dst = reinterpret_cast<uint4 *>(bsm);
+            for (int k = tid; k < G::bbytes / 16; k += 256)
+                dst[k] = src[k];
+            cur_p = tp.p;
+        }
+
+        // 3) scale by a power of two (largest component in [2^10, 2^11)) and split into fp16 hi/lo
+        const float wm = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        int xe = 0;
+        if (wm > 0.f) {
+            int E;
+            frexpf(wm, &E);  // wm = f 2^E, f in [0.5, 1)
+            xe = 11 - E;
+        }
+        const float xs2 = ldexpf(1.0f, xe);
+#pragma unroll
+        for (int q = 0; q < G::spp; ++q) {
+            const int e = 2 * tid + 512 * q;
+            if (e < G::span) {  // span is even: a pair is either wholly inside or outside
+                const float r0 = xv[q][0].x * xs2, r1 = xv[q][1].x * xs2;
+                const float i0f = xv[q][0].y * xs2, i1f = xv[q][1].y * xs2;
+                const half2v rh = {(_Float16)r0, (_Float16)r1};
+                const half2v ih = {(_Float16)i0f, (_Float16)i1f};
+                const half2v rl = {(_Float16)(r0 - (float)rh[0]), (_Float16)(r1 - (float)rh[1])};
+                const half2v il = {(_Float16)(i0f - (float)ih[0]), (_Float16)(i1f - (float)ih[1])};
+                *reinterpret_cast<half2v *>(a_rh + e) = rh;
+                *reinterpret_cast<half2v *>(a_rl + e) = rl;
+                *reinterpret_cast<half2v *>(a_ih + e) = ih;
+                *reinterpret_cast<half2v *>(a_il + e) = il;
+            }
+        }
+
+        // 4) start fetching the next tile; its loads fly while the matrix cores work on this one
+        const SincJob cj = jb;
+        const int64_t cM0 = M0;
+        const MfTile ct = tp;
+        if (i + 1 < i1) {
+            tile_at(i + 1, jb, M0);
+            tp = mf_tile(jb.alpha, M0);
+            fetch(jb, M0 + (int64_t)tp.Sd - H);
+        }
+        __syncthreads();  // A and B are in LDS
+
+        // 5) the GEMM.  Wave w owns sub-tiles w and w + 4 and runs them together: each B
+        //    fragment is read from LDS once per 32-tap step for both.
+        if (cM0 + 256 * wave < cj.n_out) {  // uniform over the wave
+            const double alpha = cj.alpha, eps = alpha - 1.0;
+            const int64_t S = (int64_t)ct.Sd;
+            const float unscale = ldexpf(1.0f, -(xe + kCoefExp));
+            // z_m = (sigma_m - sigma_p) / delta_max = z_c + (m - mcen) eps / delta_max
+            const float zc = (float)((ct.sc - (double)ct.p / kPhases) / kDeltaMax);
+            const float zstep = (float)(eps / kDeltaMax);
+            const float sc32 = (float)ct.sc;
+            const float e32 = (float)eps;
+
+            floatx4 acc[2][kMfOrders][2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r = 0; r < kMfOrders; ++r)
+                    acc[t][r][0] = acc[t][r][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const int arow = 256 * wave + 16 * (lane & 15) + 8 * (lane >> 4);
+            // not unrolled: hoisting the next step's fragments would cost the second wave per SIMD
+#pragma unroll 1
+            for (int s = 0; s < G::ksteps; ++s) {
+                half8 xh[2][2], xl[2][2];  // [sub-tile][re/im]
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int e = arow + 1024 * t + 32 * s;
+                    xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
+                    xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
+                    xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
+                    xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
                 }
-                out = make_float2(yr * unscale, yi * unscale);
+                const half8 *blk = reinterpret_cast<const half8 *>(bsm + s * kMfBlk * 1024);
+                half8 bh[kMfOrders], bl[kMfLo];
+#pragma unroll
+                for (int r = 0; r < kMfOrders; ++r)
+                    bh[r] = blk[64 * r + lane];
+#pragma unroll
+                for (int r = 0; r < kMfLo; ++r)
+                    bl[r] = blk[64 * (kMfOrders + r) + lane];
+                // hi*hi for every order, then hi*lo and lo*hi for the low orders: at least eight
+                // independent products between two that update the same accumulator
+#pragma unroll
+                for (int r = 0; r < kMfOrders; ++r)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c)
+                            acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh[t][c], bh[r], acc[t][r][c], 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < kMfLo; ++r)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c)
+                            acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh[t][c], bl[r], acc[t][r][c], 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < kMfLo; ++r)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c)
+                            acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl[t][c], bh[r], acc[t][r][c], 0, 0, 0);
             }
-            jb.y[m] = out;
+
+            // 6) lane holds Z_r[row 4 (l/16) + j][col l % 16] of each sub-tile: output
+            //    m = M0 + 256 sub + 16 row + col.  z is linear in m; the float64 position is
+            //    recomputed only next to an exact sample instant (sigma within 1e-5 of 0), where
+            //    alpha m may round to an integer.
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int off = 256 * (wave + 4 * t) + 16 * (4 * (lane >> 4) + j) + (lane & 15);  // m - M0
+                    const int64_t m = cM0 + off;
+                    if (m >= cj.n_out)
+                        continue;
+                    const float dm = (float)off - (float)kMfHalf;
+                    const float z = fmaf(dm, zstep, zc);
+                    bool exact = false;
+                    if (fabsf(fmaf(dm, e32, sc32)) < 1e-5f) {
+                        const double md = (double)m;
+                        exact = ((__dmul_rn(alpha, md) - md) - ct.Sd) == 0.0;
+                    }
+                    float2 out;
+                    if (exact) {
+                        const int64_t src = m + S;
+                        out = (src >= 0 && src < cj.n_in) ? cj.x[src] : make_float2(0.f, 0.f);
+                    } else {
+                        float yr = acc[t][kMfOrders - 1][0][j], yi = acc[t][kMfOrders - 1][1][j];
+#pragma unroll
+                        for (int r = kMfOrders - 2; r >= 0; --r) {
+                            yr = fmaf(yr, z, acc[t][r][0][j]);
+                            yi = fmaf(yi, z, acc[t][r][1][j]);
+                        }
+                        out = make_float2(yr * unscale, yi * unscale);
+                    }
+                    cj.y[m] = out;
+                }
+            }
         }
     }
 }
@@ -364,29 +491,106 @@ hipError_t build_table_h(const KaiserPoly &kp, void **dev, std::vector<void *> &
     return hipStreamSynchronize(0);
 }
 
+// Per device: resident workgroups of k_sinc_mfma<H> per CU (the LDS limit raised once) and CUs.
+struct MfDevice {
+    bool ready = false;
+    int per_cu = 0;
+    int cus = 0;
+};
+
 template <int H>
-hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int64_t nblk,
-                    const unsigned char *table, hipStream_t s)
+hipError_t mf_device(MfDevice **out)
 {
-    const size_t lds = MfGeom<H>::bytes;
+    static MfDevice devs[64];
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess)
         return e;
-    // the LDS limit is raised once per device (more than 64 KiB of dynamic LDS)
-    static bool attr_set[64] = {false};
     if (dev < 0 || dev >= 64)
         return hipErrorInvalidDevice;
-    if (!attr_set[dev]) {
+    MfDevice &d = devs[dev];
+    if (!d.ready) {
+        const int lds = MfGeom<H>::bytes;
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sinc_mfma<H>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.per_cu, k_sinc_mfma<H>, 256, lds);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess)
             return e;
-        attr_set[dev] = true;
+        if (d.per_cu < 1)
+            d.per_cu = 1;
+        d.ready = true;
     }
-    hipLaunchKernelGGL(k_sinc_mfma<H>, dim3((unsigned)nblk, (unsigned)njobs), dim3(256), lds, s, jobs_dev,
-                       inl, table);
-    return hipGetLastError();
+    *out = &d;
+    return hipSuccess;
+}
+
+template <int H>
+hipError_t resident_wgs(int64_t *n)
+{
+    MfDevice *d = nullptr;
+    hipError_t e = mf_device<H>(&d);
+    if (e == hipSuccess)
+        *n = (int64_t)d->per_cu * d->cus;
+    return e;
+}
+
+// workspace: [ref: uint2 x n][list: uint2 x n][phase: u8 x n]
+size_t work_list_off(int64_t n) { return (size_t)n * 8; }
+size_t work_phase_off(int64_t n) { return (size_t)n * 16; }
+
+template <int H>
+hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int64_t max_out, int64_t ntiles,
+                    void *work, const unsigned char *table, hipStream_t s, Profiler *prof)
+{
+    MfDevice *d = nullptr;
+    hipError_t e = mf_device<H>(&d);
+    if (e != hipSuccess)
+        return e;
+    const size_t lds = MfGeom<H>::bytes;
+    const int64_t resident = (int64_t)d->per_cu * d->cus;
+    if (ntiles <= resident || !work) {
+        const int64_t nblk = (max_out + kMfOut - 1) / kMfOut;
+        if (prof)
+            prof->begin(kKSincMfma, s);
+        hipLaunchKernelGGL(k_sinc_mfma<H>, dim3((unsigned)nblk, (unsigned)njobs), dim3(256), lds, s, jobs_dev,
+                           inl, nullptr, (int64_t)0, table);
+        e = hipGetLastError();
+        if (prof)
+            prof->end(s);
+        return e;
+    }
+    // sorted tile list, then the persistent grid
+    unsigned char *w = static_cast<unsigned char *>(work);
+    uint2 *ref = reinterpret_cast<uint2 *>(w);
+    uint2 *list = reinterpret_cast<uint2 *>(w + work_list_off(ntiles));
+    unsigned char *phase = w + work_phase_off(ntiles);
+    const int64_t tblk = (max_out + (int64_t)kMfOut * 256 - 1) / ((int64_t)kMfOut * 256);
+    if (prof)
+        prof->begin(kKSincTiles, s);
+    hipLaunchKernelGGL(k_mf_tile_phase, dim3((unsigned)tblk, (unsigned)njobs), dim3(256), 0, s, jobs_dev, ref, phase);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_mf_tile_sort, dim3(1), dim3(1024), 0, s, ref, phase, ntiles, list);
+    e = hipGetLastError();
+    if (prof)
+        prof->end(s);
+    if (e != hipSuccess)
+        return e;
+    int64_t grid = resident;
+    if (grid >= kXcds)
+        grid -= grid % kXcds;
+    if (prof)
+        prof->begin(kKSincMfma, s);
+    hipLaunchKernelGGL(k_sinc_mfma<H>, dim3((unsigned)grid), dim3(256), lds, s, jobs_dev, SincJob{}, list, ntiles,
+                       table);
+    e = hipGetLastError();
+    if (prof)
+        prof->end(s);
+    return e;
 }
 
 }  // namespace
@@ -396,6 +600,15 @@ bool sinc_mfma_eligible(double alpha, const rc_sinc &k)
     return k.window == RC_WIN_KAISER && (k.half_width == 64 || k.half_width == 128) &&
            std::fabs(alpha - 1.0) <= kSincMfmaMaxEps && make_kaiser_poly(k.kaiser_beta).n <= kMfKaiserTerms;
 }
+
+bool sinc_mfma_uses_list(int half_width, int64_t ntiles)
+{
+    int64_t resident = 0;
+    const hipError_t e = half_width == 64 ? resident_wgs<64>(&resident) : resident_wgs<128>(&resident);
+    return e == hipSuccess && ntiles > resident;
+}
+
+size_t sinc_mfma_work_bytes(int64_t ntiles) { return work_phase_off(ntiles) + (size_t)ntiles; }
 
 hipError_t build_sinc_mfma_table(int half_width, double beta, void **dev, std::vector<void *> &allocs)
 {
@@ -410,22 +623,21 @@ hipError_t build_sinc_mfma_table(int half_width, double beta, void **dev, std::v
 }
 
 hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, int njobs, int64_t max_out,
-                            int half_width, const void *table, hipStream_t s, Profiler *prof)
+                            int64_t ntiles, void *work, int half_width, const void *table, hipStream_t s,
+                            Profiler *prof)
 {
     if (njobs <= 0 || max_out <= 0)
         return hipSuccess;
     const int64_t nblk = (max_out + kMfOut - 1) / kMfOut;
-    if (nblk > 0x7fffffff || njobs > 65535 || !table)
+    // the list holds 32-bit job and tile indices and is sorted in 32-bit counters
+    if (nblk > 0x7fffffff || njobs > 65535 || !table || ntiles <= 0 || ntiles > 0x7fffffff)
         return hipErrorInvalidValue;
+    if (work && !jobs_dev)
+        return hipErrorInvalidValue;  // the list kernels read the job array
     const SincJob inl = job_inline ? *job_inline : SincJob{};
     const unsigned char *t = static_cast<const unsigned char *>(table);
-    if (prof)
-        prof->begin(kKSincMfma, s);
-    hipError_t e = half_width == 64 ? launch_h<64>(jobs_dev, inl, njobs, nblk, t, s)
-                                    : launch_h<128>(jobs_dev, inl, njobs, nblk, t, s);
-    if (prof)
-        prof->end(s);
-    return e;
+    return half_width == 64 ? launch_h<64>(jobs_dev, inl, njobs, max_out, ntiles, work, t, s, prof)
+                            : launch_h<128>(jobs_dev, inl, njobs, max_out, ntiles, work, t, s, prof);
 }
 
 }  // namespace rc

@@ -290,6 +290,44 @@ def test_batch_c2_full_size_sampled(torch, ctx, orc):
         assert rel_l2(y[p * n:(p + 1) * n], ref) <= TOL, p
 
 
+def test_batch_tile_list_matches_single_calls(torch, ctx, orc):
+    """A ragged batch with more 2048-output matrix-core tiles than resident workgroups (the
+    persistent path over the tile list sorted by phase): every pulse equals, bit for bit, its
+    single-pulse call (one workgroup per tile), and sampled pulses match the oracle."""
+    import paper_2508_04951_amd as rc
+
+    rng = wf.rng_for(131, 0)
+    lens = [int(n) for n in rng.integers(1, 120000, size=40)] + [1, 2047, 2048, 2049, 1 << 17]
+    pulses, xs = [], []
+    off_in = off_out = 3
+    for i, n in enumerate(lens):
+        v = rng.uniform(-8800, 8800) if i % 9 else rng.uniform(9000, 12000)  # a few off the matrix cores
+        pulses.append(dict(off_in=off_in, n_in=n, off_out=off_out, n_out=n, fs=10e6, alpha=alpha_exact(v),
+                           tec=0.0, carrier=450e6, flags=1))
+        xs.append(wf.bandlimited_noise(n, wf.rng_for(131, i + 1)) if n > 1 else np.ones(1, np.complex64))
+        off_in += n + 7
+        off_out += n + 1
+    assert sum((n + 2047) // 2048 for n in lens) > 1100  # above any resident grid of 256 CUs x 4
+    xp = np.zeros(off_in, np.complex64)
+    for p, x in zip(pulses, xs):
+        xp[p["off_in"]:p["off_in"] + p["n_in"]] = x
+    xd = dev(torch, xp)
+    yd = torch.full((off_out,), complex("nan"), dtype=torch.complex64, device="cuda")
+    k = rc.Sinc(64, "kaiser", 8.0)
+    ctx.correct_pulse_batch(xd, yd, pulses, k)
+    yb = host(yd)
+    gaps = np.ones(off_out, bool)
+    for i, (p, x) in enumerate(zip(pulses, xs)):
+        got = yb[p["off_out"]:p["off_out"] + p["n_out"]]
+        gaps[p["off_out"]:p["off_out"] + p["n_out"]] = False
+        single = host(ctx.correct_doppler(dev(torch, x), p["alpha"], k))
+        assert np.array_equal(single, got), i
+        if i in (0, 5, 40, 43, 44):
+            ref = orc.doppler(x, p["alpha"], 64, "kaiser", 8.0)
+            assert rel_l2(got, ref) <= TOL, (i, rel_l2(got, ref))
+    assert np.isnan(yb[gaps]).all()
+
+
 def test_repeat_runs_are_bit_identical(torch, ctx):
     import paper_2508_04951_amd as rc
 
