@@ -165,8 +165,8 @@ rc_status rc_set_sinc_engine(rc_context ctx, int32_t engine);
  * the recorded events, adds their spans to per-kernel totals, and returns (then clears) the
  * total milliseconds and launch count of one kernel: "k_sinc_mfma", "k_sinc_fast",
  * "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono", "k_fft_strided_inv" or
- * "k_mf_tile_sort" (the two small kernels that sort a batch's matrix-core tiles by phase, timed
- * together as one launch).  Unknown names give
+ * "k_mf_tile_list" (the three small kernels that sort a batch's matrix-core tiles by phase,
+ * timed together as one launch).  Unknown names give
  * RC_ERR_INVALID_ARG.  Timing adds two event records per launch and no synchronisation. */
 rc_status rc_profile_enable(rc_context ctx, int enable);
 rc_status rc_profile_read(rc_context ctx, const char *kernel, double *total_ms, int64_t *launches);

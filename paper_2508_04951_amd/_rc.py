@@ -27,7 +27,7 @@ SYMBOLS = (
     "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine",
 )
 KERNELS = ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono",
-           "k_fft_strided_inv", "k_mf_tile_sort")
+           "k_fft_strided_inv", "k_mf_tile_list")
 SINC_ENGINES = {"auto": 0, "valu": 1, "direct": 2}
 
 

@@ -143,7 +143,7 @@ __device__ __forceinline__ void stage(float2 *lds, int log2L, int log2C, bool lc
             const int step = kFftTile / (Ns * R);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw[(r * k * step) & (kFftTile - 1)];
+                float2 w = gmem(tw)[(r * k * step) & (kFftTile - 1)];
                 if (S > 0)
                     w.y = -w.y;
                 v[p][r] = cmul(v[p][r], w);
@@ -267,9 +267,9 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided_reg(StridedArgs a)
     const int64_t rem = blk & ((int64_t(1) << a.log2pp) - 1);
     const int64_t o = rem >> a.log2cb;
     const int64_t col = ((rem & ((int64_t(1) << a.log2cb) - 1)) << 8) + threadIdx.x;  // n'
-    const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
+    const IonoJob jb = a.jobs ? gload(a.jobs, p) : a.inl;
     const int64_t base = o * (R * a.inner) + col;
-    const float2 *src = a.from_x ? jb.x : jb.y;
+    const auto src = gmem(a.from_x ? jb.x : jb.y);
     float2 v[R];
 #pragma unroll
     for (int l = 0; l < R; ++l)
@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided_reg(StridedArgs a)
     }
 #pragma unroll
     for (int l = 0; l < R; ++l)
-        jb.y[base + l * a.inner] = v[l];
+        gmem(jb.y)[base + l * a.inner] = v[l];
 }
 
 // Strided level of length 32..256: lines of length L along stride `inner`; the LDS tile holds
@@ -303,10 +303,10 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(StridedArgs a)
     const int64_t rem = blk & ((int64_t(1) << a.log2pp) - 1);
     const int64_t o = rem >> a.log2cb;
     const int64_t cb = rem & ((int64_t(1) << a.log2cb) - 1);
-    const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
+    const IonoJob jb = a.jobs ? gload(a.jobs, p) : a.inl;
     const int L = 1 << a.log2L, C = 1 << a.log2C;
     const int64_t base = o * ((int64_t)L * a.inner) + cb * C;
-    const float2 *src = a.from_x ? jb.x : jb.y;
+    const auto src = gmem(a.from_x ? jb.x : jb.y);
     for (int e = tid; e < kFftTile; e += kFftThreads) {
         const int c = e & (C - 1), l = e >> a.log2C;
         float2 v = src[base + (int64_t)l * a.inner + c];
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(StridedArgs a)
             v.x *= a.scale;
             v.y *= a.scale;
         }
-        jb.y[base + (int64_t)l * a.inner + c] = v;
+        gmem(jb.y)[base + (int64_t)l * a.inner + c] = v;
     }
 }
 
@@ -407,8 +407,8 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
     const int64_t g = blockIdx.x;
     const int p = (int)(g >> a.log2rpp);
     const int64_t r = g & ((int64_t(1) << a.log2rpp) - 1);
-    const IonoJob jb = a.jobs ? a.jobs[p] : a.inl;
-    const float2 *src = (a.from_x ? jb.x : jb.y) + (r << 12);
+    const IonoJob jb = a.jobs ? gload(a.jobs, p) : a.inl;
+    const auto src = gmem(a.from_x ? jb.x : jb.y) + (r << 12);
     float2 v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q)
@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
         v[q] = lds[rpad(j + 256 * q)];
     __syncthreads();
     row4096<+1>(v, lds, j, a.tw4096);
-    float2 *dst = jb.y + (r << 12);
+    const auto dst = gmem(jb.y) + (r << 12);
 #pragma unroll
     for (int q = 0; q < 16; ++q)
         dst[j + 256 * q] = make_float2(v[q].x * a.scale, v[q].y * a.scale);
@@ -461,8 +461,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_iono(RowArgs a)
         const int g = g0 + c;
         float2 v = make_float2(0.f, 0.f);
         if (g < a.njobs) {
-            const IonoJob jb = a.jobs ? a.jobs[g] : a.inl;
-            v = (a.from_x ? jb.x : jb.y)[l];
+            const IonoJob jb = a.jobs ? gload(a.jobs, g) : a.inl;
+            v = gmem(a.from_x ? jb.x : jb.y)[l];
         }
         lds[tidx(c, l, a.log2L, a.log2C, true)] = v;
     }
@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_iono(RowArgs a)
         const int g = g0 + c;
         if (g >= a.njobs)
             continue;
-        const IonoJob jb = a.jobs ? a.jobs[g] : a.inl;
+        const IonoJob jb = a.jobs ? gload(a.jobs, g) : a.inl;
         const int idx = tidx(c, l, a.log2L, a.log2C, true);
         lds[idx] = cmul(lds[idx], iono_phase(jb, l, a.n));
     }
@@ -484,11 +484,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_iono(RowArgs a)
         const int g = g0 + c;
         if (g >= a.njobs)
             continue;
-        const IonoJob jb = a.jobs ? a.jobs[g] : a.inl;
+        const IonoJob jb = a.jobs ? gload(a.jobs, g) : a.inl;
         float2 v = lds[tidx(c, l, a.log2L, a.log2C, true)];
         v.x *= a.scale;
         v.y *= a.scale;
-        jb.y[l] = v;
+        gmem(jb.y)[l] = v;
     }
 }
 

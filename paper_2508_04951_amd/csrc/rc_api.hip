@@ -632,7 +632,7 @@ namespace rc {
 
 const char *const kKernelNames[kKGroups] = {"k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd",
                                             "k_fft_rows_iono", "k_fft_strided_inv", "k_sinc_mfma",
-                                            "k_mf_tile_sort"};
+                                            "k_mf_tile_list"};
 
 hipEvent_t Profiler::take()
 {

@@ -64,6 +64,27 @@ struct KaiserPoly {
     double c[56];   // c[j] = (beta^2/4)^j / (j!)^2 / I0(beta)
 };
 
+// Global-memory view of a device pointer.  Kernels read their pointers from job descriptors,
+// so the compiler cannot tell them from LDS and emits flat accesses, which also count against
+// the LDS wait counter: every wait for an LDS result would then wait for outstanding HBM loads
+// too.  Accesses through this view compile to global_* instructions.
+#ifdef __HIP_DEVICE_COMPILE__
+#define RC_GLOBAL_AS __attribute__((address_space(1)))
+#else
+#define RC_GLOBAL_AS  // the host pass has no device address spaces
+#endif
+template <class T>
+__device__ __forceinline__ RC_GLOBAL_AS T *gmem(T *p)
+{
+    return (RC_GLOBAL_AS T *)p;
+}
+
+template <class T>
+__device__ __forceinline__ T gload(const T *p, int64_t i)
+{
+    return gmem(p)[i];
+}
+
 // One resampling job (one pulse).  Pointers are device addresses.
 struct SincJob {
     const float2 *x;

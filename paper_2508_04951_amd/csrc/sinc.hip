@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256)
 k_sinc_fast(const SincJob *__restrict__ jobs, SincJob inl, int H, KaiserPoly kp)
 {
     extern __shared__ float4 smem[];
-    const SincJob jb = jobs ? jobs[blockIdx.y] : inl;
+    const SincJob jb = jobs ? gload(jobs, blockIdx.y) : inl;
     const int64_t M0 = (int64_t)blockIdx.x * kSincWgOut;
     if (M0 >= jb.n_out)
         return;  // uniform over the workgroup
@@ -111,7 +111,7 @@ k_sinc_fast(const SincJob *__restrict__ jobs, SincJob inl, int H, KaiserPoly kp)
         const int64_t pos = lo + e;
         float2 v = make_float2(0.f, 0.f);
         if (pos >= 0 && pos < jb.n_in)
-            v = jb.x[pos];
+            v = gmem(jb.x)[pos];
         xs[xpad(e)] = v;
     }
 
@@ -185,7 +185,7 @@ k_sinc_fast(const SincJob *__restrict__ jobs, SincJob inl, int H, KaiserPoly kp)
             float2 r = make_float2(ar[i], ai[i]);
             if (exact[i])
                 r = xs[xpad(e0 + i + H)];
-            jb.y[m] = r;
+            gmem(jb.y)[m] = r;
         }
     }
 }
@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(256)
 k_sinc_direct(const SincJob *__restrict__ jobs, SincJob inl, int H, int window, KaiserPoly kp,
               int log2g)
 {
-    const SincJob jb = jobs ? jobs[blockIdx.y] : inl;
+    const SincJob jb = jobs ? gload(jobs, blockIdx.y) : inl;
     const int G = 1 << log2g;
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t m = gid >> log2g;
@@ -207,7 +207,7 @@ k_sinc_direct(const SincJob *__restrict__ jobs, SincJob inl, int H, int window, 
         if (t == f) {
             mode = 1;  // only lane 0 of the group carries the sample into the reduction
             if (sub == 0 && f < (double)jb.n_in) {
-                const float2 v = jb.x[(int64_t)f];
+                const float2 v = gmem(jb.x)[(int64_t)f];
                 re = v.x;
                 im = v.y;
             }
@@ -238,7 +238,7 @@ k_sinc_direct(const SincJob *__restrict__ jobs, SincJob inl, int H, int window, 
                 double w = (((n - fi) & 1) ? -sp : sp) / (kPi * u);
                 if (taper)
                     w *= kaiser_at(kp, u * inv_h);
-                const float2 v = jb.x[n];
+                const float2 v = gmem(jb.x)[n];
                 re = fma((double)v.x, w, re);
                 im = fma((double)v.y, w, im);
             }
@@ -249,7 +249,7 @@ k_sinc_direct(const SincJob *__restrict__ jobs, SincJob inl, int H, int window, 
         im += __shfl_xor(im, o, 64);
     }
     if (mode != 0 && sub == 0)
-        jb.y[m] = make_float2((float)re, (float)im);
+        gmem(jb.y)[m] = make_float2((float)re, (float)im);
 }
 
 }  // namespace

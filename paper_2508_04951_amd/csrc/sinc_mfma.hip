@@ -22,9 +22,9 @@
 // input, take hi*hi alone (11 bits).
 //
 // Batches of many tiles run persistent workgroups over a tile list sorted by phase (built on the
-// device by k_mf_tile_phase + k_mf_tile_sort): a workgroup walks a run of that list, copies a
-// phase's B block into LDS only when the phase changes, and prefetches the next tile's input
-// into registers while the matrix cores work on the current one.  Consecutive workgroup indices
+// device by k_mf_tile_phase, k_mf_tile_count and k_mf_tile_scatter): a workgroup walks a run of
+// that list, copies a phase's B block into LDS only when the phase changes, and prefetches the
+// next tile's input into registers while the matrix cores work on the current one.  Consecutive workgroup indices
 // are spread over the eight XCDs, so each XCD's L2 serves a contiguous range of phases.
 #include <cmath>
 #include <vector>
@@ -171,7 +171,7 @@ __device__ __forceinline__ MfTile mf_tile(double alpha, int64_t M0)
 __global__ void __launch_bounds__(256)
 k_mf_tile_phase(const SincJob *__restrict__ jobs, uint2 *__restrict__ ref, unsigned char *__restrict__ phase)
 {
-    const SincJob jb = jobs[blockIdx.y];
+    const SincJob jb = gload(jobs, blockIdx.y);
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t * kMfOut >= jb.n_out)
         return;
@@ -180,36 +180,85 @@ k_mf_tile_phase(const SincJob *__restrict__ jobs, uint2 *__restrict__ ref, unsig
     phase[jb.tile0 + t] = (unsigned char)(tp.p + kPhases / 2);
 }
 
-// Tile list, step 2 (one workgroup): counting sort of the references by phase.  The order of
+// Tile list, steps 2 and 3: a counting sort of the references by phase over chunks of
+// kSortChunk tiles, one workgroup per chunk.  Step 2 counts each chunk's phases; step 3 turns
+// the counts of all chunks into the chunk's first slot per phase and scatters.  The order of
 // equal phases is arbitrary; no output depends on it.
-__global__ void __launch_bounds__(1024)
-k_mf_tile_sort(const uint2 *__restrict__ ref, const unsigned char *__restrict__ phase, int64_t ntiles,
-               uint2 *__restrict__ list)
+constexpr int kSortChunk = 256;
+
+__global__ void __launch_bounds__(256)
+k_mf_tile_count(const unsigned char *__restrict__ phase, int64_t ntiles, unsigned *__restrict__ counts)
 {
     __shared__ unsigned cnt[kPhaseRows];
     const int tid = threadIdx.x;
-    for (int i = tid; i < kPhaseRows; i += 1024)
-        cnt[i] = 0;
+    if (tid < kPhaseRows)
+        cnt[tid] = 0;
     __syncthreads();
-    for (int64_t i = tid; i < ntiles; i += 1024)
+    const int64_t i0 = (int64_t)blockIdx.x * kSortChunk;
+    const int64_t i1 = i0 + kSortChunk < ntiles ? i0 + kSortChunk : ntiles;
+    for (int64_t i = i0 + tid; i < i1; i += 256)
         atomicAdd(&cnt[phase[i]], 1u);
+    __syncthreads();
+    if (tid < kPhaseRows)
+        counts[(size_t)blockIdx.x * kPhaseRows + tid] = cnt[tid];
+}
+
+__global__ void __launch_bounds__(256)
+k_mf_tile_scatter(const uint2 *__restrict__ ref, const unsigned char *__restrict__ phase, int64_t ntiles,
+                  const unsigned *__restrict__ counts, uint2 *__restrict__ list)
+{
+    __shared__ unsigned tot[kPhaseRows], base[kPhaseRows];
+    const int tid = threadIdx.x;
+    const int nchunks = gridDim.x, me = blockIdx.x;
+    if (tid < kPhaseRows) {
+        unsigned all = 0, before = 0;
+        for (int w = 0; w < nchunks; ++w) {
+            const unsigned c = counts[(size_t)w * kPhaseRows + tid];
+            all += c;
+            before += w < me ? c : 0u;
+        }
+        tot[tid] = all;
+        base[tid] = before;
+    }
     __syncthreads();
     if (tid == 0) {
         unsigned run = 0;
-        for (int i = 0; i < kPhaseRows; ++i) {
-            const unsigned c = cnt[i];
-            cnt[i] = run;
-            run += c;
+        for (int p = 0; p < kPhaseRows; ++p) {
+            base[p] += run;
+            run += tot[p];
         }
     }
     __syncthreads();
-    for (int64_t i = tid; i < ntiles; i += 1024)
-        list[atomicAdd(&cnt[phase[i]], 1u)] = ref[i];
+    const int64_t i0 = (int64_t)me * kSortChunk;
+    const int64_t i1 = i0 + kSortChunk < ntiles ? i0 + kSortChunk : ntiles;
+    for (int64_t i = i0 + tid; i < i1; i += 256)
+        list[atomicAdd(&base[phase[i]], 1u)] = ref[i];
+}
+
+// Lane l takes lane l + 2 of the same 16-lane row (DPP row_shl:2); lanes 14 and 15 of a row
+// keep `fill`.
+__device__ __forceinline__ half8 rows_up2(half8 fill, half8 v)
+{
+    typedef int int4v __attribute__((ext_vector_type(4)));
+    const int4v f = __builtin_bit_cast(int4v, fill), w = __builtin_bit_cast(int4v, v);
+    int4v r;
+    r.x = __builtin_amdgcn_update_dpp(f.x, w.x, 0x102, 0xf, 0xf, false);
+    r.y = __builtin_amdgcn_update_dpp(f.y, w.y, 0x102, 0xf, 0xf, false);
+    r.z = __builtin_amdgcn_update_dpp(f.z, w.z, 0x102, 0xf, 0xf, false);
+    r.w = __builtin_amdgcn_update_dpp(f.w, w.w, 0x102, 0xf, 0xf, false);
+    return __builtin_bit_cast(half8, r);
 }
 
 // The resampling GEMM.  Without a list, workgroup (x, y) computes tile x of job y.  With a list,
 // the grid is persistent: workgroup b takes the run c(b) of the sorted list, where c deals
 // consecutive b to different XCDs so that an XCD holds a contiguous range of phases.
+// A tile of the persistent loop: its job, first output and position in the input.
+struct MfCur {
+    SincJob jb;
+    int64_t M0;
+    MfTile tp;
+};
+
 template <int H>
 __global__ void __launch_bounds__(256, 2)
 k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restrict__ list, int64_t ntiles,
@@ -234,45 +283,49 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
         if (i0 >= i1)
             return;  // uniform over the workgroup
     }
-    auto tile_at = [&](int64_t i, SincJob &jb, int64_t &M0) {
+    auto tile_at = [&](int64_t i) {
+        MfCur t;
         if (list) {
-            const uint2 e = list[i];
-            jb = jobs[e.x];
-            M0 = (int64_t)e.y * kMfOut;
+            const uint2 e = gload(list, i);
+            t.jb = gload(jobs, e.x);
+            t.M0 = (int64_t)e.y * kMfOut;
         } else {
-            jb = jobs ? jobs[blockIdx.y] : inl;
-            M0 = (int64_t)blockIdx.x * kMfOut;
+            t.jb = jobs ? gload(jobs, blockIdx.y) : inl;
+            t.M0 = (int64_t)blockIdx.x * kMfOut;
         }
+        t.tp = mf_tile(t.jb.alpha, t.M0);
+        return t;
     };
-    // the input span of a tile: samples lo .. lo + span - 1, two per thread and step
+
+    // The input span of a tile, samples lo .. lo + span - 1, is fetched into registers (two
+    // per thread and step) one tile ahead.
     float2 xv[G::spp][2];
-    auto fetch = [&](const SincJob &jb, int64_t lo) {
-        const bool whole = lo >= 0 && lo + G::span <= jb.n_in;  // no sample of the span is outside x
-        const float2 *xs = jb.x + lo;
+    auto fetch = [&](const MfCur &t) {
+        const int64_t lo = t.M0 + (int64_t)t.tp.Sd - H;
+        const int64_t last = t.jb.n_in - 1;
+        const auto xs = gmem(t.jb.x);
+        // every lane loads an in-bounds sample (index clamped) and zeroes what lies outside x
+        // or past the span: no branch between the loads
 #pragma unroll
         for (int q = 0; q < G::spp; ++q) {
-            const int e = 2 * tid + 512 * q;
 #pragma unroll
             for (int h2 = 0; h2 < 2; ++h2) {
-                float2 v = make_float2(0.f, 0.f);
-                if (e + h2 < G::span && (whole || (lo + e + h2 >= 0 && lo + e + h2 < jb.n_in)))
-                    v = xs[e + h2];
-                xv[q][h2] = v;
+                const int e = 2 * tid + 512 * q + h2;
+                const int64_t g = lo + e;
+                const bool ok = e < G::span && g >= 0 && g <= last;
+                const int64_t gc = g < 0 ? 0 : (g > last ? last : g);
+                const float2 v = xs[gc];
+                xv[q][h2] = ok ? v : make_float2(0.f, 0.f);
             }
         }
     };
 
-    SincJob jb;
-    int64_t M0;
-    tile_at(i0, jb, M0);
-    if (M0 >= jb.n_out)
-        return;  // only without a list (ragged jobs); uniform over the workgroup
-    MfTile tp = mf_tile(jb.alpha, M0);
-    fetch(jb, M0 + (int64_t)tp.Sd - H);
+    // Staging of the fetched span into LDS for phase p; returns the scale exponent.  Every wave
+    // must be done with the LDS operands of the previous tile (the barrier inside ensures it
+    // before anything is overwritten).
     int cur_p = kPhaseRows;  // no B block in LDS yet
-
-    for (int64_t i = i0; i < i1; ++i) {
-        // 1) largest component of the fetched span
+    auto stage = [&](int p) {
+        // largest component of the span
         float mx = 0.f;
 #pragma unroll
         for (int q = 0; q < G::spp; ++q)
@@ -283,18 +336,42 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
             mx = fmaxf(mx, __shfl_xor(mx, o, 64));
         if (lane == 0)
             wmax[wave] = mx;
-        __syncthreads();  // every wave is done with the previous tile's A and B
-
-        // 2) this phase's B fragments, unless they are in LDS already (uniform branch)
-        if (tp.p != cur_p) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(table + (size_t)(tp.p + kPhases / 2) * G::bbytes);
+        __syncthreads();
+        // this phase's B fragments, unless they are in LDS already (uniform branch); the loads
+        // of a round are all issued before the first is waited for
+        if (p != cur_p) {
+            const auto src = gmem(reinterpret_cast<const uint4 *>(table + (size_t)(p + kPhases / 2) * G::bbytes));
             uint4 *dst = reinterpret_cast<uint4 *>(bsm);
-            for (int k = tid; k < G::bbytes / 16; k += 256)
-                dst[k] = src[k];
-            cur_p = tp.p;
+            constexpr int n16 = G::bbytes / 16, per = 8, full = n16 / (per * 256);
+            constexpr int tail = (n16 - full * per * 256 + 255) / 256;
+#pragma unroll 1
+            for (int k0 = 0; k0 < full * per * 256; k0 += per * 256) {
+                uint4 v[per];
+#pragma unroll
+                for (int u = 0; u < per; ++u)
+                    v[u] = src[k0 + u * 256 + tid];
+#pragma unroll
+                for (int u = 0; u < per; ++u)
+                    dst[k0 + u * 256 + tid] = v[u];
+            }
+            if (tail > 0) {
+                constexpr int k0 = full * per * 256;
+                uint4 v[tail > 0 ? tail : 1];
+#pragma unroll
+                for (int u = 0; u < tail; ++u) {
+                    const int k = k0 + u * 256 + tid;
+                    v[u] = src[k < n16 ? k : n16 - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < tail; ++u) {
+                    const int k = k0 + u * 256 + tid;
+                    if (k < n16)
+                        dst[k] = v[u];
+                }
+            }
+            cur_p = p;
         }
-
-        // 3) scale by a power of two (largest component in [2^10, 2^11)) and split into fp16 hi/lo
+        // scale by a power of two (largest component in [2^10, 2^11)), split into fp16 hi/lo
         const float wm = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
         int xe = 0;
         if (wm > 0.f) {
@@ -319,49 +396,54 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
                 *reinterpret_cast<half2v *>(a_il + e) = il;
             }
         }
+        return xe;
+    };
 
-        // 4) start fetching the next tile; its loads fly while the matrix cores work on this one
-        const SincJob cj = jb;
-        const int64_t cM0 = M0;
-        const MfTile ct = tp;
-        if (i + 1 < i1) {
-            tile_at(i + 1, jb, M0);
-            tp = mf_tile(jb.alpha, M0);
-            fetch(jb, M0 + (int64_t)tp.Sd - H);
-        }
-        __syncthreads();  // A and B are in LDS
+    MfCur cur = tile_at(i0);
+    if (cur.M0 >= cur.jb.n_out)
+        return;  // only without a list (ragged jobs); uniform over the workgroup
+    fetch(cur);
+    int xe = stage(cur.tp.p);
+    MfCur nxt = cur;
+    if (i0 + 1 < i1) {
+        nxt = tile_at(i0 + 1);
+        fetch(nxt);
+    }
+    __syncthreads();  // the first tile's A and B are in LDS
 
-        // 5) the GEMM.  Wave w owns sub-tiles w and w + 4 and runs them together: each B
+    // Per tile: the matrix products, then the next tile's staging and the fetch of the one after
+    // (its loads are issued before this tile's stores, and both are waited for only after the
+    // next tile's products), then this tile's stores.
+    for (int64_t i = i0; i < i1; ++i) {
+        const bool active = cur.M0 + 256 * wave < cur.jb.n_out;  // uniform over the wave
+        floatx4 acc[2][kMfOrders][2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < kMfOrders; ++r)
+                acc[t][r][0] = acc[t][r][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+        // 1) the GEMM.  Wave w owns sub-tiles w and w + 4 and runs them together: each B
         //    fragment is read from LDS once per 32-tap step for both.
-        if (cM0 + 256 * wave < cj.n_out) {  // uniform over the wave
-            const double alpha = cj.alpha, eps = alpha - 1.0;
-            const int64_t S = (int64_t)ct.Sd;
-            const float unscale = ldexpf(1.0f, -(xe + kCoefExp));
-            // z_m = (sigma_m - sigma_p) / delta_max = z_c + (m - mcen) eps / delta_max
-            const float zc = (float)((ct.sc - (double)ct.p / kPhases) / kDeltaMax);
-            const float zstep = (float)(eps / kDeltaMax);
-            const float sc32 = (float)ct.sc;
-            const float e32 = (float)eps;
-
-            floatx4 acc[2][kMfOrders][2];
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int r = 0; r < kMfOrders; ++r)
-                    acc[t][r][0] = acc[t][r][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (active) {
+            // A fragments: lane (i, q) = (l % 16, l / 16) holds the 8 samples at
+            // 16 i + 8 q + 32 s of its sub-tile's span.  The Hankel structure gives the next step
+            // for free: row i at step s + 1 is row i + 2 at step s, a 2-lane shift inside each
+            // 16-lane DPP row; only rows 14 and 15 read new samples from LDS.
             const int arow = 256 * wave + 16 * (lane & 15) + 8 * (lane >> 4);
+            const bool edge = (lane & 15) >= 14;
+            half8 xh[2][2], xl[2][2];  // [sub-tile][re/im]
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int e = arow + 1024 * t;
+                xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
+                xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
+                xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
+                xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
+            }
             // not unrolled: hoisting the next step's fragments would cost the second wave per SIMD
 #pragma unroll 1
             for (int s = 0; s < G::ksteps; ++s) {
-                half8 xh[2][2], xl[2][2];  // [sub-tile][re/im]
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int e = arow + 1024 * t + 32 * s;
-                    xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
-                    xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
-                    xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
-                    xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
-                }
                 const half8 *blk = reinterpret_cast<const half8 *>(bsm + s * kMfBlk * 1024);
                 half8 bh[kMfOrders], bl[kMfLo];
 #pragma unroll
@@ -393,44 +475,99 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
 #pragma unroll
                         for (int c = 0; c < 2; ++c)
                             acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl[t][c], bh[r], acc[t][r][c], 0, 0, 0);
+                if (s + 1 < G::ksteps) {
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            xh[t][c] = rows_up2(xh[t][c], xh[t][c]);
+                            xl[t][c] = rows_up2(xl[t][c], xl[t][c]);
+                        }
+                    if (edge) {
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) {
+                            const int e = arow + 1024 * t + 32 * (s + 1);
+                            xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
+                            xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
+                            xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
+                            xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
+                        }
+                    }
+                }
             }
+        }
 
-            // 6) lane holds Z_r[row 4 (l/16) + j][col l % 16] of each sub-tile: output
-            //    m = M0 + 256 sub + 16 row + col.  z is linear in m; the float64 position is
-            //    recomputed only next to an exact sample instant (sigma within 1e-5 of 0), where
-            //    alpha m may round to an integer.
+        // 2) the next tile into LDS (after every wave's products: the barrier in stage), and the
+        //    fetch of the tile after it
+        const int cxe = xe;
+        const MfCur c = cur;
+        if (i + 1 < i1) {
+            xe = stage(nxt.tp.p);
+            cur = nxt;
+            if (i + 2 < i1) {
+                nxt = tile_at(i + 2);
+                fetch(nxt);
+            }
+        }
+
+        // 3) lane holds Z_r[row 4 (l/16) + j][col l % 16] of each sub-tile: output
+        //    m = M0 + 256 sub + 16 row + col.  z is linear in m.  Outputs next to an exact
+        //    sample instant (sigma within 1e-5 of 0), where alpha m may round to an integer,
+        //    are checked in float64 and, if exact, rewritten with the input sample after all
+        //    stores are issued (a load between the stores would make each store wait).
+        if (active) {
+            const double alpha = c.jb.alpha, eps = alpha - 1.0;
+            const int64_t S = (int64_t)c.tp.Sd;
+            const float unscale = ldexpf(1.0f, -(cxe + kCoefExp));
+            // z_m = (sigma_m - sigma_p) / delta_max = z_c + (m - mcen) eps / delta_max
+            const float zc = (float)((c.tp.sc - (double)c.tp.p * (1.0 / kPhases)) * (1.0 / kDeltaMax));
+            const float zstep = (float)(eps * (1.0 / kDeltaMax));
+            const float sc32 = (float)c.tp.sc;
+            const float e32 = (float)eps;
+            const auto yg = gmem(c.jb.y);
+            unsigned near = 0;  // bit 4 t + j: output (t, j) is next to an exact instant
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int off = 256 * (wave + 4 * t) + 16 * (4 * (lane >> 4) + j) + (lane & 15);  // m - M0
-                    const int64_t m = cM0 + off;
-                    if (m >= cj.n_out)
+                    const int64_t m = c.M0 + off;
+                    if (m >= c.jb.n_out)
                         continue;
                     const float dm = (float)off - (float)kMfHalf;
                     const float z = fmaf(dm, zstep, zc);
-                    bool exact = false;
-                    if (fabsf(fmaf(dm, e32, sc32)) < 1e-5f) {
-                        const double md = (double)m;
-                        exact = ((__dmul_rn(alpha, md) - md) - ct.Sd) == 0.0;
-                    }
-                    float2 out;
-                    if (exact) {
-                        const int64_t src = m + S;
-                        out = (src >= 0 && src < cj.n_in) ? cj.x[src] : make_float2(0.f, 0.f);
-                    } else {
-                        float yr = acc[t][kMfOrders - 1][0][j], yi = acc[t][kMfOrders - 1][1][j];
+                    if (fabsf(fmaf(dm, e32, sc32)) < 1e-5f)
+                        near |= 1u << (4 * t + j);
+                    float yr = acc[t][kMfOrders - 1][0][j], yi = acc[t][kMfOrders - 1][1][j];
 #pragma unroll
-                        for (int r = kMfOrders - 2; r >= 0; --r) {
-                            yr = fmaf(yr, z, acc[t][r][0][j]);
-                            yi = fmaf(yi, z, acc[t][r][1][j]);
-                        }
-                        out = make_float2(yr * unscale, yi * unscale);
+                    for (int r = kMfOrders - 2; r >= 0; --r) {
+                        yr = fmaf(yr, z, acc[t][r][0][j]);
+                        yi = fmaf(yi, z, acc[t][r][1][j]);
                     }
-                    cj.y[m] = out;
+                    yg[m] = make_float2(yr * unscale, yi * unscale);
+                }
+            }
+            if (__any(near != 0)) {  // rare: uniform over the wave
+                const auto xg = gmem(c.jb.x);
+#pragma unroll 1
+                for (int b = 0; b < 8; ++b) {
+                    if (!((near >> b) & 1u))
+                        continue;
+                    const int t = b >> 2, j = b & 3;
+                    const int64_t m = c.M0 + 256 * (wave + 4 * t) + 16 * (4 * (lane >> 4) + j) + (lane & 15);
+                    const double md = (double)m;
+                    if (((__dmul_rn(alpha, md) - md) - c.tp.Sd) == 0.0) {
+                        const int64_t src = m + S;
+                        float2 v = make_float2(0.f, 0.f);
+                        if (src >= 0 && src < c.jb.n_in)
+                            v = xg[src];
+                        yg[m] = v;
+                    }
                 }
             }
         }
+        if (i + 1 < i1)
+            __syncthreads();  // the next tile's A and B are in LDS
     }
 }
 
@@ -537,9 +674,11 @@ hipError_t resident_wgs(int64_t *n)
     return e;
 }
 
-// workspace: [ref: uint2 x n][list: uint2 x n][phase: u8 x n]
+// workspace: [ref: uint2 x n][list: uint2 x n][counts: u32 x 129 x chunks][phase: u8 x n]
+int64_t sort_chunks(int64_t n) { return (n + kSortChunk - 1) / kSortChunk; }
 size_t work_list_off(int64_t n) { return (size_t)n * 8; }
-size_t work_phase_off(int64_t n) { return (size_t)n * 16; }
+size_t work_counts_off(int64_t n) { return (size_t)n * 16; }
+size_t work_phase_off(int64_t n) { return work_counts_off(n) + (size_t)sort_chunks(n) * kPhaseRows * 4; }
 
 template <int H>
 hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int64_t max_out, int64_t ntiles,
@@ -574,8 +713,14 @@ hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int6
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_mf_tile_sort, dim3(1), dim3(1024), 0, s, ref, phase, ntiles, list);
+    unsigned *counts = reinterpret_cast<unsigned *>(w + work_counts_off(ntiles));
+    const unsigned nch = (unsigned)sort_chunks(ntiles);
+    hipLaunchKernelGGL(k_mf_tile_count, dim3(nch), dim3(256), 0, s, phase, ntiles, counts);
     e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_mf_tile_scatter, dim3(nch), dim3(256), 0, s, ref, phase, ntiles, counts, list);
+        e = hipGetLastError();
+    }
     if (prof)
         prof->end(s);
     if (e != hipSuccess)
