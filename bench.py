@@ -57,17 +57,70 @@ def make_workload(pulses: int):
     return x, desc
 
 
+MFMA_FP16_PEAK_TFLOPS = 2500.0   # dense fp16 matrix-core peak
+MFMA_FLOP = 16 * 16 * 32 * 2      # one v_mfma_f32_16x16x32_f16
+MFMA_CYCLES = 16                  # its issue interval at the full fp16 rate
+CLOCK_HZ = 2.4e9
+MF_TILE = 2048
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sinc_mfma_c2_traffic.md")
+KERNEL_SOURCES = {"k_sinc_mfma": ["paper_2508_04951_amd/csrc/sinc_mfma.hip", "paper_2508_04951_amd/csrc/rc_internal.h"]}
+
+
+def source_sha(kernel: str):
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken on the current
+    source of the kernel (else None)."""
+    if not os.path.exists(TRAFFIC_FILE) or kernel not in KERNEL_SOURCES:
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != source_sha(kernel):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def roofline_for(kernel: str, avg_ms: float, samples: int, half_width: int, passes_per_kernel: float):
     """Algorithmic work of one launch of `kernel` divided by its average duration."""
-    if kernel in ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct"):
-        flops = 8.0 * half_width * samples  # 2H taps x (2 FMA = 4 flop) per output sample
-        achieved = flops / (avg_ms * 1e-3) / 1e12
+    t = avg_ms * 1e-3
+    if kernel == "k_sinc_mfma":
+        flops = 8.0 * half_width * samples  # 2H taps x (2 real FMA = 4 flop) per output sample
+        achieved = flops / t / 1e12
+        ksteps = -(-(2 * half_width + 16) // 32)
+        tiles = samples / MF_TILE
+        mfma = tiles * 4 * ksteps * 36  # 4 waves x steps x (5 hi*hi + 2 hi*lo + 2 lo*hi) x 4 (sub-tile, re/im)
+        return {"kernel": kernel, "bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_FP16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / MFMA_FP16_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(kernel), "traffic_unit": "bytes/launch",
+                "algorithmic_bytes_per_launch": BYTES_PER_SAMPLE_PASS * samples, "algorithmic_per_launch": flops,
+                "avg_launch_ms": round(avg_ms, 4),
+                "mfma_issued_flops_per_launch": mfma * MFMA_FLOP,
+                "mfma_issue_frac": round(mfma / 1024 * MFMA_CYCLES / CLOCK_HZ / t, 4),
+                "hbm_algorithmic_gbs": round(BYTES_PER_SAMPLE_PASS * samples / t / 1e9, 1)}
+    if kernel in ("k_sinc_fast", "k_sinc_direct"):
+        flops = 8.0 * half_width * samples
+        achieved = flops / t / 1e12
         return {"kernel": kernel, "bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "frac_of_nonpacked_peak": round(achieved / FP32_NONPACKED_TFLOPS, 4),
                 "algorithmic_per_launch": flops, "avg_launch_ms": round(avg_ms, 4), "traffic": None}
     bytes_ = BYTES_PER_SAMPLE_PASS * samples * passes_per_kernel
-    achieved = bytes_ / (avg_ms * 1e-3) / 1e9
+    achieved = bytes_ / t / 1e9
     return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_per_launch": bytes_,
             "avg_launch_ms": round(avg_ms, 4), "traffic": None}

@@ -130,8 +130,10 @@ rc_status correct_doppler(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 
  *   y = IDFT_n( DFT_n(x) * exp(s i 4 pi K2 / (c f_k)) ),  s = -1 (RC_CORRECT) or +1,
  *   f_k = carrier_hz + fs_hz * fftfreq(n)[k]; bins with f_k == 0 keep their value.
  * DFT unnormalised, IDFT scaled by 1/n, both circular over the n given samples.
- * n must be a power of two (this build); y may equal x (in place) but must not
- * partially overlap it. */
+ * Any n >= 1: powers of two up to 2^24 run a multi-level FFT, other lengths up to 2^23 the
+ * same N-point DFT by Bluestein's chirp convolution at the power of two >= 2n - 1 (its
+ * workspace comes from the context); longer pulses give RC_ERR_UNSUPPORTED.  y may equal x
+ * (in place) but must not partially overlap it. */
 rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n,
                              double fs_hz, double carrier_hz, double tec_el_per_m2,
                              int32_t direction, void *stream);

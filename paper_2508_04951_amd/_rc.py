@@ -62,6 +62,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             return _lib
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is missing: build it with `python -m paper_2508_04951_amd.build`")
+        # torch ships its own HIP runtime; loading it first makes librc.so bind to that same
+        # runtime, so tensors and streams from torch are valid in the library's calls.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(path)
         c_i32, c_i64, c_d, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
         lib.rc_create.argtypes = [ctypes.c_int, ctypes.POINTER(p)]

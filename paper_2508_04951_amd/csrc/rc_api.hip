@@ -36,6 +36,19 @@ bool overlaps(const void *a, int64_t abytes, const void *b, int64_t bbytes)
 
 bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
 
+// Power-of-two lengths run the multi-level FFT directly (up to 2^24); other lengths run
+// Bluestein at the power of two m >= 2n - 1 (so up to 2^23).
+constexpr int64_t kMaxIonoLength = int64_t(1) << 24;
+int64_t iono_plan_length(int64_t n)
+{
+    if (is_pow2(n))
+        return n;
+    int64_t m = 1;
+    while (m < 2 * n - 1)
+        m <<= 1;
+    return m;
+}
+
 rc_status check_sinc(rc_context ctx, const rc_sinc *k)
 {
     if (!k)
@@ -382,17 +395,33 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
         return fail(ctx, RC_ERR_INVALID_ARG, "direction must be RC_CORRECT or RC_DISTORT");
     if (x != y && overlaps(x, n * 8, y, n * 8))
         return fail(ctx, RC_ERR_INVALID_ARG, "x and y partially overlap");
-    if (!is_pow2(n))
-        return fail(ctx, RC_ERR_UNSUPPORTED, "n must be a power of two in this build");
+    if (n > kMaxIonoLength)
+        return fail(ctx, RC_ERR_UNSUPPORTED, "n above 2^24 (power of two) or 2^23 (other lengths)");
     DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double phase = phase_numerator(tec_el_per_m2, direction);
+    const float2 *xf = reinterpret_cast<const float2 *>(x);
+    float2 *yf = reinterpret_cast<float2 *>(y);
     const FftPlan *plan = nullptr;
-    rc_status st = get_plan(ctx, n, &plan);
+    rc_status st = get_plan(ctx, iono_plan_length(n), &plan);
     if (st != RC_OK)
         return st;
-    const IonoJob job{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y),
-                      phase_numerator(tec_el_per_m2, direction), carrier_hz, fs_hz};
-    hipError_t e = rc::launch_iono(*plan, ctx->tw4096, nullptr, &job, 1, static_cast<hipStream_t>(stream),
-                                   prof_of(ctx));
+    hipError_t e;
+    if (is_pow2(n)) {
+        const IonoJob job{xf, yf, phase, carrier_hz, fs_hz, nullptr};
+        e = rc::launch_iono(*plan, ctx->tw4096, nullptr, &job, 1, s, prof_of(ctx));
+    } else {
+        // Bluestein: its workspace is a staging slot, reused only after this work completes
+        const void *dev = nullptr;
+        st = stage_descriptors(ctx, nullptr, 0, rc::bluestein_work_bytes(n), s, &dev);
+        if (st != RC_OK)
+            return st;
+        e = rc::launch_iono_bluestein(n, *plan, ctx->tw4096, xf, yf, phase, carrier_hz, fs_hz,
+                                      const_cast<void *>(dev), s, prof_of(ctx));
+        st = mark_descriptors_used(ctx, s);
+        if (e == hipSuccess && st != RC_OK)
+            return st;
+    }
     if (e != hipSuccess)
         return device_fail(ctx, e, "correct_ionosphere launch");
     return RC_OK;
@@ -439,8 +468,8 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
                 return fail(ctx, RC_ERR_INVALID_ARG, at + "tec must be finite and >= 0, carrier finite");
             if (p.direction != RC_CORRECT && p.direction != RC_DISTORT)
                 return fail(ctx, RC_ERR_INVALID_ARG, at + "bad direction");
-            if (!is_pow2(p.n_out))
-                return fail(ctx, RC_ERR_UNSUPPORTED, at + "iono length must be a power of two in this build");
+            if (p.n_out > kMaxIonoLength || (!is_pow2(p.n_out) && 2 * p.n_out - 1 > kMaxIonoLength))
+                return fail(ctx, RC_ERR_UNSUPPORTED, at + "iono length above 2^24 (power of two) or 2^23 (other)");
         }
         outs.emplace_back(p.off_out, p.off_out + p.n_out);
     }
@@ -487,11 +516,14 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
     }
     if (mfma.size() > 65535 || fast.size() > 65535 || direct.size() > 65535)
         return fail(ctx, RC_ERR_UNSUPPORTED, "more than 65535 pulses of one kind in a batch");
+    size_t bs_work = 0;  // Bluestein workspace: one region, reused by the pulses in stream order
     for (auto &kv : iono) {
         const FftPlan *plan = nullptr;
-        st = get_plan(ctx, kv.first, &plan);
+        st = get_plan(ctx, iono_plan_length(kv.first), &plan);
         if (st != RC_OK)
             return st;
+        if (!is_pow2(kv.first))
+            bs_work = std::max(bs_work, rc::bluestein_work_bytes(kv.first));
     }
     const void *mfma_table = nullptr;
     int64_t mfma_tiles = 0;
@@ -522,16 +554,21 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
     const size_t off_fast = fast.empty() ? 0 : append(fast.data(), fast.size() * sizeof(SincJob));
     const size_t off_direct = direct.empty() ? 0 : append(direct.data(), direct.size() * sizeof(SincJob));
     std::vector<size_t> off_iono;
-    for (auto &kv : iono)
-        off_iono.push_back(append(kv.second.data(), kv.second.size() * sizeof(IonoJob)));
+    for (auto &kv : iono)  // Bluestein lengths run from the host copies of their descriptors
+        off_iono.push_back(is_pow2(kv.first) ? append(kv.second.data(), kv.second.size() * sizeof(IonoJob)) : 0);
+    // device workspace after the descriptors: [tile list][Bluestein]
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t extra = mfma_work || bs_work ? al(mfma_work) + bs_work : 0;
     const void *dev = nullptr;
-    if (!blob.empty()) {
-        st = stage_descriptors(ctx, blob.data(), blob.size(), mfma_work, s, &dev);
+    if (!blob.empty() || extra) {
+        st = stage_descriptors(ctx, blob.data(), blob.size(), extra, s, &dev);
         if (st != RC_OK)
             return st;
     }
     char *devc = static_cast<char *>(const_cast<void *>(dev));
-    void *work = mfma_work ? devc + ((blob.size() + 255) & ~(size_t)255) : nullptr;
+    char *wbase = extra ? devc + al(blob.size()) : nullptr;
+    void *work = mfma_work ? wbase : nullptr;
+    void *bwork = bs_work ? wbase + al(mfma_work) : nullptr;
     // from here on the slot is in use: mark it whatever happens
     struct SlotMark {
         rc_context ctx;
@@ -542,7 +579,7 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
             if (armed)
                 (void)mark_descriptors_used(ctx, s);
         }
-    } slot_mark{ctx, s, !blob.empty()};
+    } slot_mark{ctx, s, dev != nullptr};
     hipError_t e = hipSuccess;
     for (int32_t i : copies) {
         const rc_pulse &p = pulses[i];
@@ -565,9 +602,19 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
     size_t gi = 0;
     for (auto &kv : iono) {
         const FftPlan *plan = nullptr;
-        st = get_plan(ctx, kv.first, &plan);
+        st = get_plan(ctx, iono_plan_length(kv.first), &plan);
         if (st != RC_OK)
             return st;
+        if (!is_pow2(kv.first)) {
+            ++gi;
+            for (const IonoJob &jb : kv.second) {
+                e = rc::launch_iono_bluestein(kv.first, *plan, ctx->tw4096, jb.x, jb.y, jb.phase_num, jb.carrier,
+                                              jb.fs, bwork, s, prof_of(ctx));
+                if (e != hipSuccess)
+                    return device_fail(ctx, e, "batch ionosphere launch");
+            }
+            continue;
+        }
         const IonoJob *jd = reinterpret_cast<const IonoJob *>(devc + off_iono[gi++]);
         // at most 65535 pulses per launch keeps every grid dimension in range
         for (size_t b = 0; b < kv.second.size(); b += 65535) {
@@ -577,7 +624,7 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
                 return device_fail(ctx, e, "batch ionosphere launch");
         }
     }
-    if (!blob.empty()) {
+    if (dev) {
         slot_mark.armed = false;
         return mark_descriptors_used(ctx, s);
     }
@@ -632,7 +679,7 @@ namespace rc {
 
 const char *const kKernelNames[kKGroups] = {"k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd",
                                             "k_fft_rows_iono", "k_fft_strided_inv", "k_sinc_mfma",
-                                            "k_mf_tile_list"};
+                                            "k_mf_tile_list", "k_bluestein"};
 
 hipEvent_t Profiler::take()
 {

@@ -22,6 +22,7 @@ enum KernelGroup {
     kKFftStridedInv,
     kKSincMfma,
     kKSincTiles,
+    kKBluestein,
     kKGroups
 };
 extern const char *const kKernelNames[kKGroups];
@@ -156,6 +157,9 @@ struct IonoJob {
     double phase_num;
     double carrier;
     double fs;
+    // When set, the spectrum is multiplied by this table (in the transform's native bin
+    // order, see launch_fft) instead of the dispersive phase: a circular convolution.
+    const float2 *mult;
 };
 
 // Decomposition of an n-point transform into levels L_0 x L_1 x ... x L_{d-1}
@@ -170,9 +174,24 @@ struct FftPlan {
 hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs);
 hipError_t make_base_twiddles(float2 **dev);  // exp(-2 pi i q / 4096), q < 4096
 
-// Full ionospheric operator for njobs pulses of the same length plan.n.
+// Full ionospheric operator for njobs pulses of the same length plan.n: forward FFT, the
+// per-bin factor (dispersive phase, or the job's `mult` table), inverse FFT with 1/n.
 hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
                        const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof);
+// Forward FFT only, the spectrum left in the native bin order of the multi-level transform:
+// bin k sits at (row r) * L + l where L is the last level and row r holds bins
+// kout(r) + (n / L) l (kout = the digit-reversed row index).  For a one-level plan the order
+// is natural.  Used to build `mult` tables.
+hipError_t launch_fft_forward(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
+                              const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof);
+
+// Ionospheric operator of a length n that is not a power of two (Bluestein): the N-point DFT
+// as a chirp convolution of power-of-two length m >= 2n - 1.  `work` holds 2 m complex
+// values (the convolution buffer and the chirp spectrum).
+size_t bluestein_work_bytes(int64_t n);
+hipError_t launch_iono_bluestein(int64_t n, const FftPlan &mplan, const float2 *tw4096, const float2 *x,
+                                 float2 *y, double phase_num, double carrier, double fs, void *work,
+                                 hipStream_t s, Profiler *prof);
 
 }  // namespace rc
 

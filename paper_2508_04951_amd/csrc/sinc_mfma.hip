@@ -211,11 +211,18 @@ k_mf_tile_scatter(const uint2 *__restrict__ ref, const unsigned char *__restrict
     const int tid = threadIdx.x;
     const int nchunks = gridDim.x, me = blockIdx.x;
     if (tid < kPhaseRows) {
+        // eight chunks' counts in flight at a time
         unsigned all = 0, before = 0;
-        for (int w = 0; w < nchunks; ++w) {
-            const unsigned c = counts[(size_t)w * kPhaseRows + tid];
-            all += c;
-            before += w < me ? c : 0u;
+        for (int w0 = 0; w0 < nchunks; w0 += 8) {
+            unsigned c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                c[u] = w0 + u < nchunks ? counts[(size_t)(w0 + u) * kPhaseRows + tid] : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                all += c[u];
+                before += w0 + u < me ? c[u] : 0u;
+            }
         }
         tot[tid] = all;
         base[tid] = before;

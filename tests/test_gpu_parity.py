@@ -166,6 +166,36 @@ def test_iono_parity(torch, ctx, orc, n, direction):
         assert err <= TOL, (n, direction, tec_tecu, fc, err)
 
 
+@pytest.mark.parametrize("n", [3, 5, 7, 12, 48, 1000, 4095, 4097, 5000, 65537, 100003, 300001])
+@pytest.mark.parametrize("direction", ["correct", "distort"])
+def test_iono_parity_any_length(torch, ctx, orc, n, direction):
+    """Lengths that are not powers of two (Bluestein at the power of two >= 2n - 1) against
+    the oracle's N-point operator."""
+    x = wf.bandlimited_noise(n, wf.rng_for(117, n))
+    for tec_tecu, fc, fs in [(50.0, 450e6, 10e6), (5.0, 150e6, 10e6), (0.0, 450e6, 10e6), (100.0, 0.0, 2.048e9)]:
+        y = host(ctx.correct_ionosphere(dev(torch, x), fs, fc, tec_tecu * wf.TECU, direction))
+        ref = orc.ionosphere(x, fs, fc, tec_tecu * wf.TECU, direction, naive=n <= 5000)
+        err = rel_l2(y, ref)
+        assert err <= TOL, (n, direction, tec_tecu, fc, err)
+
+
+def test_iono_any_length_in_place_and_round_trip(torch, ctx, orc):
+    """Bluestein in place equals out of place bit for bit; at 2^22 + 12345 (the longest serving
+    lengths) distort then correct is the identity and the norm is kept."""
+    x = wf.bandlimited_noise(70001, wf.rng_for(118, 0))
+    xd = dev(torch, x)
+    y = host(ctx.correct_ionosphere(xd, 10e6, 450e6, 60 * wf.TECU))
+    ctx.correct_ionosphere(xd, 10e6, 450e6, 60 * wf.TECU, out=xd)
+    assert np.array_equal(host(xd), y)
+    n = (1 << 22) + 12345
+    x = wf.bandlimited_noise(n, wf.rng_for(118, 1))
+    xd = dev(torch, x)
+    d = ctx.correct_ionosphere(xd, 10e6, 450e6, 90 * wf.TECU, "distort")
+    z = host(ctx.correct_ionosphere(d, 10e6, 450e6, 90 * wf.TECU, "correct"))
+    assert rel_l2(z, x) <= 2 * TOL
+    assert abs(np.linalg.norm(host(d)) / np.linalg.norm(x) - 1) <= 1e-5
+
+
 def test_iono_in_place(torch, ctx, orc):
     x = wf.bandlimited_noise(65536, wf.rng_for(106, 0))
     xd = dev(torch, x)
@@ -220,7 +250,7 @@ def _ragged_batch():
     """Pulses of mixed length, alpha, TEC, flags and direction, packed with gaps."""
     rng = wf.rng_for(109, 0)
     specs = [(65536, 3), (4096, 3), (8192, 1), (1000, 1), (65536, 2), (256, 3), (1 << 17, 3), (4096, 2),
-             (3000, 1), (16, 3)]
+             (3000, 1), (16, 3), (5000, 3), (70001, 2), (12, 3), (70001, 3)]
     pulses, xs = [], []
     off_in = off_out = 5
     for i, (n, flags) in enumerate(specs):
@@ -359,9 +389,11 @@ def test_invalid_arguments_are_rejected(torch, ctx):
         ctx.correct_ionosphere(x, 10e6, 450e6, -1.0)
     with pytest.raises(ValueError):
         ctx.correct_ionosphere(x[1:], 10e6, 450e6, 1e17, out=x[:-1])  # partial overlap
+    big = torch.zeros((1 << 23) + 1, dtype=torch.complex64, device="cuda")
     with pytest.raises(rc.RcError) as ei:
-        ctx.correct_ionosphere(x[:48], 10e6, 450e6, 1e17)
-    assert ei.value.status == 2  # RC_ERR_UNSUPPORTED (not a power of two)
+        ctx.correct_ionosphere(big, 10e6, 450e6, 1e17)
+    assert ei.value.status == 2  # RC_ERR_UNSUPPORTED (Bluestein would need m > 2^24)
+    del big
     ok = dict(off_in=0, n_in=32, off_out=0, n_out=32, fs=10e6, alpha=1.0, tec=1e17, carrier=450e6)
     with pytest.raises(ValueError):
         ctx.correct_pulse_batch(x, y, [dict(ok, off_in=40)])  # past the end of x
