@@ -340,6 +340,7 @@ struct RowArgs {
     int len[kFftMaxLevels];   // level lengths (the last is L)
     const float2 *tw4096;
     bool from_x;
+    bool fwd_only;            // store the spectrum (native order) after the forward transform
     float scale;              // 1/n when this is the only pass, else 1
 };
 
@@ -414,6 +415,13 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
     for (int q = 0; q < 16; ++q)
         v[q] = src[j + 256 * q];
     row4096<-1>(v, lds, j, a.tw4096);
+    if (a.fwd_only) {
+        const auto dst = gmem(jb.y) + (r << 12);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            dst[j + 256 * q] = make_float2(v[q].x * a.scale, v[q].y * a.scale);
+        return;  // uniform over the workgroup
+    }
     // bin of row position l: k = kout(r) + (n / 4096) l, kout = digit-reversed row index
     int64_t kout = 0, mult = 1;
     {
@@ -433,10 +441,24 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
 #pragma unroll
     for (int q = 0; q < 16; ++q)
         lds[rpad(j + 256 * q)] = v[q];
-#pragma unroll 1
-    for (int q = 0; q < 16; ++q) {
-        const int i = rpad(j + 256 * q);
-        lds[i] = cmul(lds[i], iono_phase(jb, kout + mult * (j + 256 * q), a.n));
+    if (jb.mult) {  // a convolution: the table is in this row's native order
+        const auto tab = gmem(jb.mult) + (r << 12);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = rpad(j + 256 * q);
+            lds[i] = cmul(lds[i], tab[j + 256 * q]);
+        }
+    } else {
+        // the 16 phases as independent chains (the samples wait in LDS meanwhile)
+        float2 ph[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            ph[q] = iono_phase(jb, kout + mult * (j + 256 * q), a.n);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = rpad(j + 256 * q);
+            lds[i] = cmul(lds[i], ph[q]);
+        }
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q)
@@ -475,8 +497,17 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_iono(RowArgs a)
             continue;
         const IonoJob jb = a.jobs ? gload(a.jobs, g) : a.inl;
         const int idx = tidx(c, l, a.log2L, a.log2C, true);
-        lds[idx] = cmul(lds[idx], iono_phase(jb, l, a.n));
+        if (a.fwd_only) {
+            float2 v = lds[idx];
+            v.x *= a.scale;
+            v.y *= a.scale;
+            gmem(jb.y)[l] = v;
+        } else {
+            lds[idx] = cmul(lds[idx], jb.mult ? gload(jb.mult, l) : iono_phase(jb, l, a.n));
+        }
     }
+    if (a.fwd_only)
+        return;  // uniform over the workgroup
     __syncthreads();
     fft_tile<+1>(lds, a.log2L, a.log2C, true, a.tw4096, tid);
     for (int e = tid; e < kFftTile; e += kFftThreads) {
@@ -557,8 +588,10 @@ hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs)
     return hipSuccess;
 }
 
-hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
-                       const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof)
+namespace {
+
+hipError_t launch_fft_impl(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
+                           const IonoJob *job_inline, int njobs, bool fwd_only, hipStream_t s, Profiler *prof)
 {
     if (njobs <= 0)
         return hipSuccess;
@@ -637,7 +670,8 @@ hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob 
             a.len[i] = plan.len[i];
         a.tw4096 = tw4096;
         a.from_x = (d == 1);
-        a.scale = (d == 1) ? inv_n : 1.0f;
+        a.fwd_only = fwd_only;
+        a.scale = (d == 1 && !fwd_only) ? inv_n : 1.0f;
         if (prof)
             prof->begin(kKFftRowsIono, s);
         if (a.log2L == 12) {
@@ -655,12 +689,148 @@ hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob 
         if (e != hipSuccess)
             return e;
     }
+    if (fwd_only)
+        return hipSuccess;
     for (int i = d - 2; i >= 0; --i) {
         hipError_t e = strided(i, true);
         if (e != hipSuccess)
             return e;
     }
     return hipSuccess;
+}
+
+// Bluestein (chirp-z) pieces.  With w_m = exp(i pi m^2 / N) and kn = (k^2 + n^2 - (k - n)^2) / 2,
+// DFT_N(x)_k = conj(w_k) (a (*) b)_k with a_n = x_n conj(w_n) and b_m = w_m for |m| < N, the
+// convolution taken circularly at a power-of-two length M >= 2N - 1.  The inverse DFT of
+// X_k H_k is (1/N) conj(DFT_N(conj(X H))), and conj(X_k H_k) conj(w_k) = conj(c_k H_k) when
+// X_k = conj(w_k) c_k, so the second convolution's input is simply conj(c_k H_k).
+
+// w_m, the argument reduced exactly: m^2 mod 2N in integers, then pi * (that / N).
+__device__ __forceinline__ float2 chirp_w(int64_t m, int64_t N)
+{
+    const int64_t r = (m * m) % (2 * N);
+    double sn, cs;
+    sincospi((double)r / (double)N, &sn, &cs);
+    return make_float2((float)cs, (float)sn);
+}
+
+// a = x conj(w) zero-padded to M; b = the chirp placed circularly (b_m = b_{M-m} = w_m, m < N).
+__global__ void __launch_bounds__(256) k_bluestein_pre(const float2 *__restrict__ x, int64_t N, int64_t M,
+                                                       float2 *__restrict__ a, float2 *__restrict__ b)
+{
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= M)
+        return;
+    float2 av = make_float2(0.f, 0.f), bv = make_float2(0.f, 0.f);
+    if (m < N) {
+        const float2 w = chirp_w(m, N);
+        const float2 v = gload(x, m);
+        av = make_float2(v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y);  // v conj(w)
+        bv = w;
+    } else if (M - m < N) {
+        bv = chirp_w(M - m, N);
+    }
+    gmem(a)[m] = av;
+    gmem(b)[m] = bv;
+}
+
+// c (first convolution) -> conj(c_k H_k) for k < N, zero above.
+__global__ void __launch_bounds__(256) k_bluestein_mid(float2 *__restrict__ c, int64_t N, int64_t M, IonoJob jb)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= M)
+        return;
+    float2 v = make_float2(0.f, 0.f);
+    if (k < N) {
+        const float2 h = cmul(gload(c, k), iono_phase(jb, k, N));
+        v = make_float2(h.x, -h.y);
+    }
+    gmem(c)[k] = v;
+}
+
+// f (second convolution) -> y_n = w_n conj(f_n) / N.
+__global__ void __launch_bounds__(256) k_bluestein_post(const float2 *__restrict__ f, int64_t N,
+                                                        float2 *__restrict__ y)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= N)
+        return;
+    const float2 w = chirp_w(n, N), v = gload(f, n);
+    const float sc = (float)(1.0 / (double)N);
+    // w conj(v)
+    gmem(y)[n] = make_float2((w.x * v.x + w.y * v.y) * sc, (w.y * v.x - w.x * v.y) * sc);
+}
+
+int64_t bluestein_m(int64_t n)
+{
+    int64_t m = 1;
+    while (m < 2 * n - 1)
+        m <<= 1;
+    return m;
+}
+
+}  // namespace
+
+hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
+                       const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof)
+{
+    return launch_fft_impl(plan, tw4096, jobs_dev, job_inline, njobs, false, s, prof);
+}
+
+hipError_t launch_fft_forward(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
+                              const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof)
+{
+    return launch_fft_impl(plan, tw4096, jobs_dev, job_inline, njobs, true, s, prof);
+}
+
+size_t bluestein_work_bytes(int64_t n) { return (size_t)bluestein_m(n) * 2 * sizeof(float2); }
+
+hipError_t launch_iono_bluestein(int64_t n, const FftPlan &mplan, const float2 *tw4096, const float2 *x,
+                                 float2 *y, double phase_num, double carrier, double fs, void *work,
+                                 hipStream_t s, Profiler *prof)
+{
+    const int64_t M = bluestein_m(n);
+    if (mplan.n != M || n < 2 || !work)
+        return hipErrorInvalidValue;
+    float2 *a = static_cast<float2 *>(work);
+    float2 *b = a + M;
+    const unsigned gm = (unsigned)((M + 255) / 256), gn = (unsigned)((n + 255) / 256);
+    if (prof)
+        prof->begin(kKBluestein, s);
+    hipLaunchKernelGGL(k_bluestein_pre, dim3(gm), dim3(256), 0, s, x, n, M, a, b);
+    hipError_t e = hipGetLastError();
+    if (prof)
+        prof->end(s);
+    if (e != hipSuccess)
+        return e;
+    // the chirp's spectrum, in the native bin order the convolutions multiply in
+    const IonoJob jb_b{b, b, 0.0, 0.0, 0.0, nullptr};
+    e = launch_fft_forward(mplan, tw4096, nullptr, &jb_b, 1, s, prof);
+    if (e != hipSuccess)
+        return e;
+    const IonoJob conv{a, a, 0.0, 0.0, 0.0, b};
+    e = launch_iono(mplan, tw4096, nullptr, &conv, 1, s, prof);
+    if (e != hipSuccess)
+        return e;
+    const IonoJob ph{nullptr, nullptr, phase_num, carrier, fs, nullptr};
+    if (prof)
+        prof->begin(kKBluestein, s);
+    hipLaunchKernelGGL(k_bluestein_mid, dim3(gm), dim3(256), 0, s, a, n, M, ph);
+    e = hipGetLastError();
+    if (prof)
+        prof->end(s);
+    if (e != hipSuccess)
+        return e;
+    e = launch_iono(mplan, tw4096, nullptr, &conv, 1, s, prof);
+    if (e != hipSuccess)
+        return e;
+    if (prof)
+        prof->begin(kKBluestein, s);
+    hipLaunchKernelGGL(k_bluestein_post, dim3(gn), dim3(256), 0, s, a, n, y);
+    e = hipGetLastError();
+    if (prof)
+        prof->end(s);
+    return e;
 }
 
 }  // namespace rc
