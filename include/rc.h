@@ -150,6 +150,29 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
                               rc_c64 *y_packed, int64_t y_len, const rc_pulse *pulses,
                               int32_t count, const rc_sinc *k, void *stream);
 
+/* A bank of Doppler hypotheses on one pulse (many alpha on the same input):
+ *   y[h * n_out + m] = sum_n x[n] h(alphas[h] m - n),  h < n_hyp, m < n_out,
+ * each row exactly the correct_doppler result for its alpha up to float32 rounding (the same
+ * Eq (17) sum; the exact-integer rule is kept).  x: n device samples; y: n_hyp * n_out device
+ * samples, must not overlap x; alphas: HOST array of n_hyp values, finite and > 0, read
+ * during the call only.  mode:
+ *   RC_BANK_FARROW           a Farrow filter bank: the 2H-tap FIR of each of 8 Chebyshev
+ *                            coefficients of the tap weight in the fractional position runs
+ *                            once per input position, then each (hypothesis, output) costs
+ *                            an 8-term sum.  Needs a Kaiser or rectangular window,
+ *                            1 <= H <= 256 and every alpha in (0, 2]; else RC_ERR_UNSUPPORTED.
+ *                            Within ~4e-7 rel-L2 of the direct sum at H = 64 and 128.
+ *   RC_BANK_PER_HYPOTHESIS   every hypothesis as a pulse of correct_pulse_batch (the
+ *                            resampling engines of correct_doppler).
+ *   RC_BANK_AUTO             the filter bank where it applies, else per hypothesis.
+ * The filter bank's workspace (8 complex values per input position) comes from the context.
+ * This extends the paper (one alpha per pulse) to the hypothesis search of a
+ * Doppler-ambiguous return; the operator per row is Eq (2) with Eq (17). */
+enum { RC_BANK_AUTO = 0, RC_BANK_FARROW = 1, RC_BANK_PER_HYPOTHESIS = 2 };
+rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c64 *y,
+                               int64_t n_out, double fs_hz, const double *alphas, int32_t n_hyp,
+                               const rc_sinc *k, int32_t mode, void *stream);
+
 /* Resampling engine (rc_set_sinc_engine).  Every engine computes the same sum of Eq (17):
  *   RC_SINC_AUTO   matrix cores for the Kaiser taper at H = 64 or 128 and |alpha - 1| <= 6e-5,
  *                  else the vector tile kernel (Kaiser, H <= 256, |alpha - 1| <= 1e-4), else the
@@ -168,7 +191,8 @@ rc_status rc_set_sinc_engine(rc_context ctx, int32_t engine);
  * total milliseconds and launch count of one kernel: "k_sinc_mfma", "k_sinc_fast",
  * "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono", "k_fft_strided_inv" or
  * "k_mf_tile_list" (the three small kernels that sort a batch's matrix-core tiles by phase,
- * timed together as one launch).  Unknown names give
+ * timed together as one launch), "k_bluestein" (the pointwise chirp kernels of lengths that are
+ * not powers of two), "k_farrow_z" or "k_farrow_bank".  Unknown names give
  * RC_ERR_INVALID_ARG.  Timing adds two event records per launch and no synchronisation. */
 rc_status rc_profile_enable(rc_context ctx, int enable);
 rc_status rc_profile_read(rc_context ctx, const char *kernel, double *total_ms, int64_t *launches);

@@ -24,10 +24,12 @@ DO_DOPPLER, DO_IONO = 1, 2
 SYMBOLS = (
     "rc_create", "rc_destroy", "rc_status_string", "rc_last_error", "rc_alpha_from_vr",
     "rc_k2_per_tec", "rc_sync", "correct_doppler", "correct_ionosphere", "correct_pulse_batch",
+    "correct_doppler_bank",
     "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine",
 )
 KERNELS = ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono",
-           "k_fft_strided_inv", "k_mf_tile_list")
+           "k_fft_strided_inv", "k_mf_tile_list", "k_bluestein", "k_farrow_z", "k_farrow_bank")
+BANK_MODES = {"auto": 0, "farrow": 1, "per_hypothesis": 2}
 SINC_ENGINES = {"auto": 0, "valu": 1, "direct": 2}
 
 
@@ -86,6 +88,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.rc_sync.restype = c_i32
         lib.correct_doppler.argtypes = [p, p, c_i64, p, c_i64, c_d, c_d, ctypes.POINTER(RcSinc), p]
         lib.correct_doppler.restype = c_i32
+        lib.correct_doppler_bank.argtypes = [p, p, c_i64, p, c_i64, c_d, ctypes.POINTER(c_d), c_i32,
+                                             ctypes.POINTER(RcSinc), c_i32, p]
+        lib.correct_doppler_bank.restype = c_i32
         lib.correct_ionosphere.argtypes = [p, p, p, c_i64, c_d, c_d, c_d, c_i32, p]
         lib.correct_ionosphere.restype = c_i32
         lib.correct_pulse_batch.argtypes = [p, p, c_i64, p, c_i64, ctypes.POINTER(RcPulse), c_i32,
@@ -261,6 +266,32 @@ class Context:
         if st != RC_OK:
             self._raise(st, "correct_pulse_batch")
         return y_packed
+
+    def correct_doppler_bank(self, x, alphas, sinc: Sinc | None = None, n_out: int | None = None,
+                             mode: str = "auto", fs: float = 1.0, out=None, stream=None):
+        """Row h of the (len(alphas), n_out) result is correct_doppler(x, alphas[h])."""
+        torch = _torch()
+        _check_samples(x, "x")
+        n_out = x.numel() if n_out is None else int(n_out)
+        a = _bank_alphas(alphas)
+        if out is None:
+            out = torch.empty((len(a), n_out), dtype=torch.complex64, device=x.device)
+        _check_samples(out, "out")
+        if out.numel() < len(a) * n_out:
+            raise ValueError("out is shorter than len(alphas) * n_out")
+        if mode not in BANK_MODES:
+            raise ValueError(f"mode must be one of {list(BANK_MODES)}")
+        k = (sinc or Sinc()).c()
+        st = self._lib.correct_doppler_bank(self._h, x.data_ptr(), x.numel(), out.data_ptr(), n_out, float(fs), a,
+                                            len(a), ctypes.byref(k), BANK_MODES[mode], self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "correct_doppler_bank")
+        return out
+
+
+def _bank_alphas(alphas) -> ctypes.Array:
+    vals = [float(a) for a in alphas]
+    return (ctypes.c_double * len(vals))(*vals)
 
 
 def pulse_array(pulses) -> ctypes.Array:

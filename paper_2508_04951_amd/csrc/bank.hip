@@ -1,0 +1,316 @@
+// bank.hip -- a bank of Doppler hypotheses on one pulse: y_h[m] = sum_n x[n] h(alpha_h m - n)
+// (Eq 2 resampled with the windowed sum of Eq 17) for many alpha_h at once.
+//
+// Farrow filter bank.  Output m of hypothesis h sits at t = alpha_h m = f + mu (f integer,
+// mu in [0, 1)) and takes taps f + j, j = -H + 1 .. H, with weights h(mu - j).  Each weight is
+// a polynomial in mu: h(mu - j) ~= sum_r c_r[j] T_r(2 mu - 1) (Chebyshev, r < R), so
+//     y_h[m] = sum_r T_r(2 mu - 1) Z[f][r],   Z[f][r] = sum_j x[f + j] c_r[j].
+// Z depends on the input position only: it is computed once per pulse (k_farrow_z, R FIR
+// filters of 2H taps) and every hypothesis then costs one Clenshaw sum of R terms per output
+// (k_farrow_bank).  The coefficients interpolate h at the R Chebyshev nodes of [0, 1] in
+// float64 (k_farrow_coef); at R = 8 the bank is within ~4e-7 rel-L2 of the direct sum at
+// H = 64 and 128.  An output whose position is an exact integer takes the input sample.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rc_internal.h"
+
+namespace rc {
+namespace {
+
+constexpr int kR = kFarrowOrders;
+constexpr int kBankM = 512;        // outputs per workgroup and hypothesis
+constexpr int kBankThreads = 256;
+
+__device__ __forceinline__ double kaiser_series(const KaiserPoly &kp, double x)
+{
+    const double s = 1.0 - x * x;
+    double acc = kp.c[kp.n - 1];
+    for (int j = kp.n - 2; j >= 0; --j)
+        acc = fma(acc, s, kp.c[j]);
+    return acc;
+}
+
+// coef[(j + H - 1) * R + r] = c_r[j]: Chebyshev interpolation of mu -> h(mu - j) on [0, 1].
+__global__ void __launch_bounds__(256) k_farrow_coef(KaiserPoly kp, int H, int taper, float *__restrict__ coef)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= 2 * H * kR)
+        return;
+    const int tap = id / kR, r = id - tap * kR;
+    const int j = tap - H + 1;
+    double acc = 0.0;
+    for (int i = 0; i < kR; ++i) {
+        const double th = (i + 0.5) / kR;            // node angle / pi
+        const double mu = 0.5 * (cospi(th) + 1.0);   // in (0, 1): |mu - j| < H for every tap
+        const double u = mu - (double)j;
+        double w = sinpi(u) / (kPi * u);
+        if (taper)
+            w *= kaiser_series(kp, u / (double)H);
+        acc = fma(w, cospi(r * th), acc);
+    }
+    acc *= 2.0 / kR;
+    if (r == 0)
+        acc *= 0.5;
+    gmem(coef)[id] = (float)acc;
+}
+
+// Z[f][r] for f in [0, F): one workgroup per 256 positions; the input span and the
+// coefficients are staged in LDS.  Dynamic LDS: 2H R floats, then 256 + 2H - 1 samples.
+__global__ void __launch_bounds__(256) k_farrow_z(const float2 *__restrict__ x, int64_t n, int64_t F, int H,
+                                                  const float *__restrict__ coef, float2 *__restrict__ Z)
+{
+    extern __shared__ __attribute__((aligned(16))) float smem_z[];
+    float *cs = smem_z;
+    float2 *xs = reinterpret_cast<float2 *>(smem_z + 2 * H * kR);
+    const int tid = threadIdx.x;
+    const int64_t f0 = (int64_t)blockIdx.x * 256;
+    for (int i = tid; i < 2 * H * kR; i += 256)
+        cs[i] = gload(coef, i);
+    const int span = 256 + 2 * H - 1;
+    for (int e = tid; e < span; e += 256) {
+        const int64_t g = f0 - H + 1 + e;
+        xs[e] = (g >= 0 && g < n) ? gload(x, g) : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const int64_t f = f0 + tid;
+    if (f >= F)
+        return;
+    float ar[kR], ai[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r)
+        ar[r] = ai[r] = 0.f;
+    for (int t = 0; t < 2 * H; ++t) {
+        const float2 v = xs[tid + t];
+        const float4 c0 = *reinterpret_cast<const float4 *>(cs + t * kR);
+        const float4 c1 = *reinterpret_cast<const float4 *>(cs + t * kR + 4);
+        const float c[kR] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            ar[r] = fmaf(v.x, c[r], ar[r]);
+            ai[r] = fmaf(v.y, c[r], ai[r]);
+        }
+    }
+    const auto zg = gmem(reinterpret_cast<float4 *>(Z + f * kR));
+#pragma unroll
+    for (int r = 0; r < kR; r += 2)
+        zg[r / 2] = make_float4(ar[r], ai[r], ar[r + 1], ai[r + 1]);
+}
+
+// One group of hypotheses (consecutive in alpha order) for kBankM outputs: the Z rows the
+// group touches are staged in LDS, then each thread walks its outputs for every hypothesis.
+struct BankGroup {
+    int first;  // index into the alpha-sorted list
+    int count;
+};
+
+__global__ void __launch_bounds__(kBankThreads)
+k_farrow_bank(const float2 *__restrict__ Z, int64_t F, const float2 *__restrict__ x, int64_t n,
+              const double *__restrict__ alpha, const int *__restrict__ hyp, const BankGroup *__restrict__ groups,
+              int64_t n_out, float2 *__restrict__ y, int max_rows)
+{
+    extern __shared__ __attribute__((aligned(16))) float4 zs[];  // rows x (R / 2) float4
+    const int tid = threadIdx.x;
+    const BankGroup g = gload(groups, blockIdx.y);
+    const int64_t m0 = (int64_t)blockIdx.x * kBankM;
+    const int64_t mlast = (m0 + kBankM < n_out ? m0 + kBankM : n_out) - 1;
+    // alphas are sorted: the group's rows are floor(a_first m0) .. floor(a_last mlast)
+    const double alo = gload(alpha, g.first), ahi = gload(alpha, g.first + g.count - 1);
+    const int64_t fmin = (int64_t)floor(__dmul_rn(alo, (double)m0));
+    const int64_t fmax = (int64_t)floor(__dmul_rn(ahi, (double)mlast));
+    const int rows = (int)(fmax - fmin + 1);
+    if (rows > max_rows)
+        return;  // the host sizes groups so this never happens; uniform over the workgroup
+    const auto zg = gmem(reinterpret_cast<const float4 *>(Z));
+    for (int e = tid; e < rows * (kR / 2); e += kBankThreads) {
+        const int64_t f = fmin + e / (kR / 2);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (f < F)
+            v = zg[fmin * (kR / 2) + e];
+        zs[e] = v;
+    }
+    __syncthreads();
+    const auto yg = gmem(y);
+    for (int i = 0; i < g.count; ++i) {
+        const double a = gload(alpha, g.first + i);
+        const auto yh = yg + (int64_t)gload(hyp, g.first + i) * n_out;
+#pragma unroll
+        for (int q = 0; q < kBankM / kBankThreads; ++q) {
+            const int64_t m = m0 + tid + kBankThreads * q;
+            if (m >= n_out)
+                continue;
+            const double t = __dmul_rn(a, (double)m);
+            const double fd = floor(t);
+            const int64_t f = (int64_t)fd;
+            float2 out;
+            if (t == fd) {  // exact sample instant: the input sample itself
+                out = make_float2(0.f, 0.f);
+                if (f < n)
+                    out = gload(x, f);
+            } else {
+                // Clenshaw: b_r = Z_r + 2 s b_{r+1} - b_{r+2};  y = Z_0 + s b_1 - b_2,  s = 2 mu - 1
+                const float s = (float)(2.0 * (t - fd) - 1.0);
+                const float4 *row = zs + (f - fmin) * (kR / 2);
+                float zr[kR], zi[kR];
+#pragma unroll
+                for (int q2 = 0; q2 < kR / 2; ++q2) {
+                    const float4 z = row[q2];  // (Z_{2 q2}, Z_{2 q2 + 1})
+                    zr[2 * q2] = z.x;
+                    zi[2 * q2] = z.y;
+                    zr[2 * q2 + 1] = z.z;
+                    zi[2 * q2 + 1] = z.w;
+                }
+                const float s2 = 2.f * s;
+                float b1r = 0.f, b1i = 0.f, b2r = 0.f, b2i = 0.f;
+#pragma unroll
+                for (int r = kR - 1; r >= 1; --r) {
+                    const float br = fmaf(s2, b1r, zr[r] - b2r), bi = fmaf(s2, b1i, zi[r] - b2i);
+                    b2r = b1r;
+                    b2i = b1i;
+                    b1r = br;
+                    b1i = bi;
+                }
+                out = make_float2(fmaf(s, b1r, zr[0] - b2r), fmaf(s, b1i, zi[0] - b2i));
+            }
+            yh[m] = out;
+        }
+    }
+}
+
+}  // namespace
+
+bool farrow_eligible(const rc_sinc &k, const double *alphas, int n_hyp)
+{
+    if (k.half_width < 1 || k.half_width > kFarrowMaxHalfWidth)
+        return false;
+    if (k.window != RC_WIN_KAISER && k.window != RC_WIN_RECT)
+        return false;
+    if (k.window == RC_WIN_KAISER && make_kaiser_poly(k.kaiser_beta).n > 56)
+        return false;
+    for (int i = 0; i < n_hyp; ++i)
+        if (!(alphas[i] > 0.0 && alphas[i] <= kFarrowMaxAlpha))
+            return false;
+    return true;
+}
+
+hipError_t build_farrow_coef(const rc_sinc &k, void **dev, std::vector<void *> &allocs)
+{
+    const int H = k.half_width;
+    const size_t bytes = (size_t)2 * H * kR * sizeof(float);
+    hipError_t e = hipMalloc(dev, bytes);
+    if (e != hipSuccess)
+        return e;
+    allocs.push_back(*dev);
+    const KaiserPoly kp = make_kaiser_poly(k.window == RC_WIN_KAISER ? k.kaiser_beta : 0.0);
+    hipLaunchKernelGGL(k_farrow_coef, dim3((2 * H * kR + 255) / 256), dim3(256), 0, 0, kp, H,
+                       k.window == RC_WIN_KAISER ? 1 : 0, static_cast<float *>(*dev));
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return hipStreamSynchronize(0);
+}
+
+FarrowPlan plan_farrow_bank(int64_t n, int64_t n_out, int H, const double *alphas, int n_hyp)
+{
+    FarrowPlan p;
+    p.n_hyp = n_hyp;
+    std::vector<int> order((size_t)n_hyp);
+    for (int i = 0; i < n_hyp; ++i)
+        order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return alphas[a] < alphas[b]; });
+    p.alpha.resize((size_t)n_hyp);
+    p.hyp.resize((size_t)n_hyp);
+    double amax = 0.0;
+    for (int i = 0; i < n_hyp; ++i) {
+        p.hyp[(size_t)i] = order[(size_t)i];
+        p.alpha[(size_t)i] = alphas[order[(size_t)i]];
+        amax = std::max(amax, p.alpha[(size_t)i]);
+    }
+    // groups: at most 64 hypotheses whose positions at the last output spread by <= 192 samples
+    const double last = (double)(n_out - 1);
+    for (int s = 0; s < n_hyp;) {
+        int e = s + 1;
+        while (e < n_hyp && e - s < 64 && (p.alpha[(size_t)e] - p.alpha[(size_t)s]) * last <= 192.0)
+            ++e;
+        p.groups.push_back({s, e - s});
+        s = e;
+    }
+    // rows one group touches in a kBankM block: floor(a_hi mlast) - floor(a_lo m0) + 1
+    //   <= a_hi (kBankM - 1) + (a_hi - a_lo) m0 + 2
+    p.max_rows = (int)std::ceil(amax * (kBankM - 1) + 192.0) + 3;
+    p.F = std::min<int64_t>((int64_t)std::floor(amax * last) + 1, n + H);
+    if (p.F < 1)
+        p.F = 1;
+    p.z_bytes = (size_t)p.F * kR * sizeof(float2);
+    p.lds_bytes = (size_t)p.max_rows * kR * sizeof(float2);
+    return p;
+}
+
+size_t farrow_desc_bytes(const FarrowPlan &p)
+{
+    return p.alpha.size() * sizeof(double) + p.hyp.size() * sizeof(int) + p.groups.size() * 8;
+}
+
+void farrow_pack_desc(const FarrowPlan &p, char *host)
+{
+    std::memcpy(host, p.alpha.data(), p.alpha.size() * sizeof(double));
+    host += p.alpha.size() * sizeof(double);
+    std::memcpy(host, p.hyp.data(), p.hyp.size() * sizeof(int));
+    host += p.hyp.size() * sizeof(int);
+    for (const auto &g : p.groups) {
+        const int v[2] = {g.first, g.count};
+        std::memcpy(host, v, 8);
+        host += 8;
+    }
+}
+
+hipError_t launch_farrow_bank(const FarrowPlan &p, const float2 *x, int64_t n, float2 *y, int64_t n_out, int H,
+                              const float *coef, const void *desc_dev, void *z_work, hipStream_t s, Profiler *prof)
+{
+    if (p.lds_bytes > 160 * 1024 || n_out <= 0 || p.groups.empty())
+        return hipErrorInvalidValue;
+    float2 *Z = static_cast<float2 *>(z_work);
+    const char *d = static_cast<const char *>(desc_dev);
+    const double *alpha = reinterpret_cast<const double *>(d);
+    const int *hyp = reinterpret_cast<const int *>(d + p.alpha.size() * sizeof(double));
+    const BankGroup *groups =
+        reinterpret_cast<const BankGroup *>(d + p.alpha.size() * sizeof(double) + p.hyp.size() * sizeof(int));
+    static bool attr[64] = {false};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= 64)
+        return hipErrorInvalidDevice;
+    if (!attr[dev]) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_farrow_bank),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess)
+            return e;
+        attr[dev] = true;
+    }
+    const size_t zlds = ((size_t)2 * H * kR * sizeof(float) + 15) / 16 * 16 + (size_t)(256 + 2 * H - 1) * 8;
+    if (prof)
+        prof->begin(kKFarrowZ, s);
+    hipLaunchKernelGGL(k_farrow_z, dim3((unsigned)((p.F + 255) / 256)), dim3(256), zlds, s, x, n, p.F, H, coef, Z);
+    e = hipGetLastError();
+    if (prof)
+        prof->end(s);
+    if (e != hipSuccess)
+        return e;
+    const int64_t mblocks = (n_out + kBankM - 1) / kBankM;
+    if (mblocks > 0x7fffffff || p.groups.size() > 65535)
+        return hipErrorInvalidValue;
+    if (prof)
+        prof->begin(kKFarrowBank, s);
+    hipLaunchKernelGGL(k_farrow_bank, dim3((unsigned)mblocks, (unsigned)p.groups.size()), dim3(kBankThreads),
+                       p.lds_bytes, s, Z, p.F, x, n, alpha, hyp, groups, n_out, y, p.max_rows);
+    e = hipGetLastError();
+    if (prof)
+        prof->end(s);
+    return e;
+}
+
+}  // namespace rc

@@ -427,14 +427,12 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
     return RC_OK;
 }
 
-rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_len, rc_c64 *y_packed,
-                              int64_t y_len, const rc_pulse *pulses, int32_t count, const rc_sinc *k,
-                              void *stream)
+namespace {
+
+// correct_pulse_batch with the context lock held (also the per-hypothesis Doppler bank)
+rc_status pulse_batch_locked(rc_context ctx, const rc_c64 *x_packed, int64_t x_len, rc_c64 *y_packed,
+                             int64_t y_len, const rc_pulse *pulses, int32_t count, const rc_sinc *k, void *stream)
 {
-    if (!ctx)
-        return RC_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->last_error.clear();
     rc_status st = check_sinc(ctx, k);
     if (st != RC_OK)
         return st;
@@ -631,6 +629,106 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
     return RC_OK;
 }
 
+rc_status get_farrow_coef(rc_context ctx, const rc_sinc &k, const float **out)
+{
+    const double beta = k.window == RC_WIN_KAISER ? k.kaiser_beta : 0.0;
+    const auto key = std::make_pair(std::make_pair((int)k.half_width, (int)k.window), beta);
+    auto it = ctx->farrow_coefs.find(key);
+    if (it == ctx->farrow_coefs.end()) {
+        void *t = nullptr;
+        hipError_t e = rc::build_farrow_coef(k, &t, ctx->allocs);
+        if (e != hipSuccess)
+            return device_fail(ctx, e, "building the filter-bank coefficients");
+        it = ctx->farrow_coefs.emplace(key, t).first;
+    }
+    *out = static_cast<const float *>(it->second);
+    return RC_OK;
+}
+
+}  // namespace
+
+rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_len, rc_c64 *y_packed,
+                              int64_t y_len, const rc_pulse *pulses, int32_t count, const rc_sinc *k,
+                              void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    return pulse_batch_locked(ctx, x_packed, x_len, y_packed, y_len, pulses, count, k, stream);
+}
+
+rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c64 *y, int64_t n_out, double fs_hz,
+                               const double *alphas, int32_t n_hyp, const rc_sinc *k, int32_t mode, void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    rc_status st = check_sinc(ctx, k);
+    if (st != RC_OK)
+        return st;
+    if (!x || !y || !alphas)
+        return fail(ctx, RC_ERR_INVALID_ARG, "NULL pointer");
+    if (n <= 0 || n_out <= 0 || n_hyp <= 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "n, n_out and n_hyp must be > 0");
+    if (!(std::isfinite(fs_hz) && fs_hz > 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "fs_hz must be finite and > 0");
+    if (mode != RC_BANK_AUTO && mode != RC_BANK_FARROW && mode != RC_BANK_PER_HYPOTHESIS)
+        return fail(ctx, RC_ERR_INVALID_ARG, "unknown bank mode");
+    for (int32_t h = 0; h < n_hyp; ++h)
+        if (!(std::isfinite(alphas[h]) && alphas[h] > 0.0))
+            return fail(ctx, RC_ERR_INVALID_ARG, "hypothesis " + std::to_string(h) + ": alpha must be finite and > 0");
+    if (n_out > INT64_MAX / 8 / n_hyp)
+        return fail(ctx, RC_ERR_INVALID_ARG, "output size overflows");
+    if (overlaps(x, n * 8, y, n_out * n_hyp * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "x and y overlap");
+    const bool farrow = mode != RC_BANK_PER_HYPOTHESIS && rc::farrow_eligible(*k, alphas, n_hyp);
+    if (mode == RC_BANK_FARROW && !farrow)
+        return fail(ctx, RC_ERR_UNSUPPORTED,
+                    "the filter bank needs a Kaiser or rectangular window, 1 <= H <= 256 and 0 < alpha <= 2");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!farrow) {
+        std::vector<rc_pulse> pulses((size_t)n_hyp);
+        for (int32_t h = 0; h < n_hyp; ++h) {
+            rc_pulse &p = pulses[(size_t)h];
+            p = rc_pulse{};
+            p.off_in = 0;
+            p.n_in = n;
+            p.off_out = (int64_t)h * n_out;
+            p.n_out = n_out;
+            p.fs_hz = fs_hz;
+            p.alpha = alphas[h];
+            p.carrier_hz = 0.0;
+            p.flags = RC_DO_DOPPLER;
+            p.direction = RC_CORRECT;
+        }
+        return pulse_batch_locked(ctx, x, n, y, n_out * n_hyp, pulses.data(), n_hyp, k, stream);
+    }
+    const float *coef = nullptr;
+    st = get_farrow_coef(ctx, *k, &coef);
+    if (st != RC_OK)
+        return st;
+    const rc::FarrowPlan plan = rc::plan_farrow_bank(n, n_out, k->half_width, alphas, n_hyp);
+    if (plan.lds_bytes > 160 * 1024)
+        return fail(ctx, RC_ERR_UNSUPPORTED, "filter-bank tile exceeds LDS");
+    std::vector<char> desc(rc::farrow_desc_bytes(plan));
+    rc::farrow_pack_desc(plan, desc.data());
+    const void *dev = nullptr;
+    st = stage_descriptors(ctx, desc.data(), desc.size(), plan.z_bytes, s, &dev);
+    if (st != RC_OK)
+        return st;
+    char *devc = static_cast<char *>(const_cast<void *>(dev));
+    hipError_t e = rc::launch_farrow_bank(plan, reinterpret_cast<const float2 *>(x), n, reinterpret_cast<float2 *>(y),
+                                          n_out, k->half_width, coef, devc, devc + ((desc.size() + 255) & ~(size_t)255),
+                                          s, prof_of(ctx));
+    st = mark_descriptors_used(ctx, s);
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "Doppler bank launch");
+    return st;
+}
+
 rc_status rc_set_sinc_engine(rc_context ctx, int32_t engine)
 {
     if (!ctx)
@@ -679,7 +777,7 @@ namespace rc {
 
 const char *const kKernelNames[kKGroups] = {"k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd",
                                             "k_fft_rows_iono", "k_fft_strided_inv", "k_sinc_mfma",
-                                            "k_mf_tile_list", "k_bluestein"};
+                                            "k_mf_tile_list", "k_bluestein", "k_farrow_z", "k_farrow_bank"};
 
 hipEvent_t Profiler::take()
 {

@@ -23,6 +23,8 @@ enum KernelGroup {
     kKSincMfma,
     kKSincTiles,
     kKBluestein,
+    kKFarrowZ,
+    kKFarrowBank,
     kKGroups
 };
 extern const char *const kKernelNames[kKGroups];
@@ -141,6 +143,34 @@ hipError_t launch_sinc_direct(const SincJob *jobs_dev, const SincJob *job_inline
                               int64_t max_taps, hipStream_t s, Profiler *prof);
 
 // ---------------------------------------------------------------------------------------
+// Doppler bank (Farrow filter bank, bank.hip)
+
+constexpr int kFarrowOrders = 8;            // Chebyshev terms per tap weight
+constexpr int kFarrowMaxHalfWidth = 256;
+constexpr double kFarrowMaxAlpha = 2.0;     // keeps a workgroup's Z rows within LDS
+struct FarrowPlan {
+    int n_hyp = 0;
+    std::vector<double> alpha;              // sorted ascending
+    std::vector<int> hyp;                   // original hypothesis index of each sorted entry
+    struct Group {
+        int first, count;
+    };
+    std::vector<Group> groups;              // consecutive sorted hypotheses sharing a workgroup
+    int max_rows = 0;                       // Z rows one workgroup stages
+    int64_t F = 0;                          // Z rows computed (input positions 0 .. F-1)
+    size_t z_bytes = 0;
+    size_t lds_bytes = 0;
+};
+bool farrow_eligible(const rc_sinc &k, const double *alphas, int n_hyp);
+hipError_t build_farrow_coef(const rc_sinc &k, void **dev, std::vector<void *> &allocs);
+FarrowPlan plan_farrow_bank(int64_t n, int64_t n_out, int H, const double *alphas, int n_hyp);
+size_t farrow_desc_bytes(const FarrowPlan &p);
+void farrow_pack_desc(const FarrowPlan &p, char *host);
+// desc_dev: farrow_pack_desc() uploaded; z_work: p.z_bytes of device memory
+hipError_t launch_farrow_bank(const FarrowPlan &p, const float2 *x, int64_t n, float2 *y, int64_t n_out, int H,
+                              const float *coef, const void *desc_dev, void *z_work, hipStream_t s, Profiler *prof);
+
+// ---------------------------------------------------------------------------------------
 // FFT / ionosphere
 // ---------------------------------------------------------------------------------------
 
@@ -203,6 +233,7 @@ struct rc_context_s {
     float2 *tw4096 = nullptr;                  // base twiddles exp(-2 pi i q / 4096)
     std::map<int64_t, rc::FftPlan> plans;      // by transform length
     std::map<std::pair<int, double>, void *> mfma_tables;  // by (half width, Kaiser beta)
+    std::map<std::pair<std::pair<int, int>, double>, void *> farrow_coefs;  // by ((H, window), beta)
     std::vector<void *> allocs;                // every device allocation owned
     // descriptor staging: a ring of pinned host + device slots; a slot is reused only after the
     // work that read it has completed (its event)
