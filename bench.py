@@ -46,12 +46,12 @@ def log(msg):
 
 
 def make_workload(pulses: int):
-    c = wf.C2
+    c = wf.BATCH
     n = c["n"]
-    v, e = wf.c2_params(pulses)
+    v, e = wf.batch_params(pulses)
     x = np.empty(pulses * n, np.complex64)
     for p in range(pulses):
-        x[p * n:(p + 1) * n] = wf.c2_pulse(p)
+        x[p * n:(p + 1) * n] = wf.batch_pulse(p)
     desc = [dict(off_in=p * n, n_in=n, off_out=p * n, n_out=n, fs=c["fs"], alpha=alpha_exact(v[p]), tec=e[p],
                  carrier=c["carrier"]) for p in range(pulses)]
     return x, desc
@@ -131,7 +131,7 @@ def cpu_baseline(x, desc, y_gpu, seconds: float):
     import oracle
 
     oracle.build()
-    c = wf.C2
+    c = wf.BATCH
     n = c["n"]
     errs = []
     t_total, done = 0.0, 0
@@ -152,12 +152,129 @@ def cpu_baseline(x, desc, y_gpu, seconds: float):
                                         f"{t_total:.1f} s"}, max(errs)
 
 
+def timed(torch, ctx, step, steps: int, warmup: int):
+    """ms per step over `steps` after `warmup`, and the library's per-kernel averages."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_read()
+    ctx.profile(True)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    ctx.profile(False)
+    kt = ctx.profile_read()
+    kernels = {k: {"avg_ms": round(v / cnt, 4), "launches_per_step": cnt / steps,
+                   "share": round(v / (ms * steps), 4)} for k, (v, cnt) in kt.items() if cnt}
+    return ms, kt, kernels
+
+
+def run_bank(args, torch, rc):
+    """One 2^20-sample polyphase pulse resampled for 256 Doppler hypotheses (correct_doppler_bank)."""
+    c = wf.BANK
+    n, nh = c["n"], c["hypotheses"]
+    xh = wf.polyphase_code(n, wf.rng_for(c["seed"], 0))
+    alphas = [alpha_exact(v) for v in wf.bank_range_rates(nh)]
+    x = torch.from_numpy(xh).cuda()
+    y = torch.empty((nh, n), dtype=torch.complex64, device="cuda")
+    ctx = rc.Context(0)
+    sinc = rc.Sinc(c["half_width"], "kaiser", c["beta"])
+    log(f"[bench] bank: {nh} hypotheses x {n} samples")
+    ms, kt, kernels = timed(torch, ctx, lambda: ctx.correct_doppler_bank(x, alphas, sinc, out=y), args.steps,
+                            args.warmup)
+    outputs = nh * n
+    value = outputs / (ms * 1e-3)
+    per_ms, _, _ = timed(torch, ctx, lambda: ctx.correct_doppler_bank(x, alphas, sinc, out=y,
+                                                                      mode="per_hypothesis"), 3, 1)
+    ctx.correct_doppler_bank(x, alphas, sinc, out=y)
+    dom = max(kt, key=lambda k: kt[k][0])
+    dom_ms = kt[dom][0] / kt[dom][1]
+    byts = 8.0 * outputs + 8.0 * n  # every output written once, the pulse read once
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(byts / (dom_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(byts / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "algorithmic_per_launch": byts, "avg_launch_ms": round(dom_ms, 4), "traffic": None}
+    cpu, err = None, None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        t_total, done, errs = 0.0, 0, []
+        for h in (0, 85, 170, 255, 42, 213, 128, 127):
+            if t_total > args.cpu_seconds and done >= 2:
+                break
+            t0 = time.perf_counter()
+            ref = oracle.doppler(xh, alphas[h], c["half_width"], "kaiser", c["beta"])
+            t_total += time.perf_counter() - t0
+            got = y[h].cpu().numpy()
+            errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+            done += 1
+        cpu = {"value": round(done * n / t_total, 1), "unit": "samples/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": f"{done} of {nh} hypotheses x {n} outputs, {t_total:.1f} s"}
+        err = max(errs)
+    out = {"metric": "Doppler-bank resampled samples/s at <=1e-5 rel err (hypotheses x outputs)",
+           "value": round(value, 1), "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"one {n}-sample polyphase code (64 phases, 4 samples/chip) x {nh} Doppler "
+                                  f"hypotheses evenly in [-8, 8] km/s, Kaiser H=64 beta=8",
+                      "hypotheses": nh, "samples": n, "half_width": c["half_width"], "beta": c["beta"]},
+           "roofline": roof, "cpu_baseline": cpu, "rel_err_max_sampled": err, "kernels": kernels,
+           "per_hypothesis_ms": round(per_ms, 4)}
+    print(json.dumps(out), flush=True)
+
+
+def run_long(args, torch, rc):
+    """64 pulses of 2^24 samples at H = 128: Doppler then the 2^24-point ionospheric FFT."""
+    c = wf.LONG_DWELL
+    n, P = c["n"], c["pulses"]
+    log(f"[bench] long: {P} x {n} band-limited noise pulses, generated on the device")
+    # band-limited complex Gaussian noise (passband 0.8 fs) drawn with a seeded device generator
+    g = torch.Generator(device="cuda")
+    g.manual_seed(c["seed"])
+    x = torch.empty(P * n, dtype=torch.complex64, device="cuda")
+    k = torch.fft.fftfreq(n, device="cuda")
+    keep = (k.abs() <= 0.4)
+    scale = float(np.sqrt(n / int(keep.sum().item())))
+    for p in range(P):
+        w = torch.complex(torch.randn(n, generator=g, device="cuda"), torch.randn(n, generator=g, device="cuda"))
+        w = w * keep / np.sqrt(2.0)
+        x[p * n:(p + 1) * n] = torch.fft.ifft(w) * (scale * np.sqrt(n))  # unit mean power, as waveforms.py
+    y = torch.empty_like(x)
+    rng = wf.rng_for(c["seed"], 0)
+    v = wf.draw_range_rates(P, rng)
+    e = wf.draw_tec(P, rng)
+    desc = [dict(off_in=p * n, n_in=n, off_out=p * n, n_out=n, fs=c["fs"], alpha=alpha_exact(v[p]), tec=e[p],
+                 carrier=c["carrier"]) for p in range(P)]
+    ctx = rc.Context(0)
+    sinc = rc.Sinc(c["half_width"], "kaiser", c["beta"])
+    steps = max(1, min(args.steps, 5))
+    ms, kt, kernels = timed(torch, ctx, lambda: ctx.correct_pulse_batch(x, y, desc, sinc), steps,
+                            max(1, min(args.warmup, 2)))
+    samples = P * n
+    dom = max(kt, key=lambda kk: kt[kk][0])
+    roof = roofline_for(dom, kt[dom][0] / kt[dom][1], int(samples * steps / kt[dom][1]), c["half_width"], 1.0)
+    out = {"metric": "corrected complex samples/s at <=1e-5 rel err (long pulses)", "value": round(samples / (ms * 1e-3), 1),
+           "unit": "samples/s", "n_gpus": 1, "steps": steps, "warmup": max(1, min(args.warmup, 2)),
+           "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{P} pulses x {n} complex64 band-limited noise, Kaiser sinc H=128 beta=8, "
+                                  f"v_r~U[-8,8] km/s, iono E~U[5,100] TECU at 450 MHz, fs 10 MHz",
+                      "pulses": P, "samples_per_pulse": n, "half_width": c["half_width"], "beta": c["beta"]},
+           "roofline": roof, "cpu_baseline": None, "kernels": kernels}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--pulses", type=int, default=wf.C2["pulses"])
+    ap.add_argument("--pulses", type=int, default=wf.BATCH["pulses"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -166,6 +283,9 @@ def main():
                          "HBM traffic counters)")
     ap.add_argument("--engine", choices=["auto", "valu", "direct"], default="auto",
                     help="resampling engine (auto: matrix cores where eligible)")
+    ap.add_argument("--workload", choices=["batch", "bank", "long"], default="batch",
+                    help="batch: 1024 x 65536 pulses (the headline); bank: one 2^20-sample pulse x 256 "
+                         "Doppler hypotheses; long: 64 x 2^24-sample pulses at H = 128")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -178,8 +298,12 @@ def main():
     import paper_2508_04951_amd as rc
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "bank":
+        return run_bank(args, torch, rc)
+    if args.workload == "long":
+        return run_long(args, torch, rc)
     dev = torch.device("cuda:0")
-    c = wf.C2
+    c = wf.BATCH
     n = c["n"]
     P = args.pulses
     log(f"[bench] generating {P} x {n} band-limited noise pulses")

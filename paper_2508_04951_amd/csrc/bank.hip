@@ -111,7 +111,9 @@ k_farrow_bank(const float2 *__restrict__ Z, int64_t F, const float2 *__restrict_
               const double *__restrict__ alpha, const int *__restrict__ hyp, const BankGroup *__restrict__ groups,
               int64_t n_out, float2 *__restrict__ y, int max_rows)
 {
-    extern __shared__ __attribute__((aligned(16))) float4 zs[];  // rows x (R / 2) float4
+    // LDS: the group's Z rows (R / 2 float4 each), then the input samples at the same positions
+    // (an exact sample instant reads LDS, so no load ever sits between two output stores)
+    extern __shared__ __attribute__((aligned(16))) float4 zs[];
     const int tid = threadIdx.x;
     const BankGroup g = gload(groups, blockIdx.y);
     const int64_t m0 = (int64_t)blockIdx.x * kBankM;
@@ -123,36 +125,68 @@ k_farrow_bank(const float2 *__restrict__ Z, int64_t F, const float2 *__restrict_
     const int rows = (int)(fmax - fmin + 1);
     if (rows > max_rows)
         return;  // the host sizes groups so this never happens; uniform over the workgroup
+    // staging in rounds of 8 loads per thread, issued before any is waited for; indices are
+    // clamped into the buffers and what lies outside them is zeroed
     const auto zg = gmem(reinterpret_cast<const float4 *>(Z));
-    for (int e = tid; e < rows * (kR / 2); e += kBankThreads) {
-        const int64_t f = fmin + e / (kR / 2);
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (f < F)
-            v = zg[fmin * (kR / 2) + e];
-        zs[e] = v;
+    const int64_t zlast = F * (kR / 2) - 1;
+    for (int e0 = 0; e0 < rows * (kR / 2); e0 += 8 * kBankThreads) {
+        float4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t gi = fmin * (kR / 2) + e0 + u * kBankThreads + tid;
+            const float4 t = zg[gi < zlast ? gi : zlast];
+            const bool ok = gi <= zlast;
+            v[u] = make_float4(ok ? t.x : 0.f, ok ? t.y : 0.f, ok ? t.z : 0.f, ok ? t.w : 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kBankThreads + tid;
+            if (e < rows * (kR / 2))
+                zs[e] = v[u];
+        }
+    }
+    float2 *xs = reinterpret_cast<float2 *>(zs + max_rows * (kR / 2));
+    const auto xg = gmem(x);
+    for (int e0 = 0; e0 < rows; e0 += 8 * kBankThreads) {
+        float2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t f = fmin + e0 + u * kBankThreads + tid;
+            const float2 t = xg[f < n ? f : n - 1];
+            v[u] = make_float2(f < n ? t.x : 0.f, f < n ? t.y : 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kBankThreads + tid;
+            if (e < rows)
+                xs[e] = v[u];
+        }
     }
     __syncthreads();
     const auto yg = gmem(y);
+    constexpr int Q = kBankM / kBankThreads;
+    double md[Q];  // this thread's output indices, as doubles (exact below 2^53)
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        md[q] = (double)(m0 + tid + kBankThreads * q);
+    const bool full = m0 + kBankM <= n_out;  // uniform: no output of the block past n_out
+    const double fmind = (double)fmin;
     for (int i = 0; i < g.count; ++i) {
         const double a = gload(alpha, g.first + i);
-        const auto yh = yg + (int64_t)gload(hyp, g.first + i) * n_out;
+        const auto yh = yg + (int64_t)gload(hyp, g.first + i) * n_out + m0 + tid;
 #pragma unroll
-        for (int q = 0; q < kBankM / kBankThreads; ++q) {
-            const int64_t m = m0 + tid + kBankThreads * q;
-            if (m >= n_out)
+        for (int q = 0; q < Q; ++q) {
+            if (!full && m0 + tid + kBankThreads * q >= n_out)
                 continue;
-            const double t = __dmul_rn(a, (double)m);
+            const double t = __dmul_rn(a, md[q]);
             const double fd = floor(t);
-            const int64_t f = (int64_t)fd;
             float2 out;
             if (t == fd) {  // exact sample instant: the input sample itself
-                out = make_float2(0.f, 0.f);
-                if (f < n)
-                    out = gload(x, f);
+                out = xs[(int)(fd - fmind)];
             } else {
                 // Clenshaw: b_r = Z_r + 2 s b_{r+1} - b_{r+2};  y = Z_0 + s b_1 - b_2,  s = 2 mu - 1
                 const float s = (float)(2.0 * (t - fd) - 1.0);
-                const float4 *row = zs + (f - fmin) * (kR / 2);
+                const float4 *row = zs + (int)(fd - fmind) * (kR / 2);
                 float zr[kR], zi[kR];
 #pragma unroll
                 for (int q2 = 0; q2 < kR / 2; ++q2) {
@@ -174,7 +208,7 @@ k_farrow_bank(const float2 *__restrict__ Z, int64_t F, const float2 *__restrict_
                 }
                 out = make_float2(fmaf(s, b1r, zr[0] - b2r), fmaf(s, b1i, zi[0] - b2i));
             }
-            yh[m] = out;
+            yh[kBankThreads * q] = out;
         }
     }
 }
@@ -244,7 +278,7 @@ FarrowPlan plan_farrow_bank(int64_t n, int64_t n_out, int H, const double *alpha
     if (p.F < 1)
         p.F = 1;
     p.z_bytes = (size_t)p.F * kR * sizeof(float2);
-    p.lds_bytes = (size_t)p.max_rows * kR * sizeof(float2);
+    p.lds_bytes = (size_t)p.max_rows * (kR + 1) * sizeof(float2);  // Z rows, then the samples
     return p;
 }
 

@@ -571,6 +571,8 @@ hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs)
         plan.levels = 1;
         plan.len[0] = (int)n;
     } else {
+        // strided levels of up to 256 points (fewer passes; a 2^24 transform measured faster as
+        // 256 x 16 x 4096 than as 16 x 16 x 16 x 4096, whose first pass strides 8 MB)
         int rest = p - 12;
         int d = 0;
         while (rest > 0) {

@@ -120,7 +120,7 @@ def test_bank_full_size_sampled(torch, ctx, orc):
     on 3000 sampled outputs each (rel-L2 over the sample)."""
     import paper_2508_04951_amd as rc
 
-    c = wf.C3
+    c = wf.BANK
     n, nh = c["n"], c["hypotheses"]
     xh = wf.polyphase_code(n, wf.rng_for(c["seed"], 0))
     alphas = [alpha_exact(v) for v in wf.bank_range_rates(nh)]

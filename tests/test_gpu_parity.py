@@ -113,7 +113,7 @@ def engine(ctx, request):
 def test_doppler_fast_paths_at_pulse_length(torch, ctx, orc, engine, v, hw):
     """The matrix-core ("auto") and vector tile kernels at the batch pulse length 65536, with a
     ragged tail; 9 and 14 km/s leave the matrix-core range and take the vector kernel."""
-    x = wf.c2_pulse(3)
+    x = wf.batch_pulse(3)
     alpha = alpha_exact(v)
     for n_out in (65536, 65536 - 333, 70000):
         y = host(ctx.correct_doppler(dev(torch, x), alpha, sinc(hw), n_out=n_out))
@@ -232,7 +232,7 @@ def test_c1_single_lfm_pulse(torch, ctx, orc):
     then ionospheric correction at 50 TECU, carrier 450 MHz."""
     import paper_2508_04951_amd as rc
 
-    c = wf.C1
+    c = wf.SINGLE_LFM
     x = wf.lfm(c["n"], c["fs"], c["bandwidth"])
     alpha = alpha_exact(c["v_r"])
     ref = orc.correct_pulse(x, c["fs"], alpha, c["tec"], c["carrier"], half_width=0, naive=True)
@@ -301,12 +301,12 @@ def test_batch_c2_full_size_sampled(torch, ctx, orc):
     four seeded pulses compared in full against the oracle, all pulses finite."""
     import paper_2508_04951_amd as rc
 
-    c = wf.C2
+    c = wf.BATCH
     n, P = c["n"], c["pulses"]
-    v, e = wf.c2_params()
+    v, e = wf.batch_params()
     x = np.empty(P * n, np.complex64)
     for p in range(P):
-        x[p * n:(p + 1) * n] = wf.c2_pulse(p)
+        x[p * n:(p + 1) * n] = wf.batch_pulse(p)
     pulses = [dict(off_in=p * n, n_in=n, off_out=p * n, n_out=n, fs=c["fs"], alpha=alpha_exact(v[p]),
                    tec=e[p], carrier=c["carrier"]) for p in range(P)]
     xd = dev(torch, x)
@@ -361,7 +361,7 @@ def test_batch_tile_list_matches_single_calls(torch, ctx, orc):
 def test_repeat_runs_are_bit_identical(torch, ctx):
     import paper_2508_04951_amd as rc
 
-    x = dev(torch, wf.c2_pulse(7))
+    x = dev(torch, wf.batch_pulse(7))
     a = alpha_exact(-6543.0)
     y1 = host(ctx.correct_ionosphere(ctx.correct_doppler(x, a, rc.Sinc(64)), 10e6, 450e6, 30 * wf.TECU))
     y2 = host(ctx.correct_ionosphere(ctx.correct_doppler(x, a, rc.Sinc(64)), 10e6, 450e6, 30 * wf.TECU))

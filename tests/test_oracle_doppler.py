@@ -116,9 +116,9 @@ def test_multitone_matches_closed_form(orc, alpha):
 # --- D4: analytic LFM (the paper's "DIR" control case) -------------------------------------
 
 def test_lfm_matches_analytic_resampling(orc):
-    """The c1 LFM resampled numerically equals the LFM regenerated at alpha t: start frequency
+    """The single-LFM workload pulse resampled numerically equals the LFM regenerated at alpha t: start frequency
     scaled by alpha, chirp rate by alpha^2 (Eq 2; analytic resampling, Sec. I / Table I)."""
-    c = wf.C1
+    c = wf.SINGLE_LFM
     n, fs, B = c["n"], c["fs"], c["bandwidth"]
     alpha = orc.alpha_from_vr(c["v_r"])
     x = wf.lfm(n, fs, B)
@@ -148,7 +148,7 @@ def _snr_loss_db(a, b, max_lag=3):
 def test_window_convergence_is_inverse_square_in_snr_loss(orc):
     """Table I: windowed Whittaker-Shannon accuracy O(N_window^-2) for LFMs (found numerically
     by the authors).  Read as the SNR loss, which goes as the square of the sample error."""
-    c = wf.C1
+    c = wf.SINGLE_LFM
     n, fs, B = c["n"], c["fs"], c["bandwidth"]
     alpha = orc.alpha_from_vr(c["v_r"])
     x = wf.lfm(n, fs, B)

@@ -6,16 +6,15 @@ tests and the GPU-side tests / benchmark draw their inputs from here, so the two
 sides see bit-identical complex64 samples.
 
 Workload shapes follow the paper's synthetic test signals (LFM pulses, Sec. II-C
-and III; no public dataset is used by the paper) and the five benchmark
-configurations of this project:
+and III; no public dataset is used by the paper):
 
-  c1  single LFM pulse, N = 4096, fs = 10 MHz, B = 5 MHz, v_r = +7.5 km/s,
-      full sinc + iono (E = 50 TECU, carrier 450 MHz)
-  c2  batch of 1024 pulses x 65536 band-limited complex Gaussian noise
-      (passband 0.8 fs), v_r ~ U[-8, 8] km/s, E ~ U[5, 100] TECU, Kaiser H = 64, beta = 8
-  c3  Doppler bank: one 2^20 polyphase-coded pulse, 256 v_r hypotheses in [-8, 8] km/s
-  c4  serving stream: Poisson arrivals at 2000 pulses/s, lengths log-uniform 2^12..2^22
-  c5  long dwell: 64 pulses x 2^24 band-limited noise, H = 128
+  SINGLE_LFM  single LFM pulse, N = 4096, fs = 10 MHz, B = 5 MHz, v_r = +7.5 km/s,
+              full sinc + iono (E = 50 TECU, carrier 450 MHz)
+  BATCH       1024 pulses x 65536 band-limited complex Gaussian noise (passband 0.8 fs),
+              v_r ~ U[-8, 8] km/s, E ~ U[5, 100] TECU, Kaiser H = 64, beta = 8
+  BANK        Doppler bank: one 2^20 polyphase-coded pulse, 256 v_r hypotheses in [-8, 8] km/s
+  SERVING     serving stream: Poisson arrivals at 2000 pulses/s, lengths log-uniform 2^12..2^22
+  LONG_DWELL  64 pulses x 2^24 band-limited noise, H = 128
 """
 from __future__ import annotations
 
@@ -97,29 +96,29 @@ def loguniform_lengths(count: int, rng: np.random.Generator, lo_exp: float = 12.
     return np.floor(2.0 ** rng.uniform(lo_exp, hi_exp, size=count)).astype(np.int64)
 
 
-# --- the five benchmark configurations (seed = config index) -------------------------------
+# --- the workloads (seed 1 .. 5 in the order above) ----------------------------------------
 
-C1 = dict(name="c1_single_lfm", seed=1, n=4096, fs=10e6, bandwidth=5e6, v_r=7500.0,
+SINGLE_LFM = dict(name="single_lfm_4096", seed=1, n=4096, fs=10e6, bandwidth=5e6, v_r=7500.0,
           tec=50 * TECU, carrier=450e6, half_width=0)
-C2 = dict(name="c2_batch_1024x65536", seed=2, pulses=1024, n=65536, fs=FS_DEFAULT,
+BATCH = dict(name="batch_1024x65536", seed=2, pulses=1024, n=65536, fs=FS_DEFAULT,
           carrier=CARRIER_DEFAULT, half_width=64, beta=8.0, passband=0.8)
-C3 = dict(name="c3_doppler_bank_256x2^20", seed=3, n=1 << 20, hypotheses=256, fs=FS_DEFAULT,
+BANK = dict(name="doppler_bank_256x2^20", seed=3, n=1 << 20, hypotheses=256, fs=FS_DEFAULT,
           half_width=64, beta=8.0)
-C4 = dict(name="c4_serving_poisson_2000hz", seed=4, rate_hz=2000.0, lo_exp=12.0, hi_exp=22.0,
+SERVING = dict(name="serving_poisson_2000hz", seed=4, rate_hz=2000.0, lo_exp=12.0, hi_exp=22.0,
           fs=FS_DEFAULT, carrier=CARRIER_DEFAULT, half_width=64, beta=8.0)
-C5 = dict(name="c5_long_dwell_64x2^24", seed=5, pulses=64, n=1 << 24, fs=FS_DEFAULT,
+LONG_DWELL = dict(name="long_dwell_64x2^24", seed=5, pulses=64, n=1 << 24, fs=FS_DEFAULT,
           carrier=CARRIER_DEFAULT, half_width=128, beta=8.0)
 
 
-def c2_pulse(p: int, n: int | None = None) -> np.ndarray:
-    """Samples of pulse p of the c2 batch (band-limited noise, passband 0.8 fs)."""
-    return bandlimited_noise(C2["n"] if n is None else n, rng_for(C2["seed"], p + 1), C2["passband"])
+def batch_pulse(p: int, n: int | None = None) -> np.ndarray:
+    """Samples of pulse p of the batch workload (band-limited noise, passband 0.8 fs)."""
+    return bandlimited_noise(BATCH["n"] if n is None else n, rng_for(BATCH["seed"], p + 1), BATCH["passband"])
 
 
-def c2_params(pulses: int | None = None) -> tuple[np.ndarray, np.ndarray]:
-    """(v_r [m/s], E [el/m^2]) for every pulse of the c2 batch."""
-    count = C2["pulses"] if pulses is None else pulses
-    rng = rng_for(C2["seed"], 0)
+def batch_params(pulses: int | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """(v_r [m/s], E [el/m^2]) for every pulse of the batch workload."""
+    count = BATCH["pulses"] if pulses is None else pulses
+    rng = rng_for(BATCH["seed"], 0)
     v = draw_range_rates(count, rng)
     e = draw_tec(count, rng)
     return v, e
