@@ -233,17 +233,7 @@ def run_long(args, torch, rc):
     c = wf.LONG_DWELL
     n, P = c["n"], c["pulses"]
     log(f"[bench] long: {P} x {n} band-limited noise pulses, generated on the device")
-    # band-limited complex Gaussian noise (passband 0.8 fs) drawn with a seeded device generator
-    g = torch.Generator(device="cuda")
-    g.manual_seed(c["seed"])
-    x = torch.empty(P * n, dtype=torch.complex64, device="cuda")
-    k = torch.fft.fftfreq(n, device="cuda")
-    keep = (k.abs() <= 0.4)
-    scale = float(np.sqrt(n / int(keep.sum().item())))
-    for p in range(P):
-        w = torch.complex(torch.randn(n, generator=g, device="cuda"), torch.randn(n, generator=g, device="cuda"))
-        w = w * keep / np.sqrt(2.0)
-        x[p * n:(p + 1) * n] = torch.fft.ifft(w) * (scale * np.sqrt(n))  # unit mean power, as waveforms.py
+    x = device_noise(torch, n, P, c["seed"]).reshape(-1)
     y = torch.empty_like(x)
     rng = wf.rng_for(c["seed"], 0)
     v = wf.draw_range_rates(P, rng)
@@ -269,6 +259,122 @@ def run_long(args, torch, rc):
     print(json.dumps(out), flush=True)
 
 
+def device_noise(torch, n: int, count: int, seed: int, passband: float = 0.8):
+    """`count` pulses of band-limited complex Gaussian noise (unit mean power), drawn on the
+    device with a seeded generator: the construction of waveforms.bandlimited_noise."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    k = torch.fft.fftfreq(n, device="cuda")
+    keep = k.abs() <= 0.5 * passband
+    scale = float(np.sqrt(n / int(keep.sum().item())))
+    out = torch.empty((count, n), dtype=torch.complex64, device="cuda")
+    for p in range(count):
+        w = torch.complex(torch.randn(n, generator=g, device="cuda"), torch.randn(n, generator=g, device="cuda"))
+        out[p] = torch.fft.ifft(w * keep / np.sqrt(2.0)) * (scale * np.sqrt(n))
+    return out
+
+
+def run_serving(args, torch, rc):
+    """Poisson arrivals at 2000 pulses/s, lengths floor(2^U), U ~ U[12, 22], each Doppler then
+    ionosphere, through the continuous-batching server; the same sequence through the plain
+    one-pulse-at-a-time path; and the server at saturation (all requests at once)."""
+    c = wf.SERVING
+    nreq = args.requests
+    rng = wf.rng_for(c["seed"], 0)
+    arrivals = wf.poisson_arrivals(c["rate_hz"], nreq, rng)
+    lens = wf.loguniform_lengths(nreq, rng, c["lo_exp"], c["hi_exp"])
+    v = wf.draw_range_rates(nreq, rng)
+    e = wf.draw_tec(nreq, rng)
+    alphas = [alpha_exact(vv) for vv in v]
+    nmax = 1 << int(np.ceil(c["hi_exp"]))
+    pool_n = 16
+    log(f"[bench] serving: {nreq} requests, mean length {lens.mean():.0f}; pool of {pool_n} x {nmax} inputs")
+    xs = device_noise(torch, nmax, pool_n, c["seed"])
+    nbuf = 64
+    ys = torch.empty((nbuf, nmax), dtype=torch.complex64, device="cuda")
+    ctx = rc.Context(0)
+    sinc = rc.Sinc(c["half_width"], "kaiser", c["beta"])
+    samples = int(lens.sum())
+
+    def request(i):
+        n = int(lens[i])
+        return xs[i % pool_n, :n], ys[i % nbuf, :n]
+
+    srv = rc.Server(ctx, sinc, mem_budget_bytes=64 << 30, max_batch=256)
+    # warm-up: every transform plan and table the sequence needs
+    for i in range(nreq):
+        x, y = request(i)
+        srv.submit(x, y, alpha=alphas[i], tec=e[i], carrier=c["carrier"], fs=c["fs"])
+        if i % nbuf == nbuf - 1:
+            srv.wait()
+    srv.wait()
+    srv.reset_stats()
+
+    def paced(submit_one):
+        t0 = time.perf_counter()
+        for i in range(nreq):
+            while time.perf_counter() - t0 < arrivals[i]:
+                pass
+            submit_one(i)
+
+    # 1) the server at the offered rate
+    slot_ticket = {}
+
+    def submit_server(i):
+        b = i % nbuf
+        if b in slot_ticket:
+            srv.wait(slot_ticket.pop(b))  # the output buffer is reused only when its last request is done
+        x, y = request(i)
+        slot_ticket[b] = srv.submit(x, y, alpha=alphas[i], tec=e[i], carrier=c["carrier"], fs=c["fs"])
+
+    paced(submit_server)
+    srv.wait()
+    st_rate = srv.stats()
+    srv.reset_stats()
+    slot_ticket.clear()
+    # 2) the server at saturation: every request submitted at once
+    t0 = time.perf_counter()
+    for i in range(nreq):
+        submit_server(i)
+    srv.wait()
+    sat_s = time.perf_counter() - t0
+    st_sat = srv.stats()
+    srv.close()
+    # 3) the plain path at the offered rate: correct_doppler then correct_ionosphere, one pulse at
+    #    a time, each waited for
+    lat = np.zeros(nreq)
+    t0 = time.perf_counter()
+    for i in range(nreq):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        x, y = request(i)
+        tmp = ctx.correct_doppler(x, alphas[i], sinc)
+        ctx.correct_ionosphere(tmp, c["fs"], c["carrier"], e[i], "correct", out=y)
+        torch.cuda.synchronize()
+        lat[i] = (time.perf_counter() - t0 - arrivals[i]) * 1e3
+    out = {"metric": "served corrected samples/s at saturation; p50/p99 end-to-end latency at 2000 pulses/s",
+           "value": round(samples / sat_s, 1), "unit": "samples/s", "n_gpus": 1, "steps": nreq, "warmup": nreq,
+           "ms_per_step": round(sat_s * 1e3 / nreq, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{nreq} requests, Poisson arrivals at {c['rate_hz']:.0f}/s, lengths "
+                                  f"floor(2^U) U~U[{c['lo_exp']:.0f},{c['hi_exp']:.0f}] (mean {lens.mean():.0f}), "
+                                  f"Doppler (Kaiser H=64 beta=8, v_r~U[-8,8] km/s) then iono (E~U[5,100] TECU, "
+                                  f"450 MHz), fs 10 MHz; inputs resident in HBM",
+                      "requests": nreq, "rate_hz": c["rate_hz"], "mean_length": float(lens.mean())},
+           "at_rate": {"latency_ms_p50": round(st_rate["latency_ms_p50"], 4),
+                       "latency_ms_p99": round(st_rate["latency_ms_p99"], 4),
+                       "latency_ms_max": round(st_rate["latency_ms_max"], 4),
+                       "mean_batch": round(st_rate["mean_batch"], 2)},
+           "plain_at_rate": {"latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
+                             "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
+                             "latency_ms_max": round(float(lat.max()), 4)},
+           "saturation": {"samples_per_s": round(samples / sat_s, 1), "mean_batch": round(st_sat["mean_batch"], 2),
+                          "latency_ms_p50": round(st_sat["latency_ms_p50"], 4),
+                          "latency_ms_p99": round(st_sat["latency_ms_p99"], 4)},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,9 +389,11 @@ def main():
                          "HBM traffic counters)")
     ap.add_argument("--engine", choices=["auto", "valu", "direct"], default="auto",
                     help="resampling engine (auto: matrix cores where eligible)")
-    ap.add_argument("--workload", choices=["batch", "bank", "long"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "bank", "long", "serving"], default="batch",
                     help="batch: 1024 x 65536 pulses (the headline); bank: one 2^20-sample pulse x 256 "
-                         "Doppler hypotheses; long: 64 x 2^24-sample pulses at H = 128")
+                         "Doppler hypotheses; long: 64 x 2^24-sample pulses at H = 128; serving: Poisson "
+                         "arrivals at 2000 pulses/s, lengths 2^12..2^22, through the server")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -302,6 +410,8 @@ def main():
         return run_bank(args, torch, rc)
     if args.workload == "long":
         return run_long(args, torch, rc)
+    if args.workload == "serving":
+        return run_serving(args, torch, rc)
     dev = torch.device("cuda:0")
     c = wf.BATCH
     n = c["n"]

@@ -173,6 +173,46 @@ rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c6
                                int64_t n_out, double fs_hz, const double *alphas, int32_t n_hyp,
                                const rc_sinc *k, int32_t mode, void *stream);
 
+/* Serving: a continuous-batching server over independent requests (the paper corrects one
+ * pulse at a time; a radar front end sees a stream of them).  Each request is one pulse,
+ * Doppler first and then the ionosphere as in correct_pulse_batch, on caller-owned device
+ * buffers that must stay valid (and y untouched) until the request completes.  A launcher
+ * thread takes everything queued (up to max_batch requests) as one batch on the server's own
+ * stream as soon as requests are queued, without waiting for earlier batches; a completer
+ * thread times each batch's completion.  Admission is by bytes: a request holds
+ * 8 (n_in + n_out) bytes, plus 32 n_out for an ionospheric length that is not a power of two,
+ * until it completes; rc_server_submit returns RC_ERR_BUSY when the budget is full and
+ * RC_ERR_UNSUPPORTED for a request that could never fit.  Every pulse uses the kernel *k
+ * given at creation.  Output of a request does not depend on what it was batched with. */
+typedef struct rc_server_s *rc_server;
+typedef struct {
+    const rc_c64 *x;        /* device input, n_in samples */
+    rc_c64 *y;              /* device output, n_out samples (may equal x without RC_DO_DOPPLER) */
+    int64_t n_in, n_out;
+    double fs_hz, alpha, tec_el_per_m2, carrier_hz;
+    uint32_t flags;         /* RC_DO_DOPPLER | RC_DO_IONO */
+    int32_t direction;      /* RC_CORRECT | RC_DISTORT */
+} rc_request;
+typedef struct {
+    int64_t submitted, completed, rejected;   /* since creation or the last reset */
+    int64_t batches;                          /* launches */
+    double mean_batch;                        /* requests per launch */
+    double latency_ms_p50, latency_ms_p99, latency_ms_max;  /* submit -> completion observed */
+    double samples_per_s;   /* completed output samples / (last completion - first submission) */
+} rc_server_stats_t;
+rc_status rc_server_create(rc_context ctx, const rc_sinc *k, int64_t mem_budget_bytes,
+                           int32_t max_batch, rc_server *out);
+rc_status rc_server_submit(rc_server srv, const rc_request *req, int64_t *ticket);
+/* done = 1 once the request is complete; a completed ticket is then released (poll again:
+ * RC_ERR_INVALID_ARG).  Returns the request's status when it reports done. */
+rc_status rc_server_poll(rc_server srv, int64_t ticket, int32_t *done);
+/* Block until the ticket (0: every request submitted so far) is complete, then release it. */
+rc_status rc_server_wait(rc_server srv, int64_t ticket);
+rc_status rc_server_stats(rc_server srv, rc_server_stats_t *out);
+rc_status rc_server_reset_stats(rc_server srv);
+/* Launch what is queued, wait for everything, free the server. */
+rc_status rc_server_destroy(rc_server srv);
+
 /* Resampling engine (rc_set_sinc_engine).  Every engine computes the same sum of Eq (17):
  *   RC_SINC_AUTO   matrix cores for the Kaiser taper at H = 64 or 128 and |alpha - 1| <= 6e-5,
  *                  else the vector tile kernel (Kaiser, H <= 256, |alpha - 1| <= 1e-4), else the

@@ -24,7 +24,8 @@ DO_DOPPLER, DO_IONO = 1, 2
 SYMBOLS = (
     "rc_create", "rc_destroy", "rc_status_string", "rc_last_error", "rc_alpha_from_vr",
     "rc_k2_per_tec", "rc_sync", "correct_doppler", "correct_ionosphere", "correct_pulse_batch",
-    "correct_doppler_bank",
+    "correct_doppler_bank", "rc_server_create", "rc_server_submit", "rc_server_poll", "rc_server_wait",
+    "rc_server_stats", "rc_server_reset_stats", "rc_server_destroy",
     "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine",
 )
 KERNELS = ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono",
@@ -43,6 +44,23 @@ class RcPulse(ctypes.Structure):
         ("n_out", ctypes.c_int64), ("fs_hz", ctypes.c_double), ("alpha", ctypes.c_double),
         ("tec_el_per_m2", ctypes.c_double), ("carrier_hz", ctypes.c_double),
         ("flags", ctypes.c_uint32), ("direction", ctypes.c_int32),
+    ]
+
+
+class RcRequest(ctypes.Structure):
+    _fields_ = [
+        ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n_in", ctypes.c_int64), ("n_out", ctypes.c_int64),
+        ("fs_hz", ctypes.c_double), ("alpha", ctypes.c_double), ("tec_el_per_m2", ctypes.c_double),
+        ("carrier_hz", ctypes.c_double), ("flags", ctypes.c_uint32), ("direction", ctypes.c_int32),
+    ]
+
+
+class RcServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+        ("batches", ctypes.c_int64), ("mean_batch", ctypes.c_double), ("latency_ms_p50", ctypes.c_double),
+        ("latency_ms_p99", ctypes.c_double), ("latency_ms_max", ctypes.c_double),
+        ("samples_per_s", ctypes.c_double),
     ]
 
 
@@ -102,6 +120,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.rc_profile_read.restype = c_i32
         lib.rc_set_sinc_engine.argtypes = [p, c_i32]
         lib.rc_set_sinc_engine.restype = c_i32
+        lib.rc_server_create.argtypes = [p, ctypes.POINTER(RcSinc), c_i64, c_i32, ctypes.POINTER(p)]
+        lib.rc_server_submit.argtypes = [p, ctypes.POINTER(RcRequest), ctypes.POINTER(c_i64)]
+        lib.rc_server_poll.argtypes = [p, c_i64, ctypes.POINTER(c_i32)]
+        lib.rc_server_wait.argtypes = [p, c_i64]
+        lib.rc_server_stats.argtypes = [p, ctypes.POINTER(RcServerStats)]
+        lib.rc_server_reset_stats.argtypes = [p]
+        lib.rc_server_destroy.argtypes = [p]
+        for f in ("rc_server_create", "rc_server_submit", "rc_server_poll", "rc_server_wait", "rc_server_stats",
+                  "rc_server_reset_stats", "rc_server_destroy"):
+            getattr(lib, f).restype = c_i32
         _lib = lib
         return lib
 
@@ -287,6 +315,86 @@ class Context:
         if st != RC_OK:
             self._raise(st, "correct_doppler_bank")
         return out
+
+
+class Server:
+    """A continuous-batching server (rc_server) on a Context: submit single-pulse requests on
+    device buffers, wait for tickets, read latency statistics."""
+
+    def __init__(self, ctx: "Context", sinc: Sinc | None = None, mem_budget_bytes: int = 8 << 30,
+                 max_batch: int = 256):
+        self._ctx = ctx  # keeps the context alive
+        self._lib = ctx._lib
+        k = (sinc or Sinc()).c()
+        h = ctypes.c_void_p()
+        st = self._lib.rc_server_create(ctx.handle, ctypes.byref(k), int(mem_budget_bytes), int(max_batch),
+                                        ctypes.byref(h))
+        if st != RC_OK:
+            ctx._raise(st, "rc_server_create")
+        self._h = h
+        self._held = {}  # ticket -> (x, y): the buffers stay referenced until the ticket is released
+
+    def submit(self, x, y, alpha: float = 1.0, tec: float = 0.0, carrier: float = 0.0, fs: float = 1.0,
+               flags: int | None = None, direction: str = "correct", n_out: int | None = None) -> int:
+        """Queue one pulse: x (device complex64) -> y (device complex64, n_out samples)."""
+        _check_samples(x, "x")
+        _check_samples(y, "y")
+        n_out = y.numel() if n_out is None else int(n_out)
+        if n_out > y.numel():
+            raise ValueError("y is shorter than n_out")
+        fl = (DO_DOPPLER | DO_IONO) if flags is None else int(flags)
+        req = RcRequest(x.data_ptr(), y.data_ptr(), x.numel(), n_out, float(fs), float(alpha), float(tec),
+                        float(carrier), fl, DIRECTIONS[direction] if isinstance(direction, str) else int(direction))
+        t = ctypes.c_int64()
+        st = self._lib.rc_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if st != RC_OK:
+            self._ctx._raise(st, "rc_server_submit")
+        self._held[t.value] = (x, y)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int32()
+        st = self._lib.rc_server_poll(self._h, int(ticket), ctypes.byref(done))
+        if st != RC_OK:
+            self._held.pop(int(ticket), None)
+            self._ctx._raise(st, "rc_server_poll")
+        if done.value:
+            self._held.pop(int(ticket), None)
+        return bool(done.value)
+
+    def wait(self, ticket: int = 0):
+        """Block until `ticket` (0: everything submitted so far) completes."""
+        st = self._lib.rc_server_wait(self._h, int(ticket))
+        if ticket == 0:
+            self._held.clear()
+        else:
+            self._held.pop(int(ticket), None)
+        if st != RC_OK:
+            self._ctx._raise(st, "rc_server_wait")
+
+    def stats(self) -> dict:
+        s = RcServerStats()
+        st = self._lib.rc_server_stats(self._h, ctypes.byref(s))
+        if st != RC_OK:
+            self._ctx._raise(st, "rc_server_stats")
+        return {f: getattr(s, f) for f, _ in RcServerStats._fields_}
+
+    def reset_stats(self):
+        st = self._lib.rc_server_reset_stats(self._h)
+        if st != RC_OK:
+            self._ctx._raise(st, "rc_server_reset_stats")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.rc_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _bank_alphas(alphas) -> ctypes.Array:

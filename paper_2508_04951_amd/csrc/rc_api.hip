@@ -1,11 +1,16 @@
 // rc_api.hip -- the extern "C" entry points of librc.so declared in include/rc.h:
 // argument validation, the per-device context, and dispatch to the HIP kernels.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <new>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "rc_internal.h"
@@ -429,6 +434,41 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
 
 namespace {
 
+// One pulse of work, with device pointers (a packed-batch entry, a server request, a bank row).
+struct PulseWork {
+    const float2 *x;
+    float2 *y;
+    int64_t n_in, n_out;
+    double fs_hz, alpha, tec, carrier;
+    uint32_t flags;
+    int32_t direction;
+};
+
+rc_status validate_pulse(rc_context ctx, const PulseWork &p, const std::string &at)
+{
+    if (p.n_in <= 0 || p.n_out <= 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, at + "n_in and n_out must be > 0");
+    if ((p.flags & ~(uint32_t)(RC_DO_DOPPLER | RC_DO_IONO)) != 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, at + "unknown flag bits");
+    if (!(std::isfinite(p.fs_hz) && p.fs_hz > 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, at + "fs_hz must be finite and > 0");
+    if ((p.flags & RC_DO_DOPPLER) && !(std::isfinite(p.alpha) && p.alpha > 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, at + "alpha must be finite and > 0");
+    if (!(p.flags & RC_DO_DOPPLER) && p.n_out != p.n_in)
+        return fail(ctx, RC_ERR_INVALID_ARG, at + "n_out must equal n_in without RC_DO_DOPPLER");
+    if (p.flags & RC_DO_IONO) {
+        if (!(std::isfinite(p.tec) && p.tec >= 0.0) || !std::isfinite(p.carrier))
+            return fail(ctx, RC_ERR_INVALID_ARG, at + "tec must be finite and >= 0, carrier finite");
+        if (p.direction != RC_CORRECT && p.direction != RC_DISTORT)
+            return fail(ctx, RC_ERR_INVALID_ARG, at + "bad direction");
+        if (p.n_out > kMaxIonoLength || (!is_pow2(p.n_out) && 2 * p.n_out - 1 > kMaxIonoLength))
+            return fail(ctx, RC_ERR_UNSUPPORTED, at + "iono length above 2^24 (power of two) or 2^23 (other)");
+    }
+    return RC_OK;
+}
+
+rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, const rc_sinc *k, hipStream_t s);
+
 // correct_pulse_batch with the context lock held (also the per-hypothesis Doppler bank)
 rc_status pulse_batch_locked(rc_context ctx, const rc_c64 *x_packed, int64_t x_len, rc_c64 *y_packed,
                              int64_t y_len, const rc_pulse *pulses, int32_t count, const rc_sinc *k, void *stream)
@@ -445,41 +485,40 @@ rc_status pulse_batch_locked(rc_context ctx, const rc_c64 *x_packed, int64_t x_l
     if (overlaps(x_packed, x_len * 8, y_packed, y_len * 8))
         return fail(ctx, RC_ERR_INVALID_ARG, "input and output buffers overlap");
     // validate every pulse; output ranges must be pairwise disjoint
+    const float2 *xb = reinterpret_cast<const float2 *>(x_packed);
+    float2 *yb = reinterpret_cast<float2 *>(y_packed);
     std::vector<std::pair<int64_t, int64_t>> outs;
+    std::vector<PulseWork> work;
     outs.reserve((size_t)count);
+    work.reserve((size_t)count);
     for (int32_t i = 0; i < count; ++i) {
         const rc_pulse &p = pulses[i];
         const std::string at = "pulse " + std::to_string(i) + ": ";
         if (p.n_in <= 0 || p.n_out <= 0 || p.off_in < 0 || p.off_out < 0 || p.off_in > x_len - p.n_in ||
             p.off_out > y_len - p.n_out)
             return fail(ctx, RC_ERR_INVALID_ARG, at + "range outside its buffer");
-        if ((p.flags & ~(uint32_t)(RC_DO_DOPPLER | RC_DO_IONO)) != 0)
-            return fail(ctx, RC_ERR_INVALID_ARG, at + "unknown flag bits");
-        if (!(std::isfinite(p.fs_hz) && p.fs_hz > 0.0))
-            return fail(ctx, RC_ERR_INVALID_ARG, at + "fs_hz must be finite and > 0");
-        if ((p.flags & RC_DO_DOPPLER) && !(std::isfinite(p.alpha) && p.alpha > 0.0))
-            return fail(ctx, RC_ERR_INVALID_ARG, at + "alpha must be finite and > 0");
-        if (!(p.flags & RC_DO_DOPPLER) && p.n_out != p.n_in)
-            return fail(ctx, RC_ERR_INVALID_ARG, at + "n_out must equal n_in without RC_DO_DOPPLER");
-        if (p.flags & RC_DO_IONO) {
-            if (!(std::isfinite(p.tec_el_per_m2) && p.tec_el_per_m2 >= 0.0) || !std::isfinite(p.carrier_hz))
-                return fail(ctx, RC_ERR_INVALID_ARG, at + "tec must be finite and >= 0, carrier finite");
-            if (p.direction != RC_CORRECT && p.direction != RC_DISTORT)
-                return fail(ctx, RC_ERR_INVALID_ARG, at + "bad direction");
-            if (p.n_out > kMaxIonoLength || (!is_pow2(p.n_out) && 2 * p.n_out - 1 > kMaxIonoLength))
-                return fail(ctx, RC_ERR_UNSUPPORTED, at + "iono length above 2^24 (power of two) or 2^23 (other)");
-        }
+        const PulseWork w{xb + p.off_in, yb + p.off_out, p.n_in, p.n_out, p.fs_hz, p.alpha, p.tec_el_per_m2,
+                          p.carrier_hz, p.flags, p.direction};
+        st = validate_pulse(ctx, w, at);
+        if (st != RC_OK)
+            return st;
+        work.push_back(w);
         outs.emplace_back(p.off_out, p.off_out + p.n_out);
     }
     std::sort(outs.begin(), outs.end());
     for (size_t i = 1; i < outs.size(); ++i)
         if (outs[i].first < outs[i - 1].second)
             return fail(ctx, RC_ERR_INVALID_ARG, "output ranges overlap");
+    return run_pulses_locked(ctx, work, k, static_cast<hipStream_t>(stream));
+}
 
+// Launch a validated list of pulses on `s`: Doppler jobs grouped by engine, ionospheric jobs
+// grouped by transform length, plain copies for pulses with neither step.
+rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, const rc_sinc *k, hipStream_t s)
+{
+    rc_status st = RC_OK;
+    const int32_t count = (int32_t)work.size();
     DeviceGuard g(ctx->device);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const float2 *xb = reinterpret_cast<const float2 *>(x_packed);
-    float2 *yb = reinterpret_cast<float2 *>(y_packed);
 
     // Group the work: fast-path Doppler jobs, generic Doppler jobs, plain copies, and the
     // ionospheric jobs by transform length (one launch sequence per length).
@@ -488,9 +527,9 @@ rc_status pulse_batch_locked(rc_context ctx, const rc_c64 *x_packed, int64_t x_l
     std::map<int64_t, std::vector<IonoJob>> iono;
     std::vector<int32_t> copies;
     for (int32_t i = 0; i < count; ++i) {
-        const rc_pulse &p = pulses[i];
+        const PulseWork &p = work[(size_t)i];
         if (p.flags & RC_DO_DOPPLER) {
-            const SincJob j{xb + p.off_in, yb + p.off_out, p.n_in, p.n_out, p.alpha, 0};
+            const SincJob j{p.x, p.y, p.n_in, p.n_out, p.alpha, 0};
             const SincPath path = sinc_path(ctx, p.alpha, *k);
             if (path == SincPath::Mfma) {
                 mfma.push_back(j);
@@ -507,9 +546,8 @@ rc_status pulse_batch_locked(rc_context ctx, const rc_c64 *x_packed, int64_t x_l
             copies.push_back(i);
         }
         if (p.flags & RC_DO_IONO) {
-            const float2 *src = (p.flags & RC_DO_DOPPLER) ? yb + p.off_out : xb + p.off_in;
-            iono[p.n_out].push_back(IonoJob{src, yb + p.off_out, phase_numerator(p.tec_el_per_m2, p.direction),
-                                            p.carrier_hz, p.fs_hz});
+            const float2 *src = (p.flags & RC_DO_DOPPLER) ? p.y : p.x;
+            iono[p.n_out].push_back(IonoJob{src, p.y, phase_numerator(p.tec, p.direction), p.carrier, p.fs_hz, nullptr});
         }
     }
     if (mfma.size() > 65535 || fast.size() > 65535 || direct.size() > 65535)
@@ -565,7 +603,7 @@ rc_status pulse_batch_locked(rc_context ctx, const rc_c64 *x_packed, int64_t x_l
     }
     char *devc = static_cast<char *>(const_cast<void *>(dev));
     char *wbase = extra ? devc + al(blob.size()) : nullptr;
-    void *work = mfma_work ? wbase : nullptr;
+    void *tile_work = mfma_work ? wbase : nullptr;
     void *bwork = bs_work ? wbase + al(mfma_work) : nullptr;
     // from here on the slot is in use: mark it whatever happens
     struct SlotMark {
@@ -580,15 +618,15 @@ rc_status pulse_batch_locked(rc_context ctx, const rc_c64 *x_packed, int64_t x_l
     } slot_mark{ctx, s, dev != nullptr};
     hipError_t e = hipSuccess;
     for (int32_t i : copies) {
-        const rc_pulse &p = pulses[i];
-        e = hipMemcpyAsync(yb + p.off_out, xb + p.off_in, (size_t)p.n_in * 8, hipMemcpyDeviceToDevice, s);
+        const PulseWork &p = work[(size_t)i];
+        e = hipMemcpyAsync(p.y, p.x, (size_t)p.n_in * 8, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess)
             return device_fail(ctx, e, "copy");
     }
     const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
     if (!mfma.empty())
         e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc + off_mfma), nullptr, (int)mfma.size(),
-                                 mfma_max, mfma_tiles, work, k->half_width, mfma_table, s, prof_of(ctx));
+                                 mfma_max, mfma_tiles, tile_work, k->half_width, mfma_table, s, prof_of(ctx));
     if (e == hipSuccess && !fast.empty())
         e = rc::launch_sinc_fast(reinterpret_cast<const SincJob *>(devc + off_fast), nullptr, (int)fast.size(),
                                  fast_max, k->half_width, kp, s, prof_of(ctx));
@@ -727,6 +765,359 @@ rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c6
     if (e != hipSuccess)
         return device_fail(ctx, e, "Doppler bank launch");
     return st;
+}
+
+// ---------------------------------------------------------------------------------------
+// Serving: continuous batching of independent requests on the server's own stream.
+
+struct rc_server_s {
+    using clock = std::chrono::steady_clock;
+    struct Req {
+        int64_t ticket;
+        PulseWork work;
+        int64_t bytes;
+        clock::time_point submitted;
+    };
+    struct Flight {
+        hipEvent_t done;
+        std::vector<Req> reqs;
+        rc_status status;
+    };
+    struct Ticket {
+        bool done = false;
+        rc_status status = RC_OK;
+    };
+    rc_context ctx = nullptr;
+    rc_sinc k{};
+    int64_t budget = 0;
+    int32_t max_batch = 0;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    std::condition_variable cv_queue, cv_flight, cv_done;
+    std::deque<Req> queue;                       // admitted, not launched
+    std::deque<Flight> flights;                  // launched, not complete (stream order)
+    std::unordered_map<int64_t, Ticket> tickets; // admitted, not yet waited for
+    std::vector<hipEvent_t> event_pool;
+    int64_t in_flight_bytes = 0;                 // admitted and not complete
+    int64_t next_ticket = 1;
+    bool stop = false, launcher_done = false;
+    std::thread launcher, completer;
+    // statistics
+    int64_t submitted = 0, completed = 0, rejected = 0, batches = 0, batched_reqs = 0, samples = 0;
+    std::vector<double> latency_ms;
+    bool have_first = false;
+    clock::time_point first_submit, last_done;
+};
+
+namespace {
+
+void server_launcher(rc_server srv)
+{
+    for (;;) {
+        std::vector<rc_server_s::Req> take;
+        hipEvent_t ev = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            srv->cv_queue.wait(lk, [&] { return srv->stop || !srv->queue.empty(); });
+            if (srv->queue.empty()) {  // stop requested and nothing left
+                srv->launcher_done = true;
+                srv->cv_flight.notify_all();
+                return;
+            }
+            while (!srv->queue.empty() && (int32_t)take.size() < srv->max_batch) {
+                take.push_back(srv->queue.front());
+                srv->queue.pop_front();
+            }
+            if (!srv->event_pool.empty()) {
+                ev = srv->event_pool.back();
+                srv->event_pool.pop_back();
+            }
+        }
+        std::vector<PulseWork> work;
+        work.reserve(take.size());
+        for (const auto &r : take)
+            work.push_back(r.work);
+        rc_status st;
+        {
+            std::lock_guard<std::mutex> lk(srv->ctx->mu);
+            srv->ctx->last_error.clear();
+            DeviceGuard g(srv->ctx->device);
+            st = run_pulses_locked(srv->ctx, work, &srv->k, srv->stream);
+            if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+                ev = nullptr;
+            if (ev && hipEventRecord(ev, srv->stream) != hipSuccess)
+                st = RC_ERR_DEVICE;
+            if (!ev)
+                st = RC_ERR_DEVICE;
+        }
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->flights.push_back({ev, std::move(take), st});
+            srv->batches += 1;
+            srv->batched_reqs += (int64_t)srv->flights.back().reqs.size();
+        }
+        srv->cv_flight.notify_all();
+    }
+}
+
+void server_completer(rc_server srv)
+{
+    for (;;) {
+        rc_server_s::Flight f;
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            srv->cv_flight.wait(lk, [&] { return !srv->flights.empty() || srv->launcher_done; });
+            if (srv->flights.empty())
+                return;  // the launcher has stopped and every batch is complete
+            f = srv->flights.front();
+        }
+        rc_status st = f.status;
+        if (f.done) {
+            DeviceGuard g(srv->ctx->device);
+            if (hipEventSynchronize(f.done) != hipSuccess && st == RC_OK)
+                st = RC_ERR_DEVICE;
+        }
+        const auto now = rc_server_s::clock::now();
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->flights.pop_front();
+            for (const auto &r : f.reqs) {
+                auto it = srv->tickets.find(r.ticket);
+                if (it != srv->tickets.end()) {
+                    it->second.done = true;
+                    it->second.status = st;
+                }
+                srv->in_flight_bytes -= r.bytes;
+                srv->completed += 1;
+                srv->samples += r.work.n_out;
+                srv->latency_ms.push_back(std::chrono::duration<double, std::milli>(now - r.submitted).count());
+            }
+            srv->last_done = now;
+            if (f.done)
+                srv->event_pool.push_back(f.done);
+        }
+        srv->cv_done.notify_all();
+    }
+}
+
+double percentile(std::vector<double> v, double q)
+{
+    if (v.empty())
+        return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * (double)(v.size() - 1);
+    const size_t i = (size_t)pos;
+    const double f = pos - (double)i;
+    return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
+}
+
+}  // namespace
+
+rc_status rc_server_create(rc_context ctx, const rc_sinc *k, int64_t mem_budget_bytes, int32_t max_batch,
+                           rc_server *out)
+{
+    if (!ctx || !out)
+        return RC_ERR_INVALID_ARG;
+    *out = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->last_error.clear();
+        rc_status st = check_sinc(ctx, k);
+        if (st != RC_OK)
+            return st;
+        if (mem_budget_bytes <= 0 || max_batch <= 0)
+            return fail(ctx, RC_ERR_INVALID_ARG, "mem_budget_bytes and max_batch must be > 0");
+    }
+    rc_server srv = new (std::nothrow) rc_server_s();
+    if (!srv)
+        return RC_ERR_OUT_OF_MEMORY;
+    srv->ctx = ctx;
+    srv->k = *k;
+    srv->budget = mem_budget_bytes;
+    srv->max_batch = max_batch;
+    {
+        DeviceGuard g(ctx->device);
+        if (hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete srv;
+            return RC_ERR_DEVICE;
+        }
+    }
+    try {
+        srv->launcher = std::thread(server_launcher, srv);
+        srv->completer = std::thread(server_completer, srv);
+    } catch (...) {
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->stop = true;
+        }
+        srv->cv_queue.notify_all();
+        if (srv->launcher.joinable())
+            srv->launcher.join();
+        if (srv->completer.joinable())
+            srv->completer.join();
+        (void)hipStreamDestroy(srv->stream);
+        delete srv;
+        return RC_ERR_OUT_OF_MEMORY;
+    }
+    *out = srv;
+    return RC_OK;
+}
+
+rc_status rc_server_submit(rc_server srv, const rc_request *req, int64_t *ticket)
+{
+    if (!srv || !req || !ticket)
+        return RC_ERR_INVALID_ARG;
+    *ticket = 0;
+    const PulseWork w{reinterpret_cast<const float2 *>(req->x), reinterpret_cast<float2 *>(req->y), req->n_in,
+                      req->n_out, req->fs_hz, req->alpha, req->tec_el_per_m2, req->carrier_hz, req->flags,
+                      req->direction};
+    {
+        std::lock_guard<std::mutex> lk(srv->ctx->mu);
+        srv->ctx->last_error.clear();
+        if (!req->x || !req->y)
+            return fail(srv->ctx, RC_ERR_INVALID_ARG, "NULL sample pointer");
+        rc_status st = validate_pulse(srv->ctx, w, "request: ");
+        if (st != RC_OK)
+            return st;
+        if ((w.flags & RC_DO_DOPPLER) && overlaps(req->x, w.n_in * 8, req->y, w.n_out * 8))
+            return fail(srv->ctx, RC_ERR_INVALID_ARG, "request: x and y overlap");
+        if (!(w.flags & RC_DO_DOPPLER) && req->x != req->y && overlaps(req->x, w.n_in * 8, req->y, w.n_out * 8))
+            return fail(srv->ctx, RC_ERR_INVALID_ARG, "request: x and y partially overlap");
+    }
+    // bytes a request holds while admitted: its input and output, and a transform workspace
+    // of up to 16 B per sample for lengths that are not powers of two
+    const int64_t bytes = 8 * (w.n_in + w.n_out) + ((w.flags & RC_DO_IONO) && !is_pow2(w.n_out) ? 32 * w.n_out : 0);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop)
+        return RC_ERR_INVALID_ARG;
+    if (bytes > srv->budget) {
+        srv->rejected += 1;
+        return RC_ERR_UNSUPPORTED;  // can never be admitted under this budget
+    }
+    if (srv->in_flight_bytes + bytes > srv->budget) {
+        srv->rejected += 1;
+        return RC_ERR_BUSY;
+    }
+    const auto now = rc_server_s::clock::now();
+    if (!srv->have_first) {
+        srv->have_first = true;
+        srv->first_submit = now;
+    }
+    const int64_t t = srv->next_ticket++;
+    srv->in_flight_bytes += bytes;
+    srv->submitted += 1;
+    srv->tickets.emplace(t, rc_server_s::Ticket{});
+    srv->queue.push_back({t, w, bytes, now});
+    srv->cv_queue.notify_one();
+    *ticket = t;
+    return RC_OK;
+}
+
+rc_status rc_server_poll(rc_server srv, int64_t ticket, int32_t *done)
+{
+    if (!srv || !done)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->tickets.find(ticket);
+    if (it == srv->tickets.end())
+        return RC_ERR_INVALID_ARG;
+    *done = it->second.done ? 1 : 0;
+    if (it->second.done) {
+        const rc_status st = it->second.status;
+        srv->tickets.erase(it);
+        return st;
+    }
+    return RC_OK;
+}
+
+rc_status rc_server_wait(rc_server srv, int64_t ticket)
+{
+    if (!srv)
+        return RC_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (ticket == 0) {  // everything submitted so far
+        const int64_t target = srv->submitted;
+        srv->cv_done.wait(lk, [&] { return srv->completed >= target; });
+        rc_status st = RC_OK;
+        for (auto it = srv->tickets.begin(); it != srv->tickets.end();) {
+            if (it->second.done) {
+                if (it->second.status != RC_OK)
+                    st = it->second.status;
+                it = srv->tickets.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        return st;
+    }
+    if (srv->tickets.find(ticket) == srv->tickets.end())
+        return RC_ERR_INVALID_ARG;
+    // another thread's wait-for-all may consume the ticket once it is done
+    srv->cv_done.wait(lk, [&] {
+        auto f = srv->tickets.find(ticket);
+        return f == srv->tickets.end() || f->second.done;
+    });
+    auto f = srv->tickets.find(ticket);
+    if (f == srv->tickets.end())
+        return RC_OK;
+    const rc_status st = f->second.status;
+    srv->tickets.erase(f);
+    return st;
+}
+
+rc_status rc_server_stats(rc_server srv, rc_server_stats_t *out)
+{
+    if (!srv || !out)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    rc_server_stats_t s{};
+    s.submitted = srv->submitted;
+    s.completed = srv->completed;
+    s.rejected = srv->rejected;
+    s.batches = srv->batches;
+    s.mean_batch = srv->batches ? (double)srv->batched_reqs / (double)srv->batches : 0.0;
+    s.latency_ms_p50 = percentile(srv->latency_ms, 0.50);
+    s.latency_ms_p99 = percentile(srv->latency_ms, 0.99);
+    s.latency_ms_max = srv->latency_ms.empty() ? 0.0 : *std::max_element(srv->latency_ms.begin(), srv->latency_ms.end());
+    const double span = srv->have_first && srv->completed
+                            ? std::chrono::duration<double>(srv->last_done - srv->first_submit).count()
+                            : 0.0;
+    s.samples_per_s = span > 0.0 ? (double)srv->samples / span : 0.0;
+    *out = s;
+    return RC_OK;
+}
+
+rc_status rc_server_reset_stats(rc_server srv)
+{
+    if (!srv)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->submitted -= srv->completed;
+    srv->completed = srv->rejected = srv->batches = srv->batched_reqs = srv->samples = 0;
+    srv->latency_ms.clear();
+    srv->have_first = false;
+    return RC_OK;
+}
+
+rc_status rc_server_destroy(rc_server srv)
+{
+    if (!srv)
+        return RC_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_queue.notify_all();
+    srv->launcher.join();  // launches what is queued, then stops
+    srv->completer.join(); // waits for every launched batch
+    {
+        DeviceGuard g(srv->ctx->device);
+        for (hipEvent_t e : srv->event_pool)
+            (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(srv->stream);
+    }
+    delete srv;
+    return RC_OK;
 }
 
 rc_status rc_set_sinc_engine(rc_context ctx, int32_t engine)

@@ -1,0 +1,126 @@
+"""GPU tests of the continuous-batching server (rc_server_*, through the C ABI): every request's
+output equals, bit for bit, the same pulse run alone through correct_doppler and
+correct_ionosphere, whatever it was batched with; admission by bytes; statistics."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import waveforms as wf
+
+pytestmark = pytest.mark.gpu
+
+C = 299792458
+
+
+def alpha_exact(v):
+    return float(Fraction(C + Fraction(v)) / Fraction(C - Fraction(v)))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2508_04951_amd as rc
+
+    return rc.Context(0)
+
+
+def dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).to("cuda")
+
+
+def alone(torch, ctx, x, r, k):
+    """The single-pulse entry points on one request."""
+    import paper_2508_04951_amd as rc
+
+    y = x
+    if r["flags"] & rc.DO_DOPPLER:
+        y = ctx.correct_doppler(x, r["alpha"], k, n_out=r["n_out"])
+    if r["flags"] & rc.DO_IONO:
+        y = ctx.correct_ionosphere(y, 10e6, 450e6, r["tec"], r["direction"])
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def test_server_mixed_stream_equals_single_calls(torch, ctx, orc):
+    import paper_2508_04951_amd as rc
+
+    rng = wf.rng_for(301, 0)
+    lens = [int(n) for n in wf.loguniform_lengths(30, rng, 8.0, 18.0)] + [4096, 65536, 1 << 17, 5000, 1]
+    k = rc.Sinc(64, "kaiser", 8.0)
+    srv = rc.Server(ctx, k, mem_budget_bytes=1 << 32, max_batch=7)
+    reqs, tickets = [], []
+    for i, n in enumerate(lens):
+        flags = [rc.DO_DOPPLER | rc.DO_IONO, rc.DO_DOPPLER, rc.DO_IONO][i % 3]
+        v = rng.uniform(-8000, 8000) if i % 5 else rng.uniform(9000, 20000)  # some off the matrix cores
+        r = dict(n=n, n_out=n + (i % 4) * 7 if flags == rc.DO_DOPPLER else n, alpha=alpha_exact(v),
+                 tec=rng.uniform(5, 100) * wf.TECU, flags=flags, direction="distort" if i % 7 == 3 else "correct")
+        x = dev(torch, wf.bandlimited_noise(n, wf.rng_for(301, i + 1)) if n > 1 else np.array([1 - 1j], np.complex64))
+        y = torch.full((r["n_out"],), complex("nan"), dtype=torch.complex64, device="cuda")
+        tickets.append(srv.submit(x, y, alpha=r["alpha"], tec=r["tec"], carrier=450e6, fs=10e6, flags=flags,
+                                  direction=r["direction"]))
+        reqs.append((r, x, y))
+    srv.wait(tickets[3])
+    srv.wait()
+    for i, (r, x, y) in enumerate(reqs):
+        got = y.cpu().numpy()
+        assert not np.isnan(got).any(), i
+        assert np.array_equal(got, alone(torch, ctx, x, r, k)), i
+    st = srv.stats()
+    assert st["submitted"] == st["completed"] == len(lens)
+    assert st["batches"] >= 1 and 1.0 <= st["mean_batch"] <= 7.0
+    assert 0.0 < st["latency_ms_p50"] <= st["latency_ms_p99"] <= st["latency_ms_max"]
+    assert st["samples_per_s"] > 0
+    # spot-check two requests against the oracle
+    for i in (0, 4):
+        r, x, y = reqs[i]
+        xh = x.cpu().numpy()
+        ref = orc.correct_pulse(xh, 10e6, r["alpha"], r["tec"], 450e6, n_out=r["n_out"], half_width=64,
+                                doppler_on=bool(r["flags"] & rc.DO_DOPPLER), iono_on=bool(r["flags"] & rc.DO_IONO),
+                                direction=r["direction"])
+        got = y.cpu().numpy()
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5, i
+    srv.close()
+
+
+def test_server_admission_poll_and_errors(torch, ctx):
+    import paper_2508_04951_amd as rc
+
+    n = 1 << 16
+    x = dev(torch, wf.bandlimited_noise(n, wf.rng_for(302, 0)))
+    ys = [torch.empty(n, dtype=torch.complex64, device="cuda") for _ in range(4)]
+    # a budget of three requests (16 B per sample each)
+    srv = rc.Server(ctx, rc.Sinc(64), mem_budget_bytes=3 * 16 * n, max_batch=16)
+    t = [srv.submit(x, ys[i], alpha=alpha_exact(1000.0 * i), tec=20 * wf.TECU, carrier=450e6, fs=10e6)
+         for i in range(3)]
+    with pytest.raises(rc.RcError) as ei:  # the fourth does not fit while three are in flight
+        srv.submit(x, ys[3], alpha=1.0)
+    assert ei.value.status == 5  # RC_ERR_BUSY
+    srv.wait(t[0])
+    srv.wait(t[1])
+    t3 = srv.submit(x, ys[3], alpha=alpha_exact(3000.0), tec=20 * wf.TECU, carrier=450e6, fs=10e6)
+    while not srv.poll(t3):
+        pass
+    with pytest.raises(ValueError):
+        srv.poll(t3)  # released
+    with pytest.raises(rc.RcError) as ei:  # could never fit
+        big = torch.empty(4 * n, dtype=torch.complex64, device="cuda")
+        srv.submit(big, big, flags=rc.DO_IONO, tec=1e17, carrier=450e6, fs=10e6)
+    assert ei.value.status == 2
+    with pytest.raises(ValueError):
+        srv.submit(x, ys[0], alpha=float("nan"))
+    with pytest.raises(ValueError):
+        srv.submit(x, x, alpha=1.1)  # Doppler in place
+    st = srv.stats()
+    assert st["rejected"] == 2 and st["completed"] == 4
+    srv.wait()
+    srv.reset_stats()
+    assert srv.stats()["completed"] == 0
+    srv.close()
