@@ -38,6 +38,12 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// two float32 values to a pair of float16, rounded toward zero (v_cvt_pkrtz_f16_f32)
+__device__ __forceinline__ half2v pkrtz(float a, float b)
+{
+    return __builtin_bit_cast(half2v, __builtin_amdgcn_cvt_pkrtz(a, b));
+}
+
 constexpr int kMfOut = kSincMfmaTile;  // outputs per tile (one phase-grid point)
 constexpr int kMfOrders = 5;           // quartic in the drift
 constexpr int kMfLo = 2;               // orders that also take the hi*lo and lo*hi products
@@ -242,20 +248,6 @@ k_mf_tile_scatter(const uint2 *__restrict__ ref, const unsigned char *__restrict
         list[atomicAdd(&base[phase[i]], 1u)] = ref[i];
 }
 
-// Lane l takes lane l + 2 of the same 16-lane row (DPP row_shl:2); lanes 14 and 15 of a row
-// keep `fill`.
-__device__ __forceinline__ half8 rows_up2(half8 fill, half8 v)
-{
-    typedef int int4v __attribute__((ext_vector_type(4)));
-    const int4v f = __builtin_bit_cast(int4v, fill), w = __builtin_bit_cast(int4v, v);
-    int4v r;
-    r.x = __builtin_amdgcn_update_dpp(f.x, w.x, 0x102, 0xf, 0xf, false);
-    r.y = __builtin_amdgcn_update_dpp(f.y, w.y, 0x102, 0xf, 0xf, false);
-    r.z = __builtin_amdgcn_update_dpp(f.z, w.z, 0x102, 0xf, 0xf, false);
-    r.w = __builtin_amdgcn_update_dpp(f.w, w.w, 0x102, 0xf, 0xf, false);
-    return __builtin_bit_cast(half8, r);
-}
-
 // The resampling GEMM.  Without a list, workgroup (x, y) computes tile x of job y.  With a list,
 // the grid is persistent: workgroup b takes the run c(b) of the sorted list, where c deals
 // consecutive b to different XCDs so that an XCD holds a contiguous range of phases.
@@ -309,6 +301,20 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
     float2 xv[G::spp][2];
     auto fetch = [&](const MfCur &t) {
         const int64_t lo = t.M0 + (int64_t)t.tp.Sd - H;
+        if (lo >= 0 && lo + G::span <= t.jb.n_in) {
+            // the whole span lies inside x (the usual case; uniform): 32-bit offsets from its start
+            const auto xs = gmem(t.jb.x) + lo;
+#pragma unroll
+            for (int q = 0; q < G::spp; ++q) {
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    const int e = 2 * tid + 512 * q + h2;
+                    const float2 v = xs[e < G::span ? e : G::span - 1];
+                    xv[q][h2] = e < G::span ? v : make_float2(0.f, 0.f);
+                }
+            }
+            return;
+        }
         const int64_t last = t.jb.n_in - 1;
         const auto xs = gmem(t.jb.x);
         // every lane loads an in-bounds sample (index clamped) and zeroes what lies outside x
@@ -391,12 +397,14 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
         for (int q = 0; q < G::spp; ++q) {
             const int e = 2 * tid + 512 * q;
             if (e < G::span) {  // span is even: a pair is either wholly inside or outside
+                // hi rounds toward zero (one packed conversion per pair); the residual x - hi is
+                // exact in float32 and becomes lo
                 const float r0 = xv[q][0].x * xs2, r1 = xv[q][1].x * xs2;
                 const float i0f = xv[q][0].y * xs2, i1f = xv[q][1].y * xs2;
-                const half2v rh = {(_Float16)r0, (_Float16)r1};
-                const half2v ih = {(_Float16)i0f, (_Float16)i1f};
-                const half2v rl = {(_Float16)(r0 - (float)rh[0]), (_Float16)(r1 - (float)rh[1])};
-                const half2v il = {(_Float16)(i0f - (float)ih[0]), (_Float16)(i1f - (float)ih[1])};
+                const half2v rh = pkrtz(r0, r1);
+                const half2v ih = pkrtz(i0f, i1f);
+                const half2v rl = pkrtz(r0 - (float)rh[0], r1 - (float)rh[1]);
+                const half2v il = pkrtz(i0f - (float)ih[0], i1f - (float)ih[1]);
                 *reinterpret_cast<half2v *>(a_rh + e) = rh;
                 *reinterpret_cast<half2v *>(a_rl + e) = rl;
                 *reinterpret_cast<half2v *>(a_ih + e) = ih;
@@ -424,33 +432,25 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
     for (int64_t i = i0; i < i1; ++i) {
         const bool active = cur.M0 + 256 * wave < cur.jb.n_out;  // uniform over the wave
         floatx4 acc[2][kMfOrders][2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int r = 0; r < kMfOrders; ++r)
-                acc[t][r][0] = acc[t][r][1] = floatx4{0.f, 0.f, 0.f, 0.f};
 
         // 1) the GEMM.  Wave w owns sub-tiles w and w + 4 and runs them together: each B
         //    fragment is read from LDS once per 32-tap step for both.
         if (active) {
             // A fragments: lane (i, q) = (l % 16, l / 16) holds the 8 samples at
-            // 16 i + 8 q + 32 s of its sub-tile's span.  The Hankel structure gives the next step
-            // for free: row i at step s + 1 is row i + 2 at step s, a 2-lane shift inside each
-            // 16-lane DPP row; only rows 14 and 15 read new samples from LDS.
+            // 16 i + 8 q + 32 s of its sub-tile's span (aligned 8-sample runs of the Hankel matrix)
             const int arow = 256 * wave + 16 * (lane & 15) + 8 * (lane >> 4);
-            const bool edge = (lane & 15) >= 14;
-            half8 xh[2][2], xl[2][2];  // [sub-tile][re/im]
+            // step s of the contraction; the first step starts every accumulator from zero (the
+            // matrix core's inline constant), so nothing is cleared beforehand
+            auto kstep = [&](int s, bool first) {
+                half8 xh[2][2], xl[2][2];  // [sub-tile][re/im]
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int e = arow + 1024 * t;
-                xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
-                xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
-                xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
-                xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
-            }
-            // not unrolled: hoisting the next step's fragments would cost the second wave per SIMD
-#pragma unroll 1
-            for (int s = 0; s < G::ksteps; ++s) {
+                for (int t = 0; t < 2; ++t) {
+                    const int e = arow + 1024 * t + 32 * s;
+                    xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
+                    xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
+                    xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
+                    xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
+                }
                 const half8 *blk = reinterpret_cast<const half8 *>(bsm + s * kMfBlk * 1024);
                 half8 bh[kMfOrders], bl[kMfLo];
 #pragma unroll
@@ -467,7 +467,8 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
                     for (int t = 0; t < 2; ++t)
 #pragma unroll
                         for (int c = 0; c < 2; ++c)
-                            acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh[t][c], bh[r], acc[t][r][c], 0, 0, 0);
+                            acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                xh[t][c], bh[r], first ? floatx4{0.f, 0.f, 0.f, 0.f} : acc[t][r][c], 0, 0, 0);
 #pragma unroll
                 for (int r = 0; r < kMfLo; ++r)
 #pragma unroll
@@ -482,26 +483,12 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
 #pragma unroll
                         for (int c = 0; c < 2; ++c)
                             acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl[t][c], bh[r], acc[t][r][c], 0, 0, 0);
-                if (s + 1 < G::ksteps) {
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-#pragma unroll
-                        for (int c = 0; c < 2; ++c) {
-                            xh[t][c] = rows_up2(xh[t][c], xh[t][c]);
-                            xl[t][c] = rows_up2(xl[t][c], xl[t][c]);
-                        }
-                    if (edge) {
-#pragma unroll
-                        for (int t = 0; t < 2; ++t) {
-                            const int e = arow + 1024 * t + 32 * (s + 1);
-                            xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
-                            xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
-                            xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
-                            xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
-                        }
-                    }
-                }
-            }
+            };
+            kstep(0, true);
+            // not unrolled: hoisting the next step's fragments would cost the second wave per SIMD
+#pragma unroll 1
+            for (int s = 1; s < G::ksteps; ++s)
+                kstep(s, false);
         }
 
         // 2) the next tile into LDS (after every wave's products: the barrier in stage), and the
@@ -531,19 +518,23 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
             const float zstep = (float)(eps * (1.0 / kDeltaMax));
             const float sc32 = (float)c.tp.sc;
             const float e32 = (float)eps;
-            const auto yg = gmem(c.jb.y);
+            const auto yt = gmem(c.jb.y) + c.M0;  // this tile's first output
+            const bool full = c.M0 + kMfOut <= c.jb.n_out;  // uniform
+            const int nvalid = full ? kMfOut : (int)(c.jb.n_out - c.M0);
+            // sigma runs over sc +- |eps| 1023.5 in this tile: only if that range comes within 1e-5
+            // of 0 can an output sit on an exact sample instant (uniform)
+            const bool may_hit = fabs(c.tp.sc) <= fabs(eps) * kMfHalf + 2e-5;
             unsigned near = 0;  // bit 4 t + j: output (t, j) is next to an exact instant
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int off = 256 * (wave + 4 * t) + 16 * (4 * (lane >> 4) + j) + (lane & 15);  // m - M0
-                    const int64_t m = c.M0 + off;
-                    if (m >= c.jb.n_out)
+                    if (!full && off >= nvalid)
                         continue;
                     const float dm = (float)off - (float)kMfHalf;
                     const float z = fmaf(dm, zstep, zc);
-                    if (fabsf(fmaf(dm, e32, sc32)) < 1e-5f)
+                    if (may_hit && fabsf(fmaf(dm, e32, sc32)) < 1e-5f)
                         near |= 1u << (4 * t + j);
                     float yr = acc[t][kMfOrders - 1][0][j], yi = acc[t][kMfOrders - 1][1][j];
 #pragma unroll
@@ -551,7 +542,7 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
                         yr = fmaf(yr, z, acc[t][r][0][j]);
                         yi = fmaf(yi, z, acc[t][r][1][j]);
                     }
-                    yg[m] = make_float2(yr * unscale, yi * unscale);
+                    yt[off] = make_float2(yr * unscale, yi * unscale);
                 }
             }
             if (__any(near != 0)) {  // rare: uniform over the wave
@@ -561,14 +552,15 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
                     if (!((near >> b) & 1u))
                         continue;
                     const int t = b >> 2, j = b & 3;
-                    const int64_t m = c.M0 + 256 * (wave + 4 * t) + 16 * (4 * (lane >> 4) + j) + (lane & 15);
+                    const int off = 256 * (wave + 4 * t) + 16 * (4 * (lane >> 4) + j) + (lane & 15);
+                    const int64_t m = c.M0 + off;
                     const double md = (double)m;
                     if (((__dmul_rn(alpha, md) - md) - c.tp.Sd) == 0.0) {
                         const int64_t src = m + S;
                         float2 v = make_float2(0.f, 0.f);
                         if (src >= 0 && src < c.jb.n_in)
                             v = xg[src];
-                        yg[m] = v;
+                        yt[off] = v;
                     }
                 }
             }
