@@ -153,20 +153,24 @@ def cpu_baseline(x, desc, y_gpu, seconds: float):
 
 
 def timed(torch, ctx, step, steps: int, warmup: int):
-    """ms per step over `steps` after `warmup`, and the library's per-kernel averages."""
+    """ms per step over `steps` timed steps after `warmup` (barrier-free: the library's per-kernel
+    events are off), then the per-kernel averages from a second run of `steps` steps with the
+    events recorded on the launch stream around every kernel."""
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    ctx.profile_read()
-    ctx.profile(True)
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0.record()
     for _ in range(steps):
         step()
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
+    ctx.profile_read()
+    ctx.profile(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
     ctx.profile(False)
     kt = ctx.profile_read()
     kernels = {k: {"avg_ms": round(v / cnt, 4), "launches_per_step": cnt / steps,
@@ -437,26 +441,7 @@ def main():
         log(f"[bench] copy calibration: 3 x {xd.numel() * 8 / 2**20:.0f} MiB read + written")
 
     log(f"[bench] warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.profile_read()  # clear
-    ctx.profile(True)
-    log(f"[bench] timing {args.steps} steps")
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    ms_per_step = t0.elapsed_time(t1) / args.steps
-    ctx.profile(False)
-    kt = ctx.profile_read()
-    kernels = {k: {"avg_ms": round(ms / cnt, 4), "launches_per_step": cnt / args.steps,
-                   "share": round(ms / (ms_per_step * args.steps), 4)}
-               for k, (ms, cnt) in kt.items() if cnt}
+    ms_per_step, kt, kernels = timed(torch, ctx, step, args.steps, args.warmup)
     value = samples / (ms_per_step * 1e-3)
     log(f"[bench] {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GS/s; kernels {kernels}")
 

@@ -129,7 +129,11 @@ rc_status stage_descriptors(rc_context ctx, const void *host, size_t bytes, size
     }
     if (bytes) {
         std::memcpy(slot.host, host, bytes);
-        e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, ctx->copy_stream);
+        if (e == hipSuccess)
+            e = hipEventRecord(slot.uploaded, ctx->copy_stream);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(s, slot.uploaded, 0);
         if (e != hipSuccess)
             return device_fail(ctx, e, "descriptor upload");
     }
@@ -257,13 +261,23 @@ rc_status rc_create(int hip_device, rc_context *out)
     ctx->device = hip_device;
     DeviceGuard g(hip_device);
     hipError_t e = rc::make_base_twiddles(&ctx->tw4096);
-    for (auto &slot : ctx->desc)
+    for (auto &slot : ctx->desc) {
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&slot.uploaded, hipEventDisableTiming);
+    }
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        for (auto &slot : ctx->desc)
+        if (ctx->copy_stream)
+            (void)hipStreamDestroy(ctx->copy_stream);
+        for (auto &slot : ctx->desc) {
             if (slot.done)
                 (void)hipEventDestroy(slot.done);
+            if (slot.uploaded)
+                (void)hipEventDestroy(slot.uploaded);
+        }
         if (ctx->tw4096)
             (void)hipFree(ctx->tw4096);
         delete ctx;
@@ -294,7 +308,11 @@ rc_status rc_destroy(rc_context ctx)
                 (void)hipHostFree(slot.host);
             if (slot.done)
                 (void)hipEventDestroy(slot.done);
+            if (slot.uploaded)
+                (void)hipEventDestroy(slot.uploaded);
         }
+        if (ctx->copy_stream)
+            (void)hipStreamDestroy(ctx->copy_stream);
         ctx->prof.release();
     }
     delete ctx;

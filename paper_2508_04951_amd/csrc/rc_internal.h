@@ -243,8 +243,12 @@ struct rc_context_s {
         size_t host_cap = 0;
         size_t dev_cap = 0;
         hipEvent_t done = nullptr;
+        hipEvent_t uploaded = nullptr;  // the upload of this slot's descriptors (copy stream)
         bool pending = false;
     };
+    // descriptors go up on their own stream, so a batch's upload overlaps the previous batch's
+    // kernels; the compute stream waits for it by event
+    hipStream_t copy_stream = nullptr;
     static constexpr int kDescSlots = 4;
     DescSlot desc[kDescSlots];
     int desc_next = 0;
