@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided_reg(StridedArgs a)
     }
 #pragma unroll
     for (int l = 0; l < R; ++l)
-        gmem(jb.y)[base + l * a.inner] = v[l];
+        store_nt(jb.y + base + l * a.inner, v[l]);
 }
 
 // Strided level of length 32..256: lines of length L along stride `inner`; the LDS tile holds
@@ -465,10 +465,9 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
         v[q] = lds[rpad(j + 256 * q)];
     __syncthreads();
     row4096<+1>(v, lds, j, a.tw4096);
-    const auto dst = gmem(jb.y) + (r << 12);
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-        dst[j + 256 * q] = make_float2(v[q].x * a.scale, v[q].y * a.scale);
+        store_nt(jb.y + (r << 12) + j + 256 * q, make_float2(v[q].x * a.scale, v[q].y * a.scale));
 }
 
 // Single-level transform of n = L < 4096 points: the tile holds C = 4096/L whole pulses.

@@ -88,6 +88,14 @@ __device__ __forceinline__ T gload(const T *p, int64_t i)
     return gmem(p)[i];
 }
 
+// Streaming store of one complex sample (non-temporal hint): large outputs read by the next
+// kernel on other XCDs gain nothing from staying in this XCD's L2.
+__device__ __forceinline__ void store_nt(float2 *p, float2 v)
+{
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(f2v{v.x, v.y}, (RC_GLOBAL_AS f2v *)p);
+}
+
 // One resampling job (one pulse).  Pointers are device addresses.
 struct SincJob {
     const float2 *x;

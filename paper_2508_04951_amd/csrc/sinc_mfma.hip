@@ -542,7 +542,7 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
                         yr = fmaf(yr, z, acc[t][r][0][j]);
                         yi = fmaf(yi, z, acc[t][r][1][j]);
                     }
-                    yt[off] = make_float2(yr * unscale, yi * unscale);
+                    store_nt(c.jb.y + c.M0 + off, make_float2(yr * unscale, yi * unscale));
                 }
             }
             if (__any(near != 0)) {  // rare: uniform over the wave
