@@ -99,19 +99,25 @@ def roofline_for(kernel: str, avg_ms: float, samples: int, half_width: int, pass
     """Algorithmic work of one launch of `kernel` divided by its average duration."""
     t = avg_ms * 1e-3
     if kernel == "k_sinc_mfma":
+        # The tap sum does 8H flop per output against 16 B of input and output: 32 flop/B at H = 64,
+        # a tenth of the fp16 matrix-core ridge (2500 TFLOP/s / 8 TB/s = 312.5 flop/B), so the roof
+        # that binds this kernel is HBM bandwidth; the matrix-core issue rate is reported beside it.
         flops = 8.0 * half_width * samples  # 2H taps x (2 real FMA = 4 flop) per output sample
-        achieved = flops / t / 1e12
+        bytes_ = BYTES_PER_SAMPLE_PASS * samples
+        achieved = bytes_ / t / 1e9
         ksteps = -(-(2 * half_width + 16) // 32)
         tiles = samples / MF_TILE
         mfma = tiles * 4 * ksteps * 36  # 4 waves x steps x (5 hi*hi + 2 hi*lo + 2 lo*hi) x 4 (sub-tile, re/im)
-        return {"kernel": kernel, "bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_FP16_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / MFMA_FP16_PEAK_TFLOPS, 4),
+        return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(kernel), "traffic_unit": "bytes/launch",
-                "algorithmic_bytes_per_launch": BYTES_PER_SAMPLE_PASS * samples, "algorithmic_per_launch": flops,
-                "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_per_launch": bytes_, "avg_launch_ms": round(avg_ms, 4),
+                "intensity_flop_per_byte": round(flops / bytes_, 2),
+                "mfma_ridge_flop_per_byte": round(MFMA_FP16_PEAK_TFLOPS / HBM_PEAK_GBS * 1e3, 1),
+                "algorithmic_flops_per_launch": flops,
+                "algorithmic_tflops": round(flops / t / 1e12, 2),
                 "mfma_issued_flops_per_launch": mfma * MFMA_FLOP,
-                "mfma_issue_frac": round(mfma / 1024 * MFMA_CYCLES / CLOCK_HZ / t, 4),
-                "hbm_algorithmic_gbs": round(BYTES_PER_SAMPLE_PASS * samples / t / 1e9, 1)}
+                "mfma_issue_frac": round(mfma / 1024 * MFMA_CYCLES / CLOCK_HZ / t, 4)}
     if kernel in ("k_sinc_fast", "k_sinc_direct"):
         flops = 8.0 * half_width * samples
         achieved = flops / t / 1e12

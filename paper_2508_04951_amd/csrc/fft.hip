@@ -344,6 +344,21 @@ struct RowArgs {
     float scale;              // 1/n when this is the only pass, else 1
 };
 
+// (cos 2 pi z, sin 2 pi z) for |z| <= 1/8 revolution: an odd and an even polynomial in z,
+// fitted to minimax on that interval (fit error below 3e-9; float32 evaluation stays within
+// 1.5 ulp of the true values).
+__device__ __forceinline__ float2 cis_eighth(float z)
+{
+    const float u = z * z;
+    float ps = fmaf(u, -0x1.2d9bb6p+6f, 0x1.465ec6p+6f);
+    ps = fmaf(u, ps, -0x1.4abbbap+5f);
+    ps = fmaf(u, ps, 0x1.921fb6p+2f);
+    float pc = fmaf(u, 0x1.d9f7bap+5f, -0x1.55c664p+6f);
+    pc = fmaf(u, pc, 0x1.03c1dep+6f);
+    pc = fmaf(u, pc, -0x1.3bd3ccp+4f);
+    return make_float2(fmaf(u, pc, 1.0f), z * ps);
+}
+
 __device__ __forceinline__ float2 iono_phase(const IonoJob &jb, int64_t k, int64_t n)
 {
     const int64_t kk = (k < (n + 1) / 2) ? k : k - n;
@@ -352,16 +367,20 @@ __device__ __forceinline__ float2 iono_phase(const IonoJob &jb, int64_t k, int64
     if (f == 0.0 || jb.phase_num == 0.0)
         return make_float2(1.f, 0.f);
     // 1/f from the hardware reciprocal and two Newton steps (within 2 ulp; the IEEE division
-    // sequence costs ~70 extra registers here).  The phase, in revolutions, is reduced modulo
-    // 1 in float64 (|phase| is ~1e3..1e5 rad); then the float32 sin/cos of pi * (2 r).
+    // sequence costs ~70 extra registers here).  The phase t, in revolutions, is split in
+    // float64 into quarter turns n4 and a remainder z in [-1/8, 1/8] (|t| is ~1e2..1e4, so z
+    // keeps ~40 bits); cis(2 pi z) is evaluated in float32 and turned by n4 quarter turns.
     double rf = __builtin_amdgcn_rcp(f);
     rf = fma(rf, fma(-f, rf, 1.0), rf);
     rf = fma(rf, fma(-f, rf, 1.0), rf);
     const double t = (jb.phase_num * rf) * 0.15915494309189533577;
-    const double r = t - rint(t);
-    float s, c;
-    sincospif((float)(2.0 * r), &s, &c);
-    return make_float2(c, s);
+    const double n4 = rint(4.0 * t);
+    const float z = (float)fma(n4, -0.25, t);
+    const int quad = (int)(n4 - 4.0 * floor(n4 * 0.25));  // n4 mod 4, exact for |n4| < 2^53
+    const float2 w = cis_eighth(z);
+    const float c = (quad & 1) ? -w.y : w.x;  // (c, s) turned by quad * 90 degrees
+    const float sn = (quad & 1) ? w.x : w.y;
+    return (quad & 2) ? make_float2(-c, -sn) : make_float2(c, sn);
 }
 
 // One radix-16 Stockham stage of a 4096-point row held as 16 samples per thread

@@ -93,7 +93,7 @@ def test_server_mixed_stream_equals_single_calls(torch, ctx, orc):
 def test_server_admission_poll_and_errors(torch, ctx):
     import paper_2508_04951_amd as rc
 
-    n = 1 << 16
+    n = 1 << 24  # ~0.6 ms of device work per request: far longer than the next submit call
     x = dev(torch, wf.bandlimited_noise(n, wf.rng_for(302, 0)))
     ys = [torch.empty(n, dtype=torch.complex64, device="cuda") for _ in range(4)]
     # a budget of three requests (16 B per sample each)
@@ -101,7 +101,7 @@ def test_server_admission_poll_and_errors(torch, ctx):
     t = [srv.submit(x, ys[i], alpha=alpha_exact(1000.0 * i), tec=20 * wf.TECU, carrier=450e6, fs=10e6)
          for i in range(3)]
     with pytest.raises(rc.RcError) as ei:  # the fourth does not fit while three are in flight
-        srv.submit(x, ys[3], alpha=1.0)
+        srv.submit(x[:1024], ys[3][:1024], alpha=1.0)
     assert ei.value.status == 5  # RC_ERR_BUSY
     srv.wait(t[0])
     srv.wait(t[1])
@@ -112,7 +112,7 @@ def test_server_admission_poll_and_errors(torch, ctx):
         srv.poll(t3)  # released
     with pytest.raises(rc.RcError) as ei:  # could never fit
         big = torch.empty(4 * n, dtype=torch.complex64, device="cuda")
-        srv.submit(big, big, flags=rc.DO_IONO, tec=1e17, carrier=450e6, fs=10e6)
+        srv.submit(big, torch.empty_like(big), flags=rc.DO_DOPPLER, alpha=alpha_exact(500.0))
     assert ei.value.status == 2
     with pytest.raises(ValueError):
         srv.submit(x, ys[0], alpha=float("nan"))
