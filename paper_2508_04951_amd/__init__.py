@@ -5,9 +5,10 @@ The compute lives in librc.so (hand-written HIP kernels behind the C ABI of incl
 this package is its Python binding.  torch supplies device memory and streams.
 """
 from ._rc import (BANK_MODES, DIRECTIONS, DO_DOPPLER, DO_IONO, KERNELS, SINC_ENGINES, SYMBOLS, WINDOWS, Context,
-                  RcError, Server, Sinc, alpha_from_vr, context, k2_per_tec, load_library, pulse_array)
+                  RcError, Server, Sinc, alpha_from_vr, context, k2_per_tec, load_library, pulse_array,
+                  PULSE_DTYPE, pulse_table)
 
 __all__ = [
     "Context", "RcError", "Server", "Sinc", "BANK_MODES", "alpha_from_vr", "k2_per_tec", "context", "load_library",
-    "pulse_array", "KERNELS", "SINC_ENGINES", "DIRECTIONS", "WINDOWS", "DO_DOPPLER", "DO_IONO", "SYMBOLS",
+    "pulse_array", "pulse_table", "PULSE_DTYPE", "KERNELS", "SINC_ENGINES", "DIRECTIONS", "WINDOWS", "DO_DOPPLER", "DO_IONO", "SYMBOLS",
 ]

@@ -283,13 +283,14 @@ class Context:
     def correct_pulse_batch(self, x_packed, y_packed, pulses, sinc: Sinc | None = None, stream=None):
         """Per-pulse Doppler then ionosphere over packed buffers; `pulses` is a sequence of
         dicts with keys off_in, n_in, off_out, n_out, fs, alpha, tec, carrier and optional
-        flags (default Doppler|iono) and direction ("correct")."""
+        flags (default Doppler|iono) and direction ("correct"), or a table from pulse_table."""
         _check_samples(x_packed, "x_packed")
         _check_samples(y_packed, "y_packed")
         arr = pulse_array(pulses)
+        ptr = arr if isinstance(arr, ctypes.Array) else arr.ctypes.data_as(ctypes.POINTER(RcPulse))
         k = (sinc or Sinc()).c()
         st = self._lib.correct_pulse_batch(self._h, x_packed.data_ptr(), x_packed.numel(), y_packed.data_ptr(),
-                                           y_packed.numel(), arr, len(arr), ctypes.byref(k),
+                                           y_packed.numel(), ptr, len(arr), ctypes.byref(k),
                                            self._stream(stream))
         if st != RC_OK:
             self._raise(st, "correct_pulse_batch")
@@ -402,8 +403,17 @@ def _bank_alphas(alphas) -> ctypes.Array:
     return (ctypes.c_double * len(vals))(*vals)
 
 
-def pulse_array(pulses) -> ctypes.Array:
-    """Pack pulse dicts into a contiguous rc_pulse array."""
+def pulse_array(pulses):
+    """The rc_pulse array for correct_pulse_batch: a sequence of pulse dicts is packed here (about
+    3 us per pulse of Python work); a table from `pulse_table` or a ctypes RcPulse array is passed
+    through without copying."""
+    if isinstance(pulses, ctypes.Array) and pulses._type_ is RcPulse:
+        return pulses
+    np = _numpy()
+    if isinstance(pulses, np.ndarray):
+        if pulses.dtype != PULSE_DTYPE or pulses.ndim != 1 or not pulses.flags.c_contiguous:
+            raise ValueError("a pulse table must be a contiguous 1-D array of PULSE_DTYPE (see pulse_table)")
+        return pulses
     arr = (RcPulse * len(pulses))()
     for i, p in enumerate(pulses):
         d = p.get("direction", "correct")
@@ -412,6 +422,38 @@ def pulse_array(pulses) -> ctypes.Array:
                          float(p.get("carrier", 0.0)), int(p.get("flags", DO_DOPPLER | DO_IONO)),
                          DIRECTIONS[d] if isinstance(d, str) else int(d))
     return arr
+
+
+def _numpy():
+    import numpy
+    return numpy
+
+
+def _pulse_dtype():
+    np = _numpy()
+    dt = np.dtype([(name, {ctypes.c_int64: "<i8", ctypes.c_double: "<f8", ctypes.c_uint32: "<u4",
+                           ctypes.c_int32: "<i4"}[ct]) for name, ct in RcPulse._fields_], align=True)
+    if dt.itemsize != ctypes.sizeof(RcPulse) or any(
+            dt.fields[name][1] != getattr(RcPulse, name).offset for name, _ in RcPulse._fields_):
+        raise RuntimeError("numpy layout of rc_pulse differs from the C layout")
+    return dt
+
+
+PULSE_DTYPE = _pulse_dtype()
+
+
+def pulse_table(off_in, n_in, off_out, n_out, fs, alpha=1.0, tec=0.0, carrier=0.0,
+                flags=DO_DOPPLER | DO_IONO, direction="correct"):
+    """Descriptor table (numpy array of PULSE_DTYPE, the rc_pulse layout) built column-wise: each
+    argument is a scalar or a 1-D array over the pulses, broadcast to a common length."""
+    np = _numpy()
+    d = DIRECTIONS[direction] if isinstance(direction, str) else direction
+    cols = [np.asarray(c) for c in (off_in, n_in, off_out, n_out, fs, alpha, tec, carrier, flags, d)]
+    count = max([c.size for c in cols if c.ndim > 0] or [1])
+    t = np.zeros(count, dtype=PULSE_DTYPE)
+    for name, c in zip(PULSE_DTYPE.names, cols):
+        t[name] = np.broadcast_to(c.reshape(-1) if c.ndim else c, (count,))
+    return t
 
 
 _contexts: dict[int, Context] = {}

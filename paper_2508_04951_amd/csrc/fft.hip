@@ -196,16 +196,13 @@ __device__ __forceinline__ float2 unit_root(int64_t q, int log2M)
     return make_float2(cs, S * sn);
 }
 
-// v[q] *= exp(S 2 pi i q m / M) for q = 1 .. R-1 (M a power of two, M <= 2^24).  The bases
-// exp(S 2 pi i 2^t m / M), t = 0..3, come from sincospi of exact float32 arguments; every other
-// power is a product of at most four bases (error within ~5 ulp).  No table gathers: a table
-// indexed by q m scatters a wave's loads over as many cache lines as it has lanes.
+// Bases exp(S 2 pi i 2^t m / M), t = 0..3 (those below R), of the stage twiddle
+// exp(S 2 pi i q m / M), M a power of two <= 2^24: sincospi of exact float32 arguments.
 template <int R, int S>
-__device__ __forceinline__ void twiddle_powers(float2 *v, int64_t m, int log2M)
+__device__ __forceinline__ void twiddle_bases(float2 *b, int64_t m, int log2M)
 {
     const int64_t mask = (int64_t(1) << log2M) - 1;
     const float scale = ldexpf(2.0f, -log2M);  // 2 / M, exact
-    float2 b[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         if ((1 << t) < R) {
@@ -215,6 +212,14 @@ __device__ __forceinline__ void twiddle_powers(float2 *v, int64_t m, int log2M)
             b[t] = make_float2(cs, S * sn);
         }
     }
+}
+
+// v[q] *= b^q for q = 1 .. R-1, where b[t] holds the 2^t-th power: every other power is a product
+// of at most four bases (error within ~5 ulp).  No table gathers: a table indexed by q m scatters
+// a wave's loads over as many cache lines as it has lanes.
+template <int R>
+__device__ __forceinline__ void twiddle_apply(float2 *v, const float2 *b)
+{
     float2 w3 = make_float2(1.f, 0.f), w5 = w3, w6 = w3, w7 = w3;
     if (R > 1) v[1] = cmul(v[1], b[0]);
     if (R > 2) {
@@ -241,6 +246,15 @@ __device__ __forceinline__ void twiddle_powers(float2 *v, int64_t m, int log2M)
         v[14] = cmul(v[14], cmul(w6, b[3]));
         v[15] = cmul(v[15], cmul(w7, b[3]));
     }
+}
+
+// v[q] *= exp(S 2 pi i q m / M) for q = 1 .. R-1.
+template <int R, int S>
+__device__ __forceinline__ void twiddle_powers(float2 *v, int64_t m, int log2M)
+{
+    float2 b[4];
+    twiddle_bases<R, S>(b, m, log2M);
+    twiddle_apply<R>(v, b);
 }
 
 struct StridedArgs {
@@ -344,43 +358,58 @@ struct RowArgs {
     float scale;              // 1/n when this is the only pass, else 1
 };
 
-// (cos 2 pi z, sin 2 pi z) for |z| <= 1/8 revolution: an odd and an even polynomial in z,
+// (cos pi w / 2, sin pi w / 2) for |w| <= 1/2 quarter turn: an even and an odd polynomial in w,
 // fitted to minimax on that interval (fit error below 3e-9; float32 evaluation stays within
 // 1.5 ulp of the true values).
-__device__ __forceinline__ float2 cis_eighth(float z)
+__device__ __forceinline__ float2 cis_quarter(float w)
 {
-    const float u = z * z;
-    float ps = fmaf(u, -0x1.2d9bb6p+6f, 0x1.465ec6p+6f);
-    ps = fmaf(u, ps, -0x1.4abbbap+5f);
-    ps = fmaf(u, ps, 0x1.921fb6p+2f);
-    float pc = fmaf(u, 0x1.d9f7bap+5f, -0x1.55c664p+6f);
-    pc = fmaf(u, pc, 0x1.03c1dep+6f);
-    pc = fmaf(u, pc, -0x1.3bd3ccp+4f);
-    return make_float2(fmaf(u, pc, 1.0f), z * ps);
+    const float u = w * w;
+    float ps = fmaf(u, -0x1.2d9bb8p-8f, 0x1.465ec6p-4f);
+    ps = fmaf(u, ps, -0x1.4abbbap-1f);
+    ps = fmaf(u, ps, 0x1.921fb6p+0f);
+    float pc = fmaf(u, 0x1.d9f7bcp-11f, -0x1.55c664p-6f);
+    pc = fmaf(u, pc, 0x1.03c1dep-2f);
+    pc = fmaf(u, pc, -0x1.3bd3ccp+0f);
+    return make_float2(fmaf(u, pc, 1.0f), w * ps);
+}
+
+// Per-job constants of the dispersive phase of Eq (15)/(16): in quarter turns the phase at bin
+// frequency f is c4 / f, with f = carrier + fs_n kk for the signed bin index kk (fs_n = fs / n).
+struct PhaseK {
+    double c4, carrier, fs_n;
+};
+
+__device__ __forceinline__ PhaseK phase_consts(const IonoJob &jb, int64_t n)
+{
+    return PhaseK{jb.phase_num * 0.63661977236758134308, jb.carrier, jb.fs * (1.0 / (double)n)};
+}
+
+__device__ __forceinline__ float2 phase_at(const PhaseK &P, int64_t kk)
+{
+    const double f = fma(P.fs_n, (double)kk, P.carrier);
+    // 1/f from the hardware reciprocal (relative error below 2^-24 on gfx950) and one Newton step,
+    // which squares that error: below 2^-48, i.e. under 1e-9 quarter turn for |t4| < 2^17 (the IEEE
+    // division sequence costs ~70 extra registers here).  The phase t4 = c4 / f, in quarter turns
+    // (|t4| is ~1e2..1e5), is split in float64 into a whole number n4 and a remainder w in
+    // [-1/2, 1/2] (exact); cis(pi w / 2) in float32 is then turned by n4 quarter turns.
+    double rf = __builtin_amdgcn_rcp(f);
+    rf = fma(rf, fma(-f, rf, 1.0), rf);
+    const double t4 = P.c4 * rf;
+    const double n4 = rint(t4);
+    const float2 w = cis_quarter((float)(t4 - n4));
+    // n4 mod 4 (beyond 2^30 quarter turns the float64 phase has no fractional bits left anyway)
+    const int quad = (int)fmin(fmax(n4, -0x1p30), 0x1p30) & 3;
+    const float c = (quad & 1) ? -w.y : w.x;  // (c, s) turned by quad * 90 degrees
+    const float sn = (quad & 1) ? w.x : w.y;
+    if (f == 0.0)
+        return make_float2(1.f, 0.f);
+    return (quad & 2) ? make_float2(-c, -sn) : make_float2(c, sn);
 }
 
 __device__ __forceinline__ float2 iono_phase(const IonoJob &jb, int64_t k, int64_t n)
 {
     const int64_t kk = (k < (n + 1) / 2) ? k : k - n;
-    // n is a power of two, so kk * (1/n) is exactly kk / n
-    const double f = jb.carrier + jb.fs * (double)kk * (1.0 / (double)n);
-    if (f == 0.0 || jb.phase_num == 0.0)
-        return make_float2(1.f, 0.f);
-    // 1/f from the hardware reciprocal and two Newton steps (within 2 ulp; the IEEE division
-    // sequence costs ~70 extra registers here).  The phase t, in revolutions, is split in
-    // float64 into quarter turns n4 and a remainder z in [-1/8, 1/8] (|t| is ~1e2..1e4, so z
-    // keeps ~40 bits); cis(2 pi z) is evaluated in float32 and turned by n4 quarter turns.
-    double rf = __builtin_amdgcn_rcp(f);
-    rf = fma(rf, fma(-f, rf, 1.0), rf);
-    rf = fma(rf, fma(-f, rf, 1.0), rf);
-    const double t = (jb.phase_num * rf) * 0.15915494309189533577;
-    const double n4 = rint(4.0 * t);
-    const float z = (float)fma(n4, -0.25, t);
-    const int quad = (int)(n4 - 4.0 * floor(n4 * 0.25));  // n4 mod 4, exact for |n4| < 2^53
-    const float2 w = cis_eighth(z);
-    const float c = (quad & 1) ? -w.y : w.x;  // (c, s) turned by quad * 90 degrees
-    const float sn = (quad & 1) ? w.x : w.y;
-    return (quad & 2) ? make_float2(-c, -sn) : make_float2(c, sn);
+    return phase_at(phase_consts(jb, n), kk);
 }
 
 // One radix-16 Stockham stage of a 4096-point row held as 16 samples per thread
@@ -389,9 +418,12 @@ __device__ __forceinline__ float2 iono_phase(const IonoJob &jb, int64_t k, int64
 __device__ __forceinline__ int rpad(int a) { return a + (a >> 4); }
 
 // Full 4096-point DFT of the thread-distributed row: in v[q] = x[j + 256 q], out v[q] = X[j + 256 q].
+// b2 and b3 are the forward twiddle bases of stages 2 and 3 (m = 16 (j % 16) and m = j over 4096);
+// the inverse uses their conjugates, so one set of sincospi serves both transforms of a row.
 template <int S>
-__device__ __forceinline__ void row4096(float2 *v, float2 *lds, int j, const float2 *__restrict__ tw)
+__device__ __forceinline__ void row4096(float2 *v, float2 *lds, int j, const float2 *b2, const float2 *b3)
 {
+    float2 w[4];
     // stage 1 (Ns = 1): outputs at 16 j + q
     dftR<16, S>(v);
 #pragma unroll
@@ -402,7 +434,10 @@ __device__ __forceinline__ void row4096(float2 *v, float2 *lds, int j, const flo
 #pragma unroll
     for (int q = 0; q < 16; ++q)
         v[q] = lds[rpad(j + 256 * q)];
-    twiddle_powers<16, S>(v, 16 * (j & 15), 12);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        w[t] = make_float2(b2[t].x, S < 0 ? b2[t].y : -b2[t].y);
+    twiddle_apply<16>(v, w);
     dftR<16, S>(v);
     __syncthreads();
     const int base = ((j >> 4) << 8) + (j & 15);
@@ -414,7 +449,10 @@ __device__ __forceinline__ void row4096(float2 *v, float2 *lds, int j, const flo
 #pragma unroll
     for (int q = 0; q < 16; ++q)
         v[q] = lds[rpad(j + 256 * q)];
-    twiddle_powers<16, S>(v, j, 12);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        w[t] = make_float2(b3[t].x, S < 0 ? b3[t].y : -b3[t].y);
+    twiddle_apply<16>(v, w);
     dftR<16, S>(v);
     __syncthreads();  // LDS free for the next transform
 }
@@ -433,7 +471,16 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
 #pragma unroll
     for (int q = 0; q < 16; ++q)
         v[q] = src[j + 256 * q];
-    row4096<-1>(v, lds, j, a.tw4096);
+    // forward twiddle bases W^(2^t m), W = exp(-2 pi i / 4096), from the float64-built table
+    // (read while the row's loads are in flight): m = 16 (j % 16) for stage 2, m = j for stage 3
+    float2 b2[4], b3[4];
+    const auto tw = gmem(a.tw4096);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        b2[t] = tw[((16 * (j & 15)) << t) & (kFftTile - 1)];
+        b3[t] = tw[(j << t) & (kFftTile - 1)];
+    }
+    row4096<-1>(v, lds, j, b2, b3);
     if (a.fwd_only) {
         const auto dst = gmem(jb.y) + (r << 12);
 #pragma unroll
@@ -470,9 +517,13 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
     } else {
         // the 16 phases as independent chains (the samples wait in LDS meanwhile)
         float2 ph[16];
+        const PhaseK pk = phase_consts(jb, a.n);
+        const int n = (int)a.n, half = (n + 1) / 2;  // n <= 2^24
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-            ph[q] = iono_phase(jb, kout + mult * (j + 256 * q), a.n);
+        for (int q = 0; q < 16; ++q) {
+            const int k = (int)kout + (int)mult * (j + 256 * q);
+            ph[q] = phase_at(pk, k < half ? k : k - n);
+        }
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int i = rpad(j + 256 * q);
@@ -483,7 +534,7 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
     for (int q = 0; q < 16; ++q)
         v[q] = lds[rpad(j + 256 * q)];
     __syncthreads();
-    row4096<+1>(v, lds, j, a.tw4096);
+    row4096<+1>(v, lds, j, b2, b3);
 #pragma unroll
     for (int q = 0; q < 16; ++q)
         store_nt(jb.y + (r << 12) + j + 256 * q, make_float2(v[q].x * a.scale, v[q].y * a.scale));

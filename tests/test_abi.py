@@ -83,3 +83,31 @@ def test_create_without_a_device_fails_cleanly(lib):
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(rc._rc.RcSinc) == 16
     assert ctypes.sizeof(rc._rc.RcPulse) == 72
+
+
+def test_pulse_table_matches_the_dict_packing():
+    import numpy as np
+
+    P, n = 37, 4096
+    rng = np.random.default_rng(5)
+    alpha = 1.0 + rng.uniform(-5e-5, 5e-5, P)
+    tec = rng.uniform(5e16, 1e18, P)
+    flags = rng.integers(1, 4, P)
+    dirs = ["correct" if p % 3 else "distort" for p in range(P)]
+    d = [dict(off_in=p * n, n_in=n, off_out=p * (n + 7), n_out=n + 7, fs=10e6, alpha=float(alpha[p]),
+              tec=float(tec[p]), carrier=450e6, flags=int(flags[p]), direction=dirs[p]) for p in range(P)]
+    t = rc.pulse_table(np.arange(P) * n, n, np.arange(P) * (n + 7), n + 7, 10e6, alpha=alpha, tec=tec,
+                       carrier=450e6, flags=flags, direction=np.array([rc.DIRECTIONS[x] for x in dirs]))
+    assert t.dtype == rc.PULSE_DTYPE and t.dtype.itemsize == ctypes.sizeof(rc._rc.RcPulse)
+    assert bytes(rc.pulse_array(d)) == t.tobytes()
+    assert rc.pulse_array(t) is t  # passed through without a copy
+
+
+def test_pulse_table_rejects_other_layouts():
+    import numpy as np
+
+    t = rc.pulse_table(np.arange(4) * 8, 8, np.arange(4) * 8, 8, 1.0)
+    with pytest.raises(ValueError):
+        rc.pulse_array(t[::2])  # not contiguous
+    with pytest.raises(ValueError):
+        rc.pulse_array(np.zeros(4, dtype=np.float64))

@@ -296,6 +296,27 @@ def test_batch_matches_oracle_and_single_calls(torch, ctx, orc):
     assert np.isnan(yb[gaps]).all()  # nothing written outside the pulses
 
 
+def test_batch_from_a_pulse_table_is_bit_identical(torch, ctx):
+    """The same ragged batch described by a pulse_table array instead of dicts."""
+    import paper_2508_04951_amd as rc
+
+    pulses, xs, x_len, y_len = _ragged_batch()
+    xp = np.zeros(x_len, np.complex64)
+    for p, x in zip(pulses, xs):
+        xp[p["off_in"]:p["off_in"] + p["n_in"]] = x
+    xd = dev(torch, xp)
+    col = lambda k: np.array([p[k] for p in pulses])
+    table = rc.pulse_table(col("off_in"), col("n_in"), col("off_out"), col("n_out"), col("fs"), alpha=col("alpha"),
+                           tec=col("tec"), carrier=col("carrier"), flags=col("flags"),
+                           direction=np.array([rc.DIRECTIONS[d] for d in col("direction")]))
+    outs = []
+    for desc in (pulses, table):
+        yd = torch.full((y_len,), complex("nan"), dtype=torch.complex64, device="cuda")
+        ctx.correct_pulse_batch(xd, yd, desc, rc.Sinc(64))
+        outs.append(host(yd))
+    assert np.array_equal(outs[0], outs[1], equal_nan=True)
+
+
 def test_batch_c2_full_size_sampled(torch, ctx, orc):
     """The full batch workload (1024 pulses x 65536, Kaiser H = 64, beta = 8) in one call;
     four seeded pulses compared in full against the oracle, all pulses finite."""
