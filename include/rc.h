@@ -178,8 +178,11 @@ rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c6
  * Doppler first and then the ionosphere as in correct_pulse_batch, on caller-owned device
  * buffers that must stay valid (and y untouched) until the request completes.  A launcher
  * thread takes everything queued (up to max_batch requests) as one batch on the server's own
- * stream as soon as requests are queued, without waiting for earlier batches; a completer
- * thread times each batch's completion.  Admission is by bytes: a request holds
+ * stream whenever fewer than two earlier batches are still running on the device: a request
+ * that arrives at an idle server starts at once, and under load the queue fills while the
+ * device works, so one launch sequence serves many requests (ionospheric lengths that are not
+ * powers of two share theirs by convolution length).  A completer thread times each batch's
+ * completion.  Admission is by bytes: a request holds
  * 8 (n_in + n_out) bytes, plus 32 n_out for an ionospheric length that is not a power of two,
  * until it completes; rc_server_submit returns RC_ERR_BUSY when the budget is full and
  * RC_ERR_UNSUPPORTED for a request that could never fit.  Every pulse uses the kernel *k

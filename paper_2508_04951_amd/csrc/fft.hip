@@ -786,51 +786,56 @@ __device__ __forceinline__ float2 chirp_w(int64_t m, int64_t N)
 }
 
 // a = x conj(w) zero-padded to M; b = the chirp placed circularly (b_m = b_{M-m} = w_m, m < N).
-__global__ void __launch_bounds__(256) k_bluestein_pre(const float2 *__restrict__ x, int64_t N, int64_t M,
-                                                       float2 *__restrict__ a, float2 *__restrict__ b)
+// One job per blockIdx.y.
+__global__ void __launch_bounds__(256) k_bluestein_pre(const BluesteinJob *jobs, BluesteinJob inl, int64_t M)
 {
-    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const BluesteinJob jb = jobs ? gload(jobs, blockIdx.y) : inl;
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x, N = jb.n;
     if (m >= M)
         return;
     float2 av = make_float2(0.f, 0.f), bv = make_float2(0.f, 0.f);
     if (m < N) {
         const float2 w = chirp_w(m, N);
-        const float2 v = gload(x, m);
+        const float2 v = gload(jb.x, m);
         av = make_float2(v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y);  // v conj(w)
         bv = w;
     } else if (M - m < N) {
         bv = chirp_w(M - m, N);
     }
-    gmem(a)[m] = av;
-    gmem(b)[m] = bv;
+    gmem(jb.a)[m] = av;
+    gmem(jb.a + M)[m] = bv;
 }
 
-// c (first convolution) -> conj(c_k H_k) for k < N, zero above.
-__global__ void __launch_bounds__(256) k_bluestein_mid(float2 *__restrict__ c, int64_t N, int64_t M, IonoJob jb)
+// c (first convolution, in a) -> conj(c_k H_k) for k < N, zero above.
+__global__ void __launch_bounds__(256) k_bluestein_mid(const BluesteinJob *jobs, BluesteinJob inl, int64_t M)
 {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const BluesteinJob jb = jobs ? gload(jobs, blockIdx.y) : inl;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x, N = jb.n;
     if (k >= M)
         return;
     float2 v = make_float2(0.f, 0.f);
     if (k < N) {
-        const float2 h = cmul(gload(c, k), iono_phase(jb, k, N));
+        const IonoJob ph{nullptr, nullptr, jb.phase_num, jb.carrier, jb.fs, nullptr};
+        const float2 h = cmul(gload(jb.a, k), iono_phase(ph, k, N));
         v = make_float2(h.x, -h.y);
     }
-    gmem(c)[k] = v;
+    gmem(jb.a)[k] = v;
 }
 
-// f (second convolution) -> y_n = w_n conj(f_n) / N.
-__global__ void __launch_bounds__(256) k_bluestein_post(const float2 *__restrict__ f, int64_t N,
-                                                        float2 *__restrict__ y)
+// f (second convolution, in a) -> y_n = w_n conj(f_n) / N.
+__global__ void __launch_bounds__(256) k_bluestein_post(const BluesteinJob *jobs, BluesteinJob inl)
 {
-    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const BluesteinJob jb = jobs ? gload(jobs, blockIdx.y) : inl;
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x, N = jb.n;
     if (n >= N)
         return;
-    const float2 w = chirp_w(n, N), v = gload(f, n);
+    const float2 w = chirp_w(n, N), v = gload(jb.a, n);
     const float sc = (float)(1.0 / (double)N);
     // w conj(v)
-    gmem(y)[n] = make_float2((w.x * v.x + w.y * v.y) * sc, (w.y * v.x - w.x * v.y) * sc);
+    gmem(jb.y)[n] = make_float2((w.x * v.x + w.y * v.y) * sc, (w.y * v.x - w.x * v.y) * sc);
 }
+
+}  // namespace
 
 int64_t bluestein_m(int64_t n)
 {
@@ -839,8 +844,6 @@ int64_t bluestein_m(int64_t n)
         m <<= 1;
     return m;
 }
-
-}  // namespace
 
 hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
                        const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof)
@@ -856,51 +859,42 @@ hipError_t launch_fft_forward(const FftPlan &plan, const float2 *tw4096, const I
 
 size_t bluestein_work_bytes(int64_t n) { return (size_t)bluestein_m(n) * 2 * sizeof(float2); }
 
-hipError_t launch_iono_bluestein(int64_t n, const FftPlan &mplan, const float2 *tw4096, const float2 *x,
-                                 float2 *y, double phase_num, double carrier, double fs, void *work,
+hipError_t launch_iono_bluestein(const FftPlan &mplan, const float2 *tw4096, const BluesteinJob *jobs_dev,
+                                 const IonoJob *ffts_dev, const BluesteinJob &inl, int njobs, int64_t max_n,
                                  hipStream_t s, Profiler *prof)
 {
-    const int64_t M = bluestein_m(n);
-    if (mplan.n != M || n < 2 || !work)
+    const int64_t M = mplan.n;
+    if (njobs <= 0)
+        return hipSuccess;
+    if (njobs > 65535 || max_n < 2 || bluestein_m(max_n) > M || (!jobs_dev && (njobs != 1 || !inl.a)) ||
+        (jobs_dev && !ffts_dev))
         return hipErrorInvalidValue;
-    float2 *a = static_cast<float2 *>(work);
-    float2 *b = a + M;
-    const unsigned gm = (unsigned)((M + 255) / 256), gn = (unsigned)((n + 255) / 256);
-    if (prof)
-        prof->begin(kKBluestein, s);
-    hipLaunchKernelGGL(k_bluestein_pre, dim3(gm), dim3(256), 0, s, x, n, M, a, b);
-    hipError_t e = hipGetLastError();
-    if (prof)
-        prof->end(s);
+    const dim3 gm((unsigned)((M + 255) / 256), (unsigned)njobs), gn((unsigned)((max_n + 255) / 256), (unsigned)njobs);
+    auto small = [&](auto kernel, dim3 grid, auto... extra) {
+        if (prof)
+            prof->begin(kKBluestein, s);
+        hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, jobs_dev, inl, extra...);
+        const hipError_t e = hipGetLastError();
+        if (prof)
+            prof->end(s);
+        return e;
+    };
+    hipError_t e = small(k_bluestein_pre, gm, M);
     if (e != hipSuccess)
         return e;
-    // the chirp's spectrum, in the native bin order the convolutions multiply in
-    const IonoJob jb_b{b, b, 0.0, 0.0, 0.0, nullptr};
-    e = launch_fft_forward(mplan, tw4096, nullptr, &jb_b, 1, s, prof);
-    if (e != hipSuccess)
-        return e;
-    const IonoJob conv{a, a, 0.0, 0.0, 0.0, b};
-    e = launch_iono(mplan, tw4096, nullptr, &conv, 1, s, prof);
-    if (e != hipSuccess)
-        return e;
-    const IonoJob ph{nullptr, nullptr, phase_num, carrier, fs, nullptr};
-    if (prof)
-        prof->begin(kKBluestein, s);
-    hipLaunchKernelGGL(k_bluestein_mid, dim3(gm), dim3(256), 0, s, a, n, M, ph);
-    e = hipGetLastError();
-    if (prof)
-        prof->end(s);
-    if (e != hipSuccess)
-        return e;
-    e = launch_iono(mplan, tw4096, nullptr, &conv, 1, s, prof);
-    if (e != hipSuccess)
-        return e;
-    if (prof)
-        prof->begin(kKBluestein, s);
-    hipLaunchKernelGGL(k_bluestein_post, dim3(gn), dim3(256), 0, s, a, n, y);
-    e = hipGetLastError();
-    if (prof)
-        prof->end(s);
+    // the chirp spectra, in the native bin order the convolutions multiply in
+    const IonoJob jb_b{inl.a + M, inl.a + M, 0.0, 0.0, 0.0, nullptr};
+    const IonoJob conv{inl.a, inl.a, 0.0, 0.0, 0.0, inl.a + M};
+    const IonoJob *fb = jobs_dev ? ffts_dev : nullptr, *fc = jobs_dev ? ffts_dev + njobs : nullptr;
+    e = launch_fft_forward(mplan, tw4096, fb, &jb_b, njobs, s, prof);
+    if (e == hipSuccess)
+        e = launch_iono(mplan, tw4096, fc, &conv, njobs, s, prof);
+    if (e == hipSuccess)
+        e = small(k_bluestein_mid, gm, M);
+    if (e == hipSuccess)
+        e = launch_iono(mplan, tw4096, fc, &conv, njobs, s, prof);
+    if (e == hipSuccess)
+        e = small(k_bluestein_post, gn);
     return e;
 }
 

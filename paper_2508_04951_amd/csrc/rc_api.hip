@@ -89,8 +89,10 @@ struct DeviceGuard {
 // `extra` more bytes of device workspace after them (from offset align256(bytes)).  A slot is
 // reused only after the work that read it has completed, so the host may run up to
 // kDescSlots - 1 calls ahead of the device.
-rc_status stage_descriptors(rc_context ctx, const void *host, size_t bytes, size_t extra, hipStream_t s,
-                            const void **dev_out)
+// Waits until the next ring slot is free and sizes it for `bytes` of descriptors plus `extra`
+// bytes of device workspace (at the next 256-byte boundary); returns the slot's pinned host
+// buffer and its device buffer.
+rc_status reserve_descriptors(rc_context ctx, size_t bytes, size_t extra, void **host_out, char **dev_out)
 {
     auto &slot = ctx->desc[ctx->desc_next];
     hipError_t e;
@@ -127,17 +129,41 @@ rc_status stage_descriptors(rc_context ctx, const void *host, size_t bytes, size
             return fail(ctx, RC_ERR_OUT_OF_MEMORY, "descriptor workspace allocation failed");
         slot.dev_cap = cap;
     }
-    if (bytes) {
-        std::memcpy(slot.host, host, bytes);
-        e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, ctx->copy_stream);
-        if (e == hipSuccess)
-            e = hipEventRecord(slot.uploaded, ctx->copy_stream);
-        if (e == hipSuccess)
-            e = hipStreamWaitEvent(s, slot.uploaded, 0);
-        if (e != hipSuccess)
-            return device_fail(ctx, e, "descriptor upload");
-    }
-    *dev_out = slot.dev;
+    *host_out = slot.host;
+    *dev_out = static_cast<char *>(slot.dev);
+    return RC_OK;
+}
+
+// Uploads the first `bytes` of the reserved slot's host buffer on the copy stream; `s` waits for it.
+rc_status upload_descriptors(rc_context ctx, size_t bytes, hipStream_t s)
+{
+    if (!bytes)
+        return RC_OK;
+    auto &slot = ctx->desc[ctx->desc_next];
+    hipError_t e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, ctx->copy_stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(slot.uploaded, ctx->copy_stream);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(s, slot.uploaded, 0);
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "descriptor upload");
+    return RC_OK;
+}
+
+rc_status stage_descriptors(rc_context ctx, const void *host, size_t bytes, size_t extra, hipStream_t s,
+                            const void **dev_out)
+{
+    void *h = nullptr;
+    char *d = nullptr;
+    rc_status st = reserve_descriptors(ctx, bytes, extra, &h, &d);
+    if (st != RC_OK)
+        return st;
+    if (bytes)
+        std::memcpy(h, host, bytes);
+    st = upload_descriptors(ctx, bytes, s);
+    if (st != RC_OK)
+        return st;
+    *dev_out = d;
     return RC_OK;
 }
 
@@ -439,8 +465,8 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
         st = stage_descriptors(ctx, nullptr, 0, rc::bluestein_work_bytes(n), s, &dev);
         if (st != RC_OK)
             return st;
-        e = rc::launch_iono_bluestein(n, *plan, ctx->tw4096, xf, yf, phase, carrier_hz, fs_hz,
-                                      const_cast<void *>(dev), s, prof_of(ctx));
+        const rc::BluesteinJob jb{xf, yf, static_cast<float2 *>(const_cast<void *>(dev)), n, phase, carrier_hz, fs_hz};
+        e = rc::launch_iono_bluestein(*plan, ctx->tw4096, nullptr, nullptr, jb, 1, n, s, prof_of(ctx));
         st = mark_descriptors_used(ctx, s);
         if (e == hipSuccess && st != RC_OK)
             return st;
@@ -451,6 +477,9 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
 }
 
 namespace {
+
+// Workspace cap of one Bluestein launch sequence in a batch (at least one pulse runs).
+constexpr size_t kBluesteinChunkBytes = size_t(256) << 20;
 
 // One pulse of work, with device pointers (a packed-batch entry, a server request, a bank row).
 struct PulseWork {
@@ -542,7 +571,8 @@ rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, 
     // ionospheric jobs by transform length (one launch sequence per length).
     std::vector<SincJob> mfma, fast, direct;
     int64_t mfma_max = 0, fast_max = 0, direct_max = 0, direct_taps = 0;
-    std::map<int64_t, std::vector<IonoJob>> iono;
+    std::map<int64_t, std::vector<IonoJob>> iono;              // power-of-two lengths, by length
+    std::map<int64_t, std::vector<rc::BluesteinJob>> blue;     // other lengths, by convolution length
     std::vector<int32_t> copies;
     for (int32_t i = 0; i < count; ++i) {
         const PulseWork &p = work[(size_t)i];
@@ -565,19 +595,46 @@ rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, 
         }
         if (p.flags & RC_DO_IONO) {
             const float2 *src = (p.flags & RC_DO_DOPPLER) ? p.y : p.x;
-            iono[p.n_out].push_back(IonoJob{src, p.y, phase_numerator(p.tec, p.direction), p.carrier, p.fs_hz, nullptr});
+            const double ph = phase_numerator(p.tec, p.direction);
+            if (is_pow2(p.n_out))
+                iono[p.n_out].push_back(IonoJob{src, p.y, ph, p.carrier, p.fs_hz, nullptr});
+            else
+                blue[rc::bluestein_m(p.n_out)].push_back(
+                    rc::BluesteinJob{src, p.y, nullptr, p.n_out, ph, p.carrier, p.fs_hz});
         }
     }
     if (mfma.size() > 65535 || fast.size() > 65535 || direct.size() > 65535)
         return fail(ctx, RC_ERR_UNSUPPORTED, "more than 65535 pulses of one kind in a batch");
-    size_t bs_work = 0;  // Bluestein workspace: one region, reused by the pulses in stream order
     for (auto &kv : iono) {
         const FftPlan *plan = nullptr;
-        st = get_plan(ctx, iono_plan_length(kv.first), &plan);
+        st = get_plan(ctx, kv.first, &plan);
         if (st != RC_OK)
             return st;
-        if (!is_pow2(kv.first))
-            bs_work = std::max(bs_work, rc::bluestein_work_bytes(kv.first));
+    }
+    // Bluestein pulses of one convolution length run in chunks of one launch sequence each; a
+    // chunk's pulses have workspaces side by side in one region (at most kBluesteinChunkBytes,
+    // or one pulse), reused by the next chunk in stream order.
+    struct BlueChunk {
+        int64_t m, max_n;
+        size_t first, count, off_jobs, off_ffts;
+    };
+    std::vector<BlueChunk> chunks;
+    size_t bs_work = 0;
+    for (auto &kv : blue) {
+        const FftPlan *plan = nullptr;
+        st = get_plan(ctx, kv.first, &plan);
+        if (st != RC_OK)
+            return st;
+        const size_t per = rc::bluestein_work_bytes(kv.second[0].n);  // 2 m complex values
+        const size_t cap = std::max<size_t>(1, std::min<size_t>(65535, kBluesteinChunkBytes / per));
+        for (size_t b = 0; b < kv.second.size(); b += cap) {
+            const size_t cnt = std::min(cap, kv.second.size() - b);
+            int64_t mx = 0;
+            for (size_t i = b; i < b + cnt; ++i)
+                mx = std::max(mx, kv.second[i].n);
+            chunks.push_back(BlueChunk{kv.first, mx, b, cnt, 0, 0});
+            bs_work = std::max(bs_work, cnt * per);
+        }
     }
     const void *mfma_table = nullptr;
     int64_t mfma_tiles = 0;
@@ -608,21 +665,46 @@ rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, 
     const size_t off_fast = fast.empty() ? 0 : append(fast.data(), fast.size() * sizeof(SincJob));
     const size_t off_direct = direct.empty() ? 0 : append(direct.data(), direct.size() * sizeof(SincJob));
     std::vector<size_t> off_iono;
-    for (auto &kv : iono)  // Bluestein lengths run from the host copies of their descriptors
-        off_iono.push_back(is_pow2(kv.first) ? append(kv.second.data(), kv.second.size() * sizeof(IonoJob)) : 0);
+    for (auto &kv : iono)
+        off_iono.push_back(append(kv.second.data(), kv.second.size() * sizeof(IonoJob)));
+    // per Bluestein chunk: its jobs, then 2 x count FFT jobs (chirp transforms, convolutions);
+    // their workspace pointers are filled in once the slot's device address is known
+    for (BlueChunk &c : chunks) {
+        c.off_jobs = append(blue[c.m].data() + c.first, c.count * sizeof(rc::BluesteinJob));
+        const std::vector<IonoJob> blank(2 * c.count);
+        c.off_ffts = append(blank.data(), blank.size() * sizeof(IonoJob));
+    }
     // device workspace after the descriptors: [tile list][Bluestein]
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t extra = mfma_work || bs_work ? al(mfma_work) + bs_work : 0;
-    const void *dev = nullptr;
+    char *devc = nullptr;
     if (!blob.empty() || extra) {
-        st = stage_descriptors(ctx, blob.data(), blob.size(), extra, s, &dev);
+        void *host = nullptr;
+        st = reserve_descriptors(ctx, blob.size(), extra, &host, &devc);
         if (st != RC_OK)
             return st;
+        float2 *bw = reinterpret_cast<float2 *>(devc + al(blob.size()) + al(mfma_work));
+        for (const BlueChunk &c : chunks) {
+            auto *jobs = reinterpret_cast<rc::BluesteinJob *>(blob.data() + c.off_jobs);
+            auto *ffts = reinterpret_cast<IonoJob *>(blob.data() + c.off_ffts);
+            for (size_t q = 0; q < c.count; ++q) {
+                float2 *a = bw + (size_t)q * 2 * c.m, *b = a + c.m;
+                jobs[q].a = a;
+                ffts[q] = IonoJob{b, b, 0.0, 0.0, 0.0, nullptr};
+                ffts[c.count + q] = IonoJob{a, a, 0.0, 0.0, 0.0, b};
+            }
+        }
+        if (!blob.empty())
+            std::memcpy(host, blob.data(), blob.size());
+        st = upload_descriptors(ctx, blob.size(), s);
+        if (st != RC_OK) {
+            (void)mark_descriptors_used(ctx, s);
+            return st;
+        }
     }
-    char *devc = static_cast<char *>(const_cast<void *>(dev));
+    const void *dev = devc;
     char *wbase = extra ? devc + al(blob.size()) : nullptr;
     void *tile_work = mfma_work ? wbase : nullptr;
-    void *bwork = bs_work ? wbase + al(mfma_work) : nullptr;
     // from here on the slot is in use: mark it whatever happens
     struct SlotMark {
         rc_context ctx;
@@ -654,21 +736,22 @@ rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, 
     if (e != hipSuccess)
         return device_fail(ctx, e, "batch Doppler launch");
     size_t gi = 0;
-    for (auto &kv : iono) {
+    for (const BlueChunk &c : chunks) {
         const FftPlan *plan = nullptr;
-        st = get_plan(ctx, iono_plan_length(kv.first), &plan);
+        st = get_plan(ctx, c.m, &plan);
         if (st != RC_OK)
             return st;
-        if (!is_pow2(kv.first)) {
-            ++gi;
-            for (const IonoJob &jb : kv.second) {
-                e = rc::launch_iono_bluestein(kv.first, *plan, ctx->tw4096, jb.x, jb.y, jb.phase_num, jb.carrier,
-                                              jb.fs, bwork, s, prof_of(ctx));
-                if (e != hipSuccess)
-                    return device_fail(ctx, e, "batch ionosphere launch");
-            }
-            continue;
-        }
+        e = rc::launch_iono_bluestein(*plan, ctx->tw4096, reinterpret_cast<const rc::BluesteinJob *>(devc + c.off_jobs),
+                                      reinterpret_cast<const IonoJob *>(devc + c.off_ffts), rc::BluesteinJob{},
+                                      (int)c.count, c.max_n, s, prof_of(ctx));
+        if (e != hipSuccess)
+            return device_fail(ctx, e, "batch ionosphere launch");
+    }
+    for (auto &kv : iono) {
+        const FftPlan *plan = nullptr;
+        st = get_plan(ctx, kv.first, &plan);
+        if (st != RC_OK)
+            return st;
         const IonoJob *jd = reinterpret_cast<const IonoJob *>(devc + off_iono[gi++]);
         // at most 65535 pulses per launch keeps every grid dimension in range
         for (size_t b = 0; b < kv.second.size(); b += 65535) {
@@ -829,6 +912,9 @@ struct rc_server_s {
 
 namespace {
 
+// Batches a server keeps on the device at once: one running and one queued behind it.
+constexpr int kServerFlights = 2;
+
 void server_launcher(rc_server srv)
 {
     for (;;) {
@@ -836,7 +922,14 @@ void server_launcher(rc_server srv)
         hipEvent_t ev = nullptr;
         {
             std::unique_lock<std::mutex> lk(srv->mu);
-            srv->cv_queue.wait(lk, [&] { return srv->stop || !srv->queue.empty(); });
+            // Launch when something is queued and fewer than kServerFlights batches are on the
+            // device: under load the queue fills meanwhile and the next batch takes all of it
+            // (up to max_batch), so the per-launch cost is shared; at light load a request
+            // starts at once.
+            srv->cv_queue.wait(lk, [&] {
+                return (srv->stop && srv->queue.empty()) ||
+                       (!srv->queue.empty() && (int)srv->flights.size() < kServerFlights);
+            });
             if (srv->queue.empty()) {  // stop requested and nothing left
                 srv->launcher_done = true;
                 srv->cv_flight.notify_all();
@@ -915,6 +1008,7 @@ void server_completer(rc_server srv)
                 srv->event_pool.push_back(f.done);
         }
         srv->cv_done.notify_all();
+        srv->cv_queue.notify_all();  // a flight slot is free
     }
 }
 

@@ -224,11 +224,23 @@ hipError_t launch_fft_forward(const FftPlan &plan, const float2 *tw4096, const I
                               const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof);
 
 // Ionospheric operator of a length n that is not a power of two (Bluestein): the N-point DFT
-// as a chirp convolution of power-of-two length m >= 2n - 1.  `work` holds 2 m complex
-// values (the convolution buffer and the chirp spectrum).
-size_t bluestein_work_bytes(int64_t n);
-hipError_t launch_iono_bluestein(int64_t n, const FftPlan &mplan, const float2 *tw4096, const float2 *x,
-                                 float2 *y, double phase_num, double carrier, double fs, void *work,
+// as a chirp convolution of power-of-two length m >= 2n - 1 (bluestein_m).  Each pulse needs
+// 2 m complex values of workspace: the convolution buffer a and the chirp spectrum b = a + m.
+struct BluesteinJob {
+    const float2 *x;  // input, n samples
+    float2 *y;        // output, n samples (may equal x)
+    float2 *a;        // workspace: a[0, m) and b = a + m
+    int64_t n;
+    double phase_num, carrier, fs;  // as in IonoJob
+};
+int64_t bluestein_m(int64_t n);
+size_t bluestein_work_bytes(int64_t n);  // 2 m complex values
+// njobs pulses whose lengths share m = mplan.n, in one launch sequence.  With jobs_dev null,
+// the single job `inl` runs (njobs must be 1; no device descriptors needed).  Otherwise
+// jobs_dev holds the njobs BluesteinJob and ffts_dev 2 njobs IonoJob: the chirp transforms
+// {b_j, b_j} and then the convolutions {a_j, a_j, mult = b_j}.  max_n bounds every job's n.
+hipError_t launch_iono_bluestein(const FftPlan &mplan, const float2 *tw4096, const BluesteinJob *jobs_dev,
+                                 const IonoJob *ffts_dev, const BluesteinJob &inl, int njobs, int64_t max_n,
                                  hipStream_t s, Profiler *prof);
 
 }  // namespace rc

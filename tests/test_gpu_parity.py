@@ -296,6 +296,37 @@ def test_batch_matches_oracle_and_single_calls(torch, ctx, orc):
     assert np.isnan(yb[gaps]).all()  # nothing written outside the pulses
 
 
+def test_batch_bluestein_chunks(torch, ctx, orc):
+    """Ionosphere-only pulses whose lengths are not powers of two: five that share the 2^23
+    convolution length (128 MiB of workspace each, so the batch runs them as chunks of two,
+    two and one) and three that share 2^13, in one call.  Each against the oracle and, bit
+    for bit, against the single-pulse entry point."""
+    import paper_2508_04951_amd as rc
+
+    lens = [4194303, 4100000, 4194000, 4150001, 4194301, 4097, 4100, 6000]
+    rng = wf.rng_for(131, 0)
+    pulses, xs, off = [], [], 0
+    for i, n in enumerate(lens):
+        xs.append(wf.bandlimited_noise(n, wf.rng_for(131, i + 1)))
+        pulses.append(dict(off_in=off, n_in=n, off_out=off, n_out=n, fs=10e6, alpha=1.0,
+                           tec=float(rng.uniform(5, 100)) * wf.TECU, carrier=450e6, flags=rc.DO_IONO,
+                           direction="distort" if i % 3 == 2 else "correct"))
+        off += n + 64
+    xp = np.zeros(off, np.complex64)
+    for p, x in zip(pulses, xs):
+        xp[p["off_in"]:p["off_in"] + p["n_in"]] = x
+    xd = dev(torch, xp)
+    yd = torch.full((off,), complex("nan"), dtype=torch.complex64, device="cuda")
+    ctx.correct_pulse_batch(xd, yd, pulses, rc.Sinc(64))
+    yb = host(yd)
+    for i, (p, x) in enumerate(zip(pulses, xs)):
+        got = yb[p["off_out"]:p["off_out"] + p["n_out"]]
+        ref = orc.ionosphere(x, p["fs"], p["carrier"], p["tec"], p["direction"])
+        assert rel_l2(got, ref) <= TOL, (i, rel_l2(got, ref))
+        one = host(ctx.correct_ionosphere(dev(torch, x), p["fs"], p["carrier"], p["tec"], p["direction"]))
+        assert np.array_equal(one, got), i
+
+
 def test_batch_from_a_pulse_table_is_bit_identical(torch, ctx):
     """The same ragged batch described by a pulse_table array instead of dicts."""
     import paper_2508_04951_amd as rc
