@@ -3,13 +3,16 @@
 //
 // Farrow filter bank.  Output m of hypothesis h sits at t = alpha_h m = f + mu (f integer,
 // mu in [0, 1)) and takes taps f + j, j = -H + 1 .. H, with weights h(mu - j).  Each weight is
-// a polynomial in mu: h(mu - j) ~= sum_r c_r[j] T_r(2 mu - 1) (Chebyshev, r < R), so
-//     y_h[m] = sum_r T_r(2 mu - 1) Z[f][r],   Z[f][r] = sum_j x[f + j] c_r[j].
+// a polynomial in s = 2 mu - 1: h(mu - j) ~= sum_r d_r[j] s^r (r < R), so
+//     y_h[m] = sum_r s^r Z[f][r],   Z[f][r] = sum_j x[f + j] d_r[j].
 // Z depends on the input position only: it is computed once per pulse (k_farrow_z, R FIR
-// filters of 2H taps) and every hypothesis then costs one Clenshaw sum of R terms per output
-// (k_farrow_bank).  The coefficients interpolate h at the R Chebyshev nodes of [0, 1] in
-// float64 (k_farrow_coef); at R = 8 the bank is within ~4e-7 rel-L2 of the direct sum at
-// H = 64 and 128.  An output whose position is an exact integer takes the input sample.
+// filters of 2H taps) and every hypothesis then costs one Horner sum of R terms per output
+// (k_farrow_bank).  The polynomials interpolate h at the R Chebyshev nodes of [0, 1] in
+// float64 (k_farrow_coef), in the Chebyshev basis and then converted to powers of s: the
+// Chebyshev coefficients of these smooth functions decay fast, so the power basis loses
+// little, and Horner costs half the vector work of a Clenshaw sum.  At R = 8 the bank is within
+// ~4e-7 rel-L2 of the direct sum at H = 64 and 128.  An output whose position is an exact
+// integer takes the input sample.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -33,28 +36,44 @@ __device__ __forceinline__ double kaiser_series(const KaiserPoly &kp, double x)
     return acc;
 }
 
-// coef[(j + H - 1) * R + r] = c_r[j]: Chebyshev interpolation of mu -> h(mu - j) on [0, 1].
+// coef[(j + H - 1) * R + r] = d_r[j]: the polynomial in s = 2 mu - 1 that interpolates
+// mu -> h(mu - j) at the R Chebyshev nodes of [0, 1].  One thread per tap, all in float64: the
+// Chebyshev coefficients c_r, then d = sum_r c_r T_r(s) expanded in powers of s.
 __global__ void __launch_bounds__(256) k_farrow_coef(KaiserPoly kp, int H, int taper, float *__restrict__ coef)
 {
-    const int id = blockIdx.x * 256 + threadIdx.x;
-    if (id >= 2 * H * kR)
+    const int tap = blockIdx.x * 256 + threadIdx.x;
+    if (tap >= 2 * H)
         return;
-    const int tap = id / kR, r = id - tap * kR;
     const int j = tap - H + 1;
-    double acc = 0.0;
+    double w[kR];
     for (int i = 0; i < kR; ++i) {
         const double th = (i + 0.5) / kR;            // node angle / pi
         const double mu = 0.5 * (cospi(th) + 1.0);   // in (0, 1): |mu - j| < H for every tap
         const double u = mu - (double)j;
-        double w = sinpi(u) / (kPi * u);
+        double v = sinpi(u) / (kPi * u);
         if (taper)
-            w *= kaiser_series(kp, u / (double)H);
-        acc = fma(w, cospi(r * th), acc);
+            v *= kaiser_series(kp, u / (double)H);
+        w[i] = v;
     }
-    acc *= 2.0 / kR;
-    if (r == 0)
-        acc *= 0.5;
-    gmem(coef)[id] = (float)acc;
+    // power-basis coefficients of T_r (rows r), by T_{r+1} = 2 s T_r - T_{r-1}
+    double T[kR][kR] = {};
+    T[0][0] = 1.0;
+    if (kR > 1)
+        T[1][1] = 1.0;
+    for (int r = 1; r + 1 < kR; ++r)
+        for (int k = 0; k < kR; ++k)
+            T[r + 1][k] = (k > 0 ? 2.0 * T[r][k - 1] : 0.0) - T[r - 1][k];
+    double d[kR] = {};
+    for (int r = 0; r < kR; ++r) {
+        double c = 0.0;
+        for (int i = 0; i < kR; ++i)
+            c = fma(w[i], cospi(r * ((i + 0.5) / kR)), c);
+        c *= (r == 0 ? 1.0 : 2.0) / kR;
+        for (int k = 0; k < kR; ++k)
+            d[k] = fma(c, T[r][k], d[k]);
+    }
+    for (int k = 0; k < kR; ++k)
+        gmem(coef)[tap * kR + k] = (float)d[k];
 }
 
 // Z[f][r] for f in [0, F): one workgroup per 256 positions; the input span and the
@@ -111,8 +130,10 @@ k_farrow_bank(const float2 *__restrict__ Z, int64_t F, const float2 *__restrict_
               const double *__restrict__ alpha, const int *__restrict__ hyp, const BankGroup *__restrict__ groups,
               int64_t n_out, float2 *__restrict__ y, int max_rows)
 {
-    // LDS: the group's Z rows (R / 2 float4 each), then the input samples at the same positions
-    // (an exact sample instant reads LDS, so no load ever sits between two output stores)
+    // LDS: the group's Z rows as R / 2 planes of float4 (plane q holds Z_{2q}, Z_{2q+1} of every
+    // row, so the lanes of a wave, whose rows are consecutive, read consecutive 16-byte slots),
+    // then the input samples at the same positions (an exact sample instant reads LDS, so no load
+    // ever sits between two output stores)
     extern __shared__ __attribute__((aligned(16))) float4 zs[];
     const int tid = threadIdx.x;
     const BankGroup g = gload(groups, blockIdx.y);
@@ -140,9 +161,9 @@ k_farrow_bank(const float2 *__restrict__ Z, int64_t F, const float2 *__restrict_
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * kBankThreads + tid;
+            const int e = e0 + u * kBankThreads + tid;  // row e / (R / 2), plane e % (R / 2)
             if (e < rows * (kR / 2))
-                zs[e] = v[u];
+                zs[(e % (kR / 2)) * max_rows + e / (kR / 2)] = v[u];
         }
     }
     float2 *xs = reinterpret_cast<float2 *>(zs + max_rows * (kR / 2));
@@ -163,7 +184,6 @@ k_farrow_bank(const float2 *__restrict__ Z, int64_t F, const float2 *__restrict_
         }
     }
     __syncthreads();
-    const auto yg = gmem(y);
     constexpr int Q = kBankM / kBankThreads;
     double md[Q];  // this thread's output indices, as doubles (exact below 2^53)
 #pragma unroll
@@ -173,7 +193,7 @@ k_farrow_bank(const float2 *__restrict__ Z, int64_t F, const float2 *__restrict_
     const double fmind = (double)fmin;
     for (int i = 0; i < g.count; ++i) {
         const double a = gload(alpha, g.first + i);
-        const auto yh = yg + (int64_t)gload(hyp, g.first + i) * n_out + m0 + tid;
+        float2 *yh = y + (int64_t)gload(hyp, g.first + i) * n_out + m0 + tid;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if (!full && m0 + tid + kBankThreads * q >= n_out)
@@ -184,31 +204,27 @@ k_farrow_bank(const float2 *__restrict__ Z, int64_t F, const float2 *__restrict_
             if (t == fd) {  // exact sample instant: the input sample itself
                 out = xs[(int)(fd - fmind)];
             } else {
-                // Clenshaw: b_r = Z_r + 2 s b_{r+1} - b_{r+2};  y = Z_0 + s b_1 - b_2,  s = 2 mu - 1
-                const float s = (float)(2.0 * (t - fd) - 1.0);
-                const float4 *row = zs + (int)(fd - fmind) * (kR / 2);
+                // Horner in s = 2 mu - 1
+                const float s = fmaf(2.f, (float)(t - fd), -1.f);
+                const float4 *row = zs + (int)(fd - fmind);
                 float zr[kR], zi[kR];
 #pragma unroll
                 for (int q2 = 0; q2 < kR / 2; ++q2) {
-                    const float4 z = row[q2];  // (Z_{2 q2}, Z_{2 q2 + 1})
+                    const float4 z = row[q2 * max_rows];  // (Z_{2 q2}, Z_{2 q2 + 1})
                     zr[2 * q2] = z.x;
                     zi[2 * q2] = z.y;
                     zr[2 * q2 + 1] = z.z;
                     zi[2 * q2 + 1] = z.w;
                 }
-                const float s2 = 2.f * s;
-                float b1r = 0.f, b1i = 0.f, b2r = 0.f, b2i = 0.f;
+                float yr = zr[kR - 1], yi = zi[kR - 1];
 #pragma unroll
-                for (int r = kR - 1; r >= 1; --r) {
-                    const float br = fmaf(s2, b1r, zr[r] - b2r), bi = fmaf(s2, b1i, zi[r] - b2i);
-                    b2r = b1r;
-                    b2i = b1i;
-                    b1r = br;
-                    b1i = bi;
+                for (int r = kR - 2; r >= 0; --r) {
+                    yr = fmaf(yr, s, zr[r]);
+                    yi = fmaf(yi, s, zi[r]);
                 }
-                out = make_float2(fmaf(s, b1r, zr[0] - b2r), fmaf(s, b1i, zi[0] - b2i));
+                out = make_float2(yr, yi);
             }
-            yh[kBankThreads * q] = out;
+            store_nt(yh + kBankThreads * q, out);  // written once, read by no later kernel here
         }
     }
 }
@@ -238,7 +254,7 @@ hipError_t build_farrow_coef(const rc_sinc &k, void **dev, std::vector<void *> &
         return e;
     allocs.push_back(*dev);
     const KaiserPoly kp = make_kaiser_poly(k.window == RC_WIN_KAISER ? k.kaiser_beta : 0.0);
-    hipLaunchKernelGGL(k_farrow_coef, dim3((2 * H * kR + 255) / 256), dim3(256), 0, 0, kp, H,
+    hipLaunchKernelGGL(k_farrow_coef, dim3((2 * H + 255) / 256), dim3(256), 0, 0, kp, H,
                        k.window == RC_WIN_KAISER ? 1 : 0, static_cast<float *>(*dev));
     e = hipGetLastError();
     if (e != hipSuccess)
@@ -262,11 +278,12 @@ FarrowPlan plan_farrow_bank(int64_t n, int64_t n_out, int H, const double *alpha
         p.alpha[(size_t)i] = alphas[order[(size_t)i]];
         amax = std::max(amax, p.alpha[(size_t)i]);
     }
-    // groups: at most 64 hypotheses whose positions at the last output spread by <= 192 samples
+    // groups: at most 256 hypotheses whose positions at the last output spread by <= 192 samples
+    // (one staging of the Z rows then serves every hypothesis of a dense bank)
     const double last = (double)(n_out - 1);
     for (int s = 0; s < n_hyp;) {
         int e = s + 1;
-        while (e < n_hyp && e - s < 64 && (p.alpha[(size_t)e] - p.alpha[(size_t)s]) * last <= 192.0)
+        while (e < n_hyp && e - s < 256 && (p.alpha[(size_t)e] - p.alpha[(size_t)s]) * last <= 192.0)
             ++e;
         p.groups.push_back({s, e - s});
         s = e;
