@@ -480,6 +480,39 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
         b2[t] = tw[((16 * (j & 15)) << t) & (kFftTile - 1)];
         b3[t] = tw[(j << t) & (kFftTile - 1)];
     }
+    // The per-bin factors (the dispersive phase, or a convolution's table) depend on bin indices
+    // only: they are computed (or loaded) while the row's samples are still in flight.
+    float2 ph[16];
+    if (!a.fwd_only) {
+        // bin of row position l: k = kout(r) + (n / 4096) l, kout = digit-reversed row index
+        int64_t kout = 0, mult = 1;
+        {
+            int64_t rr = r;
+            int64_t digits[kFftMaxLevels];
+            for (int i = a.levels - 2; i >= 0; --i) {
+                digits[i] = rr & (a.len[i] - 1);
+                rr >>= __ffs(a.len[i]) - 1;
+            }
+            for (int i = 0; i < a.levels - 1; ++i) {
+                kout += digits[i] * mult;
+                mult *= a.len[i];
+            }
+        }
+        if (jb.mult) {  // a convolution: the table is in this row's native order
+            const auto tab = gmem(jb.mult) + (r << 12);
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                ph[q] = tab[j + 256 * q];
+        } else {
+            const PhaseK pk = phase_consts(jb, a.n);
+            const int n = (int)a.n, half = (n + 1) / 2;  // n <= 2^24
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = (int)kout + (int)mult * (j + 256 * q);
+                ph[q] = phase_at(pk, k < half ? k : k - n);
+            }
+        }
+    }
     row4096<-1>(v, lds, j, b2, b3);
     if (a.fwd_only) {
         const auto dst = gmem(jb.y) + (r << 12);
@@ -488,52 +521,9 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
             dst[j + 256 * q] = make_float2(v[q].x * a.scale, v[q].y * a.scale);
         return;  // uniform over the workgroup
     }
-    // bin of row position l: k = kout(r) + (n / 4096) l, kout = digit-reversed row index
-    int64_t kout = 0, mult = 1;
-    {
-        int64_t rr = r;
-        int64_t digits[kFftMaxLevels];
-        for (int i = a.levels - 2; i >= 0; --i) {
-            digits[i] = rr & (a.len[i] - 1);
-            rr >>= __ffs(a.len[i]) - 1;
-        }
-        for (int i = 0; i < a.levels - 1; ++i) {
-            kout += digits[i] * mult;
-            mult *= a.len[i];
-        }
-    }
-    // The spectrum is parked in this thread's own LDS slots while the float64 phase is
-    // applied one bin at a time, so the samples are not live across the phase arithmetic.
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-        lds[rpad(j + 256 * q)] = v[q];
-    if (jb.mult) {  // a convolution: the table is in this row's native order
-        const auto tab = gmem(jb.mult) + (r << 12);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = rpad(j + 256 * q);
-            lds[i] = cmul(lds[i], tab[j + 256 * q]);
-        }
-    } else {
-        // the 16 phases as independent chains (the samples wait in LDS meanwhile)
-        float2 ph[16];
-        const PhaseK pk = phase_consts(jb, a.n);
-        const int n = (int)a.n, half = (n + 1) / 2;  // n <= 2^24
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int k = (int)kout + (int)mult * (j + 256 * q);
-            ph[q] = phase_at(pk, k < half ? k : k - n);
-        }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = rpad(j + 256 * q);
-            lds[i] = cmul(lds[i], ph[q]);
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-        v[q] = lds[rpad(j + 256 * q)];
-    __syncthreads();
+        v[q] = cmul(v[q], ph[q]);
     row4096<+1>(v, lds, j, b2, b3);
 #pragma unroll
     for (int q = 0; q < 16; ++q)
