@@ -111,3 +111,9 @@ def test_pulse_table_rejects_other_layouts():
         rc.pulse_array(t[::2])  # not contiguous
     with pytest.raises(ValueError):
         rc.pulse_array(np.zeros(4, dtype=np.float64))
+
+
+def test_empty_pulse_table():
+    t = rc.pulse_table([], [], [], [], [])
+    assert t.dtype == rc.PULSE_DTYPE and t.shape == (0,)
+    assert len(rc.pulse_array(t)) == 0

@@ -457,3 +457,26 @@ def test_invalid_arguments_are_rejected(torch, ctx):
         ctx.correct_pulse_batch(x, y, [dict(ok, flags=2, n_out=16)])  # length change without Doppler
     ctx.correct_pulse_batch(x, y, [ok])
     ctx.sync()
+
+
+def test_empty_batches_and_zero_lengths(torch, ctx):
+    """A batch of no pulses does nothing; a pulse or call of length 0 is an argument error."""
+    import paper_2508_04951_amd as rc
+
+    x = torch.ones(64, dtype=torch.complex64, device="cuda")
+    y = torch.full((64,), complex("nan"), dtype=torch.complex64, device="cuda")
+    ctx.correct_pulse_batch(x, y, [])
+    ctx.correct_pulse_batch(x, y, rc.pulse_table([], [], [], [], []))
+    assert torch.isnan(y).all().item()
+    ok = dict(off_in=0, n_in=32, off_out=0, n_out=32, fs=10e6, alpha=1.0, tec=1e17, carrier=450e6)
+    for bad in (dict(ok, n_in=0), dict(ok, n_out=0), dict(ok, n_in=0, n_out=0, flags=rc.DO_IONO)):
+        with pytest.raises(ValueError):
+            ctx.correct_pulse_batch(x, y, [bad])
+    with pytest.raises(ValueError):
+        ctx.correct_doppler(x[:0], 1.0)
+    with pytest.raises(ValueError):
+        ctx.correct_doppler(x, 1.0, n_out=0)
+    with pytest.raises(ValueError):
+        ctx.correct_ionosphere(x[:0], 10e6, 450e6, 1e17)
+    ctx.sync()
+    assert torch.isnan(y).all().item()
