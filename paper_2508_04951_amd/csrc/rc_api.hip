@@ -167,6 +167,13 @@ rc_status stage_descriptors(rc_context ctx, const void *host, size_t bytes, size
     return RC_OK;
 }
 
+// The tile-list stream of a call whose descriptors went up in the current slot: its kernels
+// start once that upload is complete.
+rc::TileStream tile_stream_of(rc_context ctx)
+{
+    return rc::TileStream{ctx->tile_stream, ctx->desc[ctx->desc_next].uploaded, ctx->tiles_done};
+}
+
 // The work that reads the slot filled by the last stage_descriptors() is now enqueued on `s`.
 rc_status mark_descriptors_used(rc_context ctx, hipStream_t s)
 {
@@ -295,7 +302,15 @@ rc_status rc_create(int hip_device, rc_context *out)
     }
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&ctx->tile_stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&ctx->tiles_done, hipEventDisableTiming);
     if (e != hipSuccess) {
+        if (ctx->tiles_done)
+            (void)hipEventDestroy(ctx->tiles_done);
+        if (ctx->tile_stream)
+            (void)hipStreamDestroy(ctx->tile_stream);
         if (ctx->copy_stream)
             (void)hipStreamDestroy(ctx->copy_stream);
         for (auto &slot : ctx->desc) {
@@ -339,6 +354,10 @@ rc_status rc_destroy(rc_context ctx)
         }
         if (ctx->copy_stream)
             (void)hipStreamDestroy(ctx->copy_stream);
+        if (ctx->tile_stream)
+            (void)hipStreamDestroy(ctx->tile_stream);
+        if (ctx->tiles_done)
+            (void)hipEventDestroy(ctx->tiles_done);
         ctx->prof.release();
     }
     delete ctx;
@@ -405,8 +424,9 @@ rc_status correct_doppler(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 
         if (ts != RC_OK)
             return ts;
         char *devc = static_cast<char *>(const_cast<void *>(dev));
+        const rc::TileStream tls = tile_stream_of(ctx);
         e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc), nullptr, 1, n_out, ntiles, devc + 256,
-                                 k->half_width, table, s, prof_of(ctx));
+                                 k->half_width, table, s, prof_of(ctx), &tls);
         ts = mark_descriptors_used(ctx, s);
         if (e == hipSuccess && ts != RC_OK)
             return ts;
@@ -724,9 +744,11 @@ rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, 
             return device_fail(ctx, e, "copy");
     }
     const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
-    if (!mfma.empty())
+    if (!mfma.empty()) {
+        const rc::TileStream tls = tile_stream_of(ctx);
         e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc + off_mfma), nullptr, (int)mfma.size(),
-                                 mfma_max, mfma_tiles, tile_work, k->half_width, mfma_table, s, prof_of(ctx));
+                                 mfma_max, mfma_tiles, tile_work, k->half_width, mfma_table, s, prof_of(ctx), &tls);
+    }
     if (e == hipSuccess && !fast.empty())
         e = rc::launch_sinc_fast(reinterpret_cast<const SincJob *>(devc + off_fast), nullptr, (int)fast.size(),
                                  fast_max, k->half_width, kp, s, prof_of(ctx));

@@ -134,11 +134,20 @@ hipError_t build_sinc_mfma_table(int half_width, double beta, void **dev, std::v
 // sorted by phase; the list needs `sinc_mfma_work_bytes(ntiles)` of device workspace.
 bool sinc_mfma_uses_list(int half_width, int64_t ntiles);
 size_t sinc_mfma_work_bytes(int64_t ntiles);
+// Where the tile-list kernels may run: on `stream` once `after` (the descriptor upload) has
+// completed, signalling `done`, which the compute stream waits for before the resampling kernel.
+// They read only the call's descriptors and write only its workspace, so on a side stream they
+// overlap whatever earlier work the compute stream still has queued.
+struct TileStream {
+    hipStream_t stream;
+    hipEvent_t after;  // may be null
+    hipEvent_t done;
+};
 // jobs_dev (device array, tile0 set) or job_inline (one job, tile0 = 0); `work` is the workspace
-// when sinc_mfma_uses_list(), else unused.
+// when sinc_mfma_uses_list(), else unused.  With ts null the tile list is built on s.
 hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, int njobs,
                             int64_t max_out, int64_t ntiles, void *work, int half_width,
-                            const void *table, hipStream_t s, Profiler *prof);
+                            const void *table, hipStream_t s, Profiler *prof, const TileStream *ts = nullptr);
 KaiserPoly make_kaiser_poly(double beta);
 size_t sinc_fast_lds_bytes(int half_width);
 
@@ -269,6 +278,9 @@ struct rc_context_s {
     // descriptors go up on their own stream, so a batch's upload overlaps the previous batch's
     // kernels; the compute stream waits for it by event
     hipStream_t copy_stream = nullptr;
+    // the matrix-core tile list of a call is built on its own stream (see rc::TileStream)
+    hipStream_t tile_stream = nullptr;
+    hipEvent_t tiles_done = nullptr;
     static constexpr int kDescSlots = 4;
     DescSlot desc[kDescSlots];
     int desc_next = 0;

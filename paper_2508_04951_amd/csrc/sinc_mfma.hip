@@ -681,7 +681,7 @@ size_t work_phase_off(int64_t n) { return work_counts_off(n) + (size_t)sort_chun
 
 template <int H>
 hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int64_t max_out, int64_t ntiles,
-                    void *work, const unsigned char *table, hipStream_t s, Profiler *prof)
+                    void *work, const unsigned char *table, hipStream_t s, Profiler *prof, const TileStream *ts)
 {
     MfDevice *d = nullptr;
     hipError_t e = mf_device<H>(&d);
@@ -706,22 +706,35 @@ hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int6
     uint2 *list = reinterpret_cast<uint2 *>(w + work_list_off(ntiles));
     unsigned char *phase = w + work_phase_off(ntiles);
     const int64_t tblk = (max_out + (int64_t)kMfOut * 256 - 1) / ((int64_t)kMfOut * 256);
+    hipStream_t ls = s;
+    if (ts) {
+        ls = ts->stream;
+        if (ts->after)
+            e = hipStreamWaitEvent(ls, ts->after, 0);
+        if (e != hipSuccess)
+            return e;
+    }
     if (prof)
-        prof->begin(kKSincTiles, s);
-    hipLaunchKernelGGL(k_mf_tile_phase, dim3((unsigned)tblk, (unsigned)njobs), dim3(256), 0, s, jobs_dev, ref, phase);
+        prof->begin(kKSincTiles, ls);
+    hipLaunchKernelGGL(k_mf_tile_phase, dim3((unsigned)tblk, (unsigned)njobs), dim3(256), 0, ls, jobs_dev, ref, phase);
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     unsigned *counts = reinterpret_cast<unsigned *>(w + work_counts_off(ntiles));
     const unsigned nch = (unsigned)sort_chunks(ntiles);
-    hipLaunchKernelGGL(k_mf_tile_count, dim3(nch), dim3(256), 0, s, phase, ntiles, counts);
+    hipLaunchKernelGGL(k_mf_tile_count, dim3(nch), dim3(256), 0, ls, phase, ntiles, counts);
     e = hipGetLastError();
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_mf_tile_scatter, dim3(nch), dim3(256), 0, s, ref, phase, ntiles, counts, list);
+        hipLaunchKernelGGL(k_mf_tile_scatter, dim3(nch), dim3(256), 0, ls, ref, phase, ntiles, counts, list);
         e = hipGetLastError();
     }
     if (prof)
-        prof->end(s);
+        prof->end(ls);
+    if (e == hipSuccess && ts) {
+        e = hipEventRecord(ts->done, ls);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(s, ts->done, 0);
+    }
     if (e != hipSuccess)
         return e;
     int64_t grid = resident;
@@ -768,7 +781,7 @@ hipError_t build_sinc_mfma_table(int half_width, double beta, void **dev, std::v
 
 hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, int njobs, int64_t max_out,
                             int64_t ntiles, void *work, int half_width, const void *table, hipStream_t s,
-                            Profiler *prof)
+                            Profiler *prof, const TileStream *ts)
 {
     if (njobs <= 0 || max_out <= 0)
         return hipSuccess;
@@ -780,8 +793,8 @@ hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, 
         return hipErrorInvalidValue;  // the list kernels read the job array
     const SincJob inl = job_inline ? *job_inline : SincJob{};
     const unsigned char *t = static_cast<const unsigned char *>(table);
-    return half_width == 64 ? launch_h<64>(jobs_dev, inl, njobs, max_out, ntiles, work, t, s, prof)
-                            : launch_h<128>(jobs_dev, inl, njobs, max_out, ntiles, work, t, s, prof);
+    return half_width == 64 ? launch_h<64>(jobs_dev, inl, njobs, max_out, ntiles, work, t, s, prof, ts)
+                            : launch_h<128>(jobs_dev, inl, njobs, max_out, ntiles, work, t, s, prof, ts);
 }
 
 }  // namespace rc
