@@ -306,7 +306,22 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided_reg(StridedArgs a)
 }
 
 // Strided level of length 32..256: lines of length L along stride `inner`; the LDS tile holds
-// C = 4096/L adjacent columns.
+// C = 4096/L adjacent columns.  Thread t owns the 16 tile elements of column c = t % C at rows
+// l0 + D k (l0 = t / C, D = 256 / C, k < 16); their twiddles exp(S 2 pi i l n' / nsub), n' the
+// column's position, are b0 (b^k), b0 = w^(l0 n'), b = w^(D n'): two sincospi-based bases and
+// products instead of one sincospi per element.
+template <int S>
+__device__ __forceinline__ void strided_twiddles(float2 *v, int l0, int D, int64_t np, int log2nsub)
+{
+    const float2 b0 = unit_root<S>((int64_t)l0 * np, log2nsub);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        v[k] = cmul(v[k], b0);
+    float2 bb[4];
+    twiddle_bases<16, S>(bb, (int64_t)D * np, log2nsub);
+    twiddle_apply<16>(v, bb);
+}
+
 template <int S>
 __global__ void __launch_bounds__(kFftThreads) k_fft_strided(StridedArgs a)
 {
@@ -320,27 +335,36 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(StridedArgs a)
     const IonoJob jb = a.jobs ? gload(a.jobs, p) : a.inl;
     const int L = 1 << a.log2L, C = 1 << a.log2C;
     const int64_t base = o * ((int64_t)L * a.inner) + cb * C;
-    const auto src = gmem(a.from_x ? jb.x : jb.y);
-    for (int e = tid; e < kFftTile; e += kFftThreads) {
-        const int c = e & (C - 1), l = e >> a.log2C;
-        float2 v = src[base + (int64_t)l * a.inner + c];
-        if (S > 0)  // inverse: conjugate twiddle before the DFT along the level
-            v = cmul(v, unit_root<+1>((int64_t)l * (cb * C + c), a.log2nsub));
-        lds[tidx(c, l, a.log2L, a.log2C, false)] = v;
-    }
+    const int c = tid & (C - 1), l0 = tid >> a.log2C, D = kFftThreads >> a.log2C;
+    const int64_t np = cb * C + c;  // n': the column's position inside the lower levels
+    const auto src = gmem(a.from_x ? jb.x : jb.y) + base + c;
+    float2 v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        v[k] = src[(int64_t)(l0 + D * k) * a.inner];
+    if (S > 0)  // inverse: conjugate twiddle before the DFT along the level
+        strided_twiddles<+1>(v, l0, D, np, a.log2nsub);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        lds[tidx(c, l0 + D * k, a.log2L, a.log2C, false)] = v[k];
     __syncthreads();
     fft_tile<S>(lds, a.log2L, a.log2C, false, a.tw4096, tid);
-    for (int e = tid; e < kFftTile; e += kFftThreads) {
-        const int c = e & (C - 1), l = e >> a.log2C;
-        float2 v = lds[tidx(c, l, a.log2L, a.log2C, false)];
-        if (S < 0) {  // forward: twiddle after the DFT, k = l, n' = column position
-            v = cmul(v, unit_root<-1>((int64_t)l * (cb * C + c), a.log2nsub));
-        } else if (a.scale != 1.0f) {
-            v.x *= a.scale;
-            v.y *= a.scale;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        v[k] = lds[tidx(c, l0 + D * k, a.log2L, a.log2C, false)];
+    if (S < 0) {  // forward: twiddle after the DFT, k = l, n' = column position
+        strided_twiddles<-1>(v, l0, D, np, a.log2nsub);
+    } else if (a.scale != 1.0f) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            v[k].x *= a.scale;
+            v[k].y *= a.scale;
         }
-        gmem(jb.y)[base + (int64_t)l * a.inner + c] = v;
     }
+    const auto dst = gmem(jb.y) + base + c;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        dst[(int64_t)(l0 + D * k) * a.inner] = v[k];
 }
 
 struct RowArgs {
