@@ -103,89 +103,6 @@ template <int R, int S> __device__ __forceinline__ void dftR(float2 *v)
     else dft16<S>(v);
 }
 
-// LDS layout of a 4096-sample tile holding C lines of length L: element (c, l) at
-// c*L + l (rows, "lc") or l*C + c (columns), with one pad slot per 16 samples.
-__device__ __forceinline__ int tidx(int c, int l, int log2L, int log2C, bool lc)
-{
-    const int a = lc ? ((c << log2L) + l) : ((l << log2C) + c);
-    return a + (a >> 4);
-}
-constexpr int kLdsSlots = kFftTile + kFftTile / 16;
-
-// One Stockham radix-R stage over every line of the tile (Ns = product of earlier radices).
-template <int R, int S>
-__device__ __forceinline__ void stage(float2 *lds, int log2L, int log2C, bool lc, int Ns,
-                                      const float2 *__restrict__ tw, int tid)
-{
-    constexpr int PER = 16 / R;
-    const int log2BL = log2L - (R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4);
-    const int BL = 1 << log2BL;  // butterflies per line
-    float2 v[PER][R];
-    int cc[PER], jj[PER];
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const int b = tid + p * kFftThreads;
-        int c, j;
-        if (lc) {
-            c = b >> log2BL;
-            j = b & (BL - 1);
-        } else {
-            c = b & ((1 << log2C) - 1);
-            j = b >> log2C;
-        }
-        cc[p] = c;
-        jj[p] = j;
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            v[p][r] = lds[tidx(c, j + r * BL, log2L, log2C, lc)];
-        if (Ns > 1) {
-            const int k = j & (Ns - 1);
-            const int step = kFftTile / (Ns * R);
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float2 w = gmem(tw)[(r * k * step) & (kFftTile - 1)];
-                if (S > 0)
-                    w.y = -w.y;
-                v[p][r] = cmul(v[p][r], w);
-            }
-        }
-        dftR<R, S>(v[p]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const int k = jj[p] & (Ns - 1);
-        const int base = (jj[p] - k) * R + k;
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            lds[tidx(cc[p], base + r * Ns, log2L, log2C, lc)] = v[p][r];
-    }
-    __syncthreads();
-}
-
-// Full length-L DFT (sign S) of every line of the tile; natural order in and out.
-template <int S>
-__device__ void fft_tile(float2 *lds, int log2L, int log2C, bool lc, const float2 *__restrict__ tw,
-                         int tid)
-{
-    int Ns = 1;
-    const int rem = log2L & 3;
-    if (rem == 1) {
-        stage<2, S>(lds, log2L, log2C, lc, Ns, tw, tid);
-        Ns = 2;
-    } else if (rem == 2) {
-        stage<4, S>(lds, log2L, log2C, lc, Ns, tw, tid);
-        Ns = 4;
-    } else if (rem == 3) {
-        stage<8, S>(lds, log2L, log2C, lc, Ns, tw, tid);
-        Ns = 8;
-    }
-    for (int s = 0; s < (log2L >> 2); ++s) {
-        stage<16, S>(lds, log2L, log2C, lc, Ns, tw, tid);
-        Ns <<= 4;
-    }
-}
-
 // exp(S 2 pi i q / M), M = 2^log2M <= 2^24: sincospi of an exact float32 argument.
 template <int S>
 __device__ __forceinline__ float2 unit_root(int64_t q, int log2M)
@@ -255,6 +172,94 @@ __device__ __forceinline__ void twiddle_powers(float2 *v, int64_t m, int log2M)
     float2 b[4];
     twiddle_bases<R, S>(b, m, log2M);
     twiddle_apply<R>(v, b);
+}
+
+// LDS layout of a 4096-sample tile holding C lines of length L: element (c, l) at
+// c*L + l (rows, "lc") or l*C + c (columns), with one pad slot per 16 samples.
+__device__ __forceinline__ int tidx(int c, int l, int log2L, int log2C, bool lc)
+{
+    const int a = lc ? ((c << log2L) + l) : ((l << log2C) + c);
+    return a + (a >> 4);
+}
+constexpr int kLdsSlots = kFftTile + kFftTile / 16;
+
+// One Stockham radix-R stage over every line of the tile (Ns = product of earlier radices).
+template <int R, int S>
+__device__ __forceinline__ void stage(float2 *lds, int log2L, int log2C, bool lc, int Ns,
+                                      const float2 *__restrict__ tw, int tid)
+{
+    constexpr int PER = 16 / R;
+    const int log2BL = log2L - (R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4);
+    const int BL = 1 << log2BL;  // butterflies per line
+    float2 v[PER][R];
+    int cc[PER], jj[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int b = tid + p * kFftThreads;
+        int c, j;
+        if (lc) {
+            c = b >> log2BL;
+            j = b & (BL - 1);
+        } else {
+            c = b & ((1 << log2C) - 1);
+            j = b >> log2C;
+        }
+        cc[p] = c;
+        jj[p] = j;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[p][r] = lds[tidx(c, j + r * BL, log2L, log2C, lc)];
+        if (Ns > 1) {
+            // twiddle W^(r k step), r < R: the log2 R bases W^(2^t k step) from the table (a
+            // gather each), the other powers as products of them
+            const int k = j & (Ns - 1);
+            const int step = kFftTile / (Ns * R);
+            constexpr int NB = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+            float2 bb[4];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+                float2 w = gmem(tw)[((k * step) << t) & (kFftTile - 1)];
+                if (S > 0)
+                    w.y = -w.y;
+                bb[t] = w;
+            }
+            twiddle_apply<R>(v[p], bb);
+        }
+        dftR<R, S>(v[p]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int k = jj[p] & (Ns - 1);
+        const int base = (jj[p] - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            lds[tidx(cc[p], base + r * Ns, log2L, log2C, lc)] = v[p][r];
+    }
+    __syncthreads();
+}
+
+// Full length-L DFT (sign S) of every line of the tile; natural order in and out.
+template <int S>
+__device__ void fft_tile(float2 *lds, int log2L, int log2C, bool lc, const float2 *__restrict__ tw,
+                         int tid)
+{
+    int Ns = 1;
+    const int rem = log2L & 3;
+    if (rem == 1) {
+        stage<2, S>(lds, log2L, log2C, lc, Ns, tw, tid);
+        Ns = 2;
+    } else if (rem == 2) {
+        stage<4, S>(lds, log2L, log2C, lc, Ns, tw, tid);
+        Ns = 4;
+    } else if (rem == 3) {
+        stage<8, S>(lds, log2L, log2C, lc, Ns, tw, tid);
+        Ns = 8;
+    }
+    for (int s = 0; s < (log2L >> 2); ++s) {
+        stage<16, S>(lds, log2L, log2C, lc, Ns, tw, tid);
+        Ns <<= 4;
+    }
 }
 
 struct StridedArgs {
