@@ -6,12 +6,14 @@
 //   forward strided passes (i = 0 .. d-2): length-L_i DFT along level i, then the twiddle
 //     exp(-2 pi i k_i n' / nsub_i) with n' the flat position inside the lower levels;
 //   one contiguous pass: forward DFT of each row, the dispersive phase of its bins (float64
-//     argument reduced modulo 2 pi, float32 sincos), inverse DFT;
+//     argument in quarter turns, float32 polynomial for the remainder), inverse DFT;
 //   inverse strided passes (i = d-2 .. 0): conjugate twiddle, inverse DFT, 1/n in the last.
 // The frequency of a bin never leaves the digit-reversed order of the levels, so no
-// reordering pass exists.  Every pass loads a 4096-sample tile into LDS with coalesced
-// accesses, runs Stockham radix-16/8/4/2 stages (twiddles from a float64-built table) and
-// writes the tile back to the same place: every pass after the first runs in place on y.
+// reordering pass exists.  Every pass works on a 4096-sample tile with coalesced accesses
+// (levels of 16 points or fewer in registers, one column per thread; others through LDS),
+// runs Stockham radix-16/8/4/2 stages and writes the tile back to the same place: every pass
+// after the first runs in place on y.  Twiddles are products of a few base roots, taken from a
+// float64-built table or from sincospi of exact float32 arguments.
 #include <cmath>
 #include <vector>
 
