@@ -82,6 +82,17 @@ def test_bank_rows_follow_the_given_order(torch, ctx):
     assert np.array_equal(yp, y[perm])
 
 
+def test_bank_duplicate_hypotheses_give_identical_rows(torch, ctx):
+    import paper_2508_04951_amd as rc
+
+    x = dev(torch, wf.polyphase_code(20000, wf.rng_for(203, 0)))
+    a = [alpha_exact(v) for v in (-3000.0, 1500.0)]
+    alphas = [a[0], a[1], a[0], a[0], a[1]]
+    y = host(ctx.correct_doppler_bank(x, alphas, rc.Sinc(64)))
+    for h, k in ((2, 0), (3, 0), (4, 1)):
+        assert np.array_equal(y[h], y[k]), h
+
+
 def test_bank_modes_agree(torch, ctx, orc):
     """The per-hypothesis mode is correct_doppler row by row, bit for bit; the filter bank agrees
     with it to the tolerance; AUTO with an alpha above 2 falls back to per hypothesis."""
