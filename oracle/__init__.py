@@ -11,7 +11,8 @@ paper (arXiv 2508.04951) equation by equation:
 * Eq (1)-(2): Doppler dilation factor and the dilated signal S(alpha t);
 * Eq (17) with App. C: windowed Whittaker-Shannon (sinc) resampling;
 * Eq (3) / App. A: ionospheric group delay tau(f) = K2 / (c f^2);
-* Eq (15) / Eq (16): FFT phase distortion / correction.
+* Eq (15) / Eq (16): FFT phase distortion / correction;
+* Sec. II-B / II-D: that correction bundled with pulse compression (matched filtering).
 
 This file only marshals numpy arrays into that library (built with gcc).
 """
@@ -81,6 +82,8 @@ def _load():
     lib.rco_iono_response.argtypes = [i64, d, d, d, i32, p]
     lib.rco_ionosphere.restype = i32
     lib.rco_ionosphere.argtypes = [p, p, i64, d, d, d, i32, i32]
+    lib.rco_compress.restype = i32
+    lib.rco_compress.argtypes = [p, p, i64, p, i64, d, d, d, i32, i32]
     lib.rco_pulse.restype = i32
     lib.rco_pulse.argtypes = [p, i64, p, i64, d, d, d, d, i32, i32, i32, i32, i32, d, i32]
     _lib = lib
@@ -191,6 +194,21 @@ def ionosphere(x, fs: float, carrier: float, tec: float, direction: str = "corre
     rc = _load().rco_ionosphere(_ptr(xin), _ptr(y), xin.size, float(fs), float(carrier),
                                 float(tec), DIRECTIONS[direction], int(bool(naive)))
     _check(rc, "ionosphere")
+    return y
+
+
+def compress(x, replica, fs: float, carrier: float, tec: float, direction: str = "correct",
+             naive: bool | None = None) -> np.ndarray:
+    """Pulse compression with the ionospheric operator in the same frequency-domain pass:
+    y = IDFT(DFT(x) * conj(DFT(r)) * H), r the replica zero-padded to len(x)."""
+    xin = _c128(x)
+    rin = _c128(replica)
+    if naive is None:
+        naive = xin.size <= 4096
+    y = np.empty_like(xin)
+    rc = _load().rco_compress(_ptr(xin), _ptr(rin), rin.size, _ptr(y), xin.size, float(fs), float(carrier),
+                              float(tec), DIRECTIONS[direction], int(bool(naive)))
+    _check(rc, "compress")
     return y
 
 

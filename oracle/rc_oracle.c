@@ -364,6 +364,49 @@ int rco_ionosphere(const double *x, double *y, int64_t n, double fs, double carr
     return rc;
 }
 
+/* Pulse compression with the ionospheric operator in the same frequency-domain pass (Sec. II-B
+ * bundles Eq (15)/(16) with pulse compression; Sec. II-D times it).  The matched filter is read
+ * as the circular cross-correlation with the replica r zero-padded to n (n_rep <= n):
+ *     y = IDFT( DFT(x) * conj(DFT(r)) * H ),  i.e.  y[m] = sum_j x_c[(j + m) mod n] conj(r[j])
+ * where x_c is the ionosphere-corrected (or distorted) x.  naive != 0 uses the O(N^2) DFT. */
+int rco_compress(const double *x, const double *r, int64_t n_rep, double *y, int64_t n, double fs,
+                 double carrier, double tec, int direction, int naive)
+{
+    if (!x || !r || !y || n <= 0 || n_rep <= 0 || n_rep > n)
+        return 1;
+    double *X = malloc(sizeof(double) * 2 * (size_t)n);
+    double *R = malloc(sizeof(double) * 2 * (size_t)n);
+    double *rp = calloc(2 * (size_t)n, sizeof(double));
+    double *H = malloc(sizeof(double) * 2 * (size_t)n);
+    if (!X || !R || !rp || !H) {
+        free(X); free(R); free(rp); free(H);
+        return 2;
+    }
+    for (int64_t j = 0; j < 2 * n_rep; ++j)
+        rp[j] = r[j];
+    int rc = naive ? rco_dft(x, X, n, -1) : rco_fft(x, X, n, -1);
+    if (!rc)
+        rc = naive ? rco_dft(rp, R, n, -1) : rco_fft(rp, R, n, -1);
+    if (!rc)
+        rc = rco_iono_response(n, fs, carrier, tec, direction, H);
+    if (!rc) {
+        for (int64_t k = 0; k < n; ++k) {
+            /* X * conj(R) */
+            const double xr = X[2 * k], xi = X[2 * k + 1], rr = R[2 * k], ri = R[2 * k + 1];
+            const double pr = xr * rr + xi * ri, pi = xi * rr - xr * ri;
+            const double hr = H[2 * k], hi = H[2 * k + 1];
+            X[2 * k] = pr * hr - pi * hi;
+            X[2 * k + 1] = pr * hi + pi * hr;
+        }
+        rc = naive ? rco_dft(X, y, n, +1) : rco_fft(X, y, n, +1);
+    }
+    if (!rc)
+        for (int64_t j = 0; j < 2 * n; ++j)
+            y[j] /= (double)n;
+    free(X); free(R); free(rp); free(H);
+    return rc;
+}
+
 /* One pulse of a batch: Doppler resampling (if do_doppler), then the ionospheric
  * operator on the resampled samples (if do_iono).  y holds n_out samples. */
 int rco_pulse(const double *x, int64_t n_in, double *y, int64_t n_out, double fs, double alpha,

@@ -146,3 +146,69 @@ def test_pulse_is_doppler_then_ionosphere(orc):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-13
     swapped = orc.doppler(orc.ionosphere(x, FS, FC, tec, naive=False), a, 64)
     assert np.linalg.norm(swapped - ref) / np.linalg.norm(ref) > 1e-3
+
+
+# --- pulse compression with the ionospheric operator in the same pass (Sec. II-B, II-D) --------
+
+def _xcorr(x, r):
+    """Circular cross-correlation by brute force: y[m] = sum_j x[(j + m) mod n] conj(r[j])."""
+    n = x.size
+    return np.array([sum(x[(j + m) % n] * np.conj(r[j]) for j in range(r.size)) for m in range(n)])
+
+
+@pytest.mark.parametrize("n,n_rep", [(1, 1), (7, 3), (16, 16), (31, 5), (64, 20)])
+def test_compress_is_circular_cross_correlation(orc, n, n_rep):
+    rng = wf.rng_for(151, n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    r = rng.standard_normal(n_rep) + 1j * rng.standard_normal(n_rep)
+    y = orc.compress(x, r, FS, FC, 0.0)
+    ref = _xcorr(x, r)
+    assert np.abs(y - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("d", [0, 1, 17, 63])
+def test_compress_with_a_unit_replica_shifts(orc, d):
+    rng = wf.rng_for(152, d)
+    n = 64
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    r = np.zeros(d + 1, complex)
+    r[d] = 1.0
+    np.testing.assert_allclose(orc.compress(x, r, FS, FC, 0.0), np.roll(x, -d), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("direction", ["correct", "distort"])
+def test_compress_applies_the_ionosphere_in_the_same_pass(orc, direction):
+    """The phase commutes with the matched filter: compressing x at TEC E equals correlating the
+    ionosphere-corrected x (the separately pinned operator) with the replica."""
+    rng = wf.rng_for(153, 0)
+    n = 256
+    x = wf.bandlimited_noise(n, rng)
+    r = wf.lfm(40, FS, 5e6)
+    tec = 60 * wf.TECU
+    y = orc.compress(x, r, FS, FC, tec, direction)
+    ref = _xcorr(orc.ionosphere(x, FS, FC, tec, direction), r)
+    assert np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_compress_autocorrelation_peak_is_the_energy(orc):
+    rng = wf.rng_for(154, 0)
+    x = wf.lfm(512, FS, 5e6) * np.exp(2j * np.pi * rng.uniform())
+    y = orc.compress(x, x, FS, FC, 0.0)
+    assert y[0].real == pytest.approx(np.vdot(x, x).real, rel=1e-12)
+    assert abs(y[0].imag) <= 1e-9 * abs(y[0])
+    assert np.abs(y[1:]).max() <= np.abs(y[0]) * (1 + 1e-12)  # Cauchy-Schwarz
+
+
+def test_compress_naive_and_fast_agree(orc):
+    rng = wf.rng_for(155, 0)
+    n = 4096
+    x = wf.bandlimited_noise(n, rng)
+    r = wf.lfm(1000, FS, 5e6)
+    a = orc.compress(x, r, FS, FC, 80 * wf.TECU, naive=True)
+    b = orc.compress(x, r, FS, FC, 80 * wf.TECU, naive=False)
+    assert np.abs(a - b).max() <= 1e-10 * np.abs(a).max()
+
+
+def test_compress_rejects_a_replica_longer_than_the_pulse(orc):
+    with pytest.raises(Exception):
+        orc.compress(np.ones(8, complex), np.ones(9, complex), FS, FC, 0.0)
