@@ -138,6 +138,26 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
                              double fs_hz, double carrier_hz, double tec_el_per_m2,
                              int32_t direction, void *stream);
 
+/* Pulse compression with the ionospheric operator in the same frequency-domain pass (Sec. II-B
+ * bundles Eq (15)/(16) with other FFT work such as pulse compression; Sec. II-D times it).
+ * Matched filtering is the circular cross-correlation with a replica r zero-padded to n:
+ *   y = IDFT_n( DFT_n(x) * conj(DFT_n(r)) * exp(s i 4 pi K2 / (c f_k)) ),
+ *   i.e. y[m] = sum_j xc[(j + m) mod n] conj(r[j]), xc the ionosphere-corrected x,
+ * with f_k, s and the scaling as in correct_ionosphere.  n must be a power of two up to 2^24
+ * (RC_ERR_UNSUPPORTED otherwise).
+ *
+ * replica_spectrum writes DFT_n(r) (r: n_rep samples, 1 <= n_rep <= n) to spec, a caller-owned
+ * device buffer of n samples, in the library's internal bin order: it is only for
+ * compress_pulse at the same n, and one spectrum serves any number of pulses.  replica and
+ * spec must not overlap.
+ * compress_pulse reads x (n samples) and spec and writes y (n samples); y may equal x (in
+ * place) but must not partially overlap it, and must not overlap spec. */
+rc_status replica_spectrum(rc_context ctx, const rc_c64 *replica, int64_t n_rep, int64_t n,
+                           rc_c64 *spec, void *stream);
+rc_status compress_pulse(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n, const rc_c64 *spec,
+                         double fs_hz, double carrier_hz, double tec_el_per_m2, int32_t direction,
+                         void *stream);
+
 /* A batch of pulses with their own alpha, TEC, carrier and lengths, in packed buffers:
  * pulse i reads x_packed[off_in .. off_in+n_in) and writes y_packed[off_out .. off_out+n_out),
  * Doppler first, then the ionosphere on the resampled samples (the order matters: the

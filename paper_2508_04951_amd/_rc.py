@@ -26,7 +26,7 @@ SYMBOLS = (
     "rc_k2_per_tec", "rc_sync", "correct_doppler", "correct_ionosphere", "correct_pulse_batch",
     "correct_doppler_bank", "rc_server_create", "rc_server_submit", "rc_server_poll", "rc_server_wait",
     "rc_server_stats", "rc_server_reset_stats", "rc_server_destroy",
-    "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine",
+    "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine", "replica_spectrum", "compress_pulse",
 )
 KERNELS = ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono",
            "k_fft_strided_inv", "k_mf_tile_list", "k_bluestein", "k_farrow_z", "k_farrow_bank")
@@ -111,6 +111,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.correct_doppler_bank.restype = c_i32
         lib.correct_ionosphere.argtypes = [p, p, p, c_i64, c_d, c_d, c_d, c_i32, p]
         lib.correct_ionosphere.restype = c_i32
+        lib.replica_spectrum.argtypes = [p, p, c_i64, c_i64, p, p]
+        lib.replica_spectrum.restype = c_i32
+        lib.compress_pulse.argtypes = [p, p, p, c_i64, p, c_d, c_d, c_d, c_i32, p]
+        lib.compress_pulse.restype = c_i32
         lib.correct_pulse_batch.argtypes = [p, p, c_i64, p, c_i64, ctypes.POINTER(RcPulse), c_i32,
                                             ctypes.POINTER(RcSinc), p]
         lib.correct_pulse_batch.restype = c_i32
@@ -278,6 +282,45 @@ class Context:
                                           self._stream(stream))
         if st != RC_OK:
             self._raise(st, "correct_ionosphere")
+        return out
+
+    def replica_spectrum(self, replica, n: int, out=None, stream=None):
+        """DFT_n of the replica zero-padded to n (internal bin order), for compress_pulse."""
+        torch = _torch()
+        _check_samples(replica, "replica")
+        n = int(n)
+        if out is None:
+            out = torch.empty(n, dtype=torch.complex64, device=replica.device)
+        _check_samples(out, "out")
+        if out.numel() < n:
+            raise ValueError("out is shorter than n")
+        st = self._lib.replica_spectrum(self._h, replica.data_ptr(), replica.numel(), n, out.data_ptr(),
+                                        self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "replica_spectrum")
+        return out
+
+    def compress_pulse(self, x, spectrum, fs: float, carrier: float, tec: float, direction: str = "correct",
+                       out=None, stream=None):
+        """Pulse compression with the ionospheric correction in the same pass:
+        y = IDFT(DFT(x) conj(R) exp(-/+ i 4 pi K2 / (c f_k))), R from replica_spectrum.  out may be x."""
+        torch = _torch()
+        _check_samples(x, "x")
+        _check_samples(spectrum, "spectrum")
+        if spectrum.numel() < x.numel():
+            raise ValueError("the spectrum is shorter than x")
+        if out is None:
+            out = torch.empty_like(x)
+        _check_samples(out, "out")
+        if out.numel() != x.numel():
+            raise ValueError("out must have as many samples as x")
+        if direction not in DIRECTIONS:
+            raise ValueError(f"direction must be one of {list(DIRECTIONS)}")
+        st = self._lib.compress_pulse(self._h, x.data_ptr(), out.data_ptr(), x.numel(), spectrum.data_ptr(),
+                                      float(fs), float(carrier), float(tec), DIRECTIONS[direction],
+                                      self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "compress_pulse")
         return out
 
     def correct_pulse_batch(self, x_packed, y_packed, pulses, sinc: Sinc | None = None, stream=None):

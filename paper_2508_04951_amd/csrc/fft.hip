@@ -443,6 +443,23 @@ __device__ __forceinline__ float2 iono_phase(const IonoJob &jb, int64_t k, int64
     return phase_at(phase_consts(jb, n), kk);
 }
 
+// The factor of bin k (table entry t of the job's native order): the table value (conjugated
+// if asked) times the dispersive phase, either of them 1 when absent.
+__device__ __forceinline__ float2 bin_factor(const IonoJob &jb, int64_t t, int64_t k, int64_t n)
+{
+    float2 f = make_float2(1.f, 0.f);
+    if (jb.mult) {
+        f = gload(jb.mult, t);
+        if (jb.conj_mult)
+            f.y = -f.y;
+    }
+    if (jb.phase_num != 0.0) {
+        const float2 w = iono_phase(jb, k, n);
+        f = jb.mult ? cmul(f, w) : w;
+    }
+    return f;
+}
+
 // One radix-16 Stockham stage of a 4096-point row held as 16 samples per thread
 // (thread j owns positions j + 256 q).  Ns = 16^stage; the output leaves through LDS,
 // except for the last stage, whose outputs j + 256 q are already in place.
@@ -529,21 +546,27 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
                 mult *= a.len[i];
             }
         }
-        if (jb.mult) {  // a convolution: the table is in this row's native order
+        if (jb.mult) {  // a convolution or correlation: the table is in this row's native order
             const auto tab = gmem(jb.mult) + (r << 12);
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
+            for (int q = 0; q < 16; ++q) {
                 ph[q] = tab[j + 256 * q];
-        } else {
+                if (jb.conj_mult)
+                    ph[q].y = -ph[q].y;
+            }
+        }
+        if (jb.phase_num != 0.0) {
             const PhaseK pk = phase_consts(jb, a.n);
             const int n = (int)a.n, half = (n + 1) / 2;  // n <= 2^24
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int k = (int)kout + (int)mult * (j + 256 * q);
-                ph[q] = phase_at(pk, k < half ? k : k - n);
+                const float2 w = phase_at(pk, k < half ? k : k - n);
+                ph[q] = jb.mult ? cmul(ph[q], w) : w;
             }
         }
     }
+    const bool scaled = jb.mult || jb.phase_num != 0.0;  // else every factor is 1 (uniform)
     row4096<-1>(v, lds, j, b2, b3);
     if (a.fwd_only) {
         const auto dst = gmem(jb.y) + (r << 12);
@@ -552,9 +575,11 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
             dst[j + 256 * q] = make_float2(v[q].x * a.scale, v[q].y * a.scale);
         return;  // uniform over the workgroup
     }
+    if (scaled) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-        v[q] = cmul(v[q], ph[q]);
+        for (int q = 0; q < 16; ++q)
+            v[q] = cmul(v[q], ph[q]);
+    }
     row4096<+1>(v, lds, j, b2, b3);
 #pragma unroll
     for (int q = 0; q < 16; ++q)
@@ -593,7 +618,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_iono(RowArgs a)
             v.y *= a.scale;
             gmem(jb.y)[l] = v;
         } else {
-            lds[idx] = cmul(lds[idx], jb.mult ? gload(jb.mult, l) : iono_phase(jb, l, a.n));
+            lds[idx] = cmul(lds[idx], bin_factor(jb, l, l, a.n));
         }
     }
     if (a.fwd_only)
@@ -857,6 +882,27 @@ __global__ void __launch_bounds__(256) k_bluestein_post(const BluesteinJob *jobs
 }
 
 }  // namespace
+
+namespace {
+
+// spec[i] = r[i] for i < n_rep, else 0: a replica zero-padded to the transform length.
+__global__ void __launch_bounds__(256) k_pad(const float2 *__restrict__ r, int64_t n_rep, float2 *__restrict__ spec,
+                                             int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        gmem(spec)[i] = i < n_rep ? gload(r, i) : make_float2(0.f, 0.f);
+}
+
+}  // namespace
+
+hipError_t launch_pad(const float2 *r, int64_t n_rep, float2 *dst, int64_t n, hipStream_t s)
+{
+    if (n <= 0 || n_rep < 0 || n_rep > n || (n + 255) / 256 > 0x7fffffff)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, n_rep, dst, n);
+    return hipGetLastError();
+}
 
 int64_t bluestein_m(int64_t n)
 {

@@ -496,6 +496,78 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
     return RC_OK;
 }
 
+rc_status replica_spectrum(rc_context ctx, const rc_c64 *replica, int64_t n_rep, int64_t n, rc_c64 *spec,
+                           void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    if (!replica || !spec)
+        return fail(ctx, RC_ERR_INVALID_ARG, "NULL sample pointer");
+    if (n <= 0 || n_rep <= 0 || n_rep > n)
+        return fail(ctx, RC_ERR_INVALID_ARG, "need 1 <= n_rep <= n");
+    if (overlaps(replica, n_rep * 8, spec, n * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "replica and spectrum overlap");
+    if (!is_pow2(n) || n > kMaxIonoLength)
+        return fail(ctx, RC_ERR_UNSUPPORTED, "pulse compression lengths are powers of two up to 2^24");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const FftPlan *plan = nullptr;
+    rc_status st = get_plan(ctx, n, &plan);
+    if (st != RC_OK)
+        return st;
+    float2 *sp = reinterpret_cast<float2 *>(spec);
+    hipError_t e = rc::launch_pad(reinterpret_cast<const float2 *>(replica), n_rep, sp, n, s);
+    if (e == hipSuccess) {
+        const IonoJob jb{sp, sp, 0.0, 0.0, 0.0, nullptr, 0};
+        e = rc::launch_fft_forward(*plan, ctx->tw4096, nullptr, &jb, 1, s, prof_of(ctx));
+    }
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "replica_spectrum launch");
+    return RC_OK;
+}
+
+rc_status compress_pulse(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n, const rc_c64 *spec, double fs_hz,
+                         double carrier_hz, double tec_el_per_m2, int32_t direction, void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    if (!x || !y || !spec)
+        return fail(ctx, RC_ERR_INVALID_ARG, "NULL sample pointer");
+    if (n <= 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "n must be > 0");
+    if (!(std::isfinite(fs_hz) && fs_hz > 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "fs_hz must be finite and > 0");
+    if (!std::isfinite(carrier_hz))
+        return fail(ctx, RC_ERR_INVALID_ARG, "carrier_hz must be finite");
+    if (!(std::isfinite(tec_el_per_m2) && tec_el_per_m2 >= 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "tec must be finite and >= 0");
+    if (direction != RC_CORRECT && direction != RC_DISTORT)
+        return fail(ctx, RC_ERR_INVALID_ARG, "direction must be RC_CORRECT or RC_DISTORT");
+    if (x != y && overlaps(x, n * 8, y, n * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "x and y partially overlap");
+    if (overlaps(spec, n * 8, y, n * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "the spectrum overlaps y");
+    if (!is_pow2(n) || n > kMaxIonoLength)
+        return fail(ctx, RC_ERR_UNSUPPORTED, "pulse compression lengths are powers of two up to 2^24");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const FftPlan *plan = nullptr;
+    rc_status st = get_plan(ctx, n, &plan);
+    if (st != RC_OK)
+        return st;
+    const IonoJob job{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y),
+                      phase_numerator(tec_el_per_m2, direction), carrier_hz, fs_hz,
+                      reinterpret_cast<const float2 *>(spec), 1};
+    const hipError_t e = rc::launch_iono(*plan, ctx->tw4096, nullptr, &job, 1, s, prof_of(ctx));
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "compress_pulse launch");
+    return RC_OK;
+}
+
 namespace {
 
 // Workspace cap of one Bluestein launch sequence in a batch (at least one pulse runs).

@@ -204,9 +204,11 @@ struct IonoJob {
     double phase_num;
     double carrier;
     double fs;
-    // When set, the spectrum is multiplied by this table (in the transform's native bin
-    // order, see launch_fft) instead of the dispersive phase: a circular convolution.
+    // When set, the spectrum is also multiplied by this table (in the transform's native bin
+    // order, see launch_fft_forward), conjugated if conj_mult: a circular convolution or, with
+    // the conjugate, a correlation.  The dispersive phase applies on top unless phase_num is 0.
     const float2 *mult;
+    int conj_mult;
 };
 
 // Decomposition of an n-point transform into levels L_0 x L_1 x ... x L_{d-1}
@@ -231,6 +233,9 @@ hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob 
 // is natural.  Used to build `mult` tables.
 hipError_t launch_fft_forward(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
                               const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof);
+
+// dst[i] = r[i] for i < n_rep, 0 up to n (a replica zero-padded to a transform length).
+hipError_t launch_pad(const float2 *r, int64_t n_rep, float2 *dst, int64_t n, hipStream_t s);
 
 // Ionospheric operator of a length n that is not a power of two (Bluestein): the N-point DFT
 // as a chirp convolution of power-of-two length m >= 2n - 1 (bluestein_m).  Each pulse needs
