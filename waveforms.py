@@ -38,6 +38,14 @@ def lfm(n: int, fs: float, bandwidth: float) -> np.ndarray:
     return np.exp(2j * np.pi * (-0.5 * bandwidth * t + 0.5 * bandwidth / T * t * t)).astype(np.complex64)
 
 
+def lfm_rf(n: int, fs: float, f0: float, bandwidth: float) -> np.ndarray:
+    """Complex analytic up-chirp from f0 to f0 + B over the pulse, T = n/fs, sampled directly
+    at RF (carrier 0): x[k] = exp(2 pi i (f0 t + B/(2T) t^2)), t = k/fs (float64, cast once)."""
+    t = np.arange(n, dtype=np.float64) / fs
+    T = n / fs
+    return np.exp(2j * np.pi * (f0 * t + 0.5 * bandwidth / T * t * t)).astype(np.complex64)
+
+
 def lfm_phase(t: np.ndarray, fs: float, n: int, bandwidth: float) -> np.ndarray:
     """Phase of the same chirp at arbitrary times t (seconds), float64."""
     T = n / fs
@@ -108,6 +116,10 @@ SERVING = dict(name="serving_poisson_2000hz", seed=4, rate_hz=2000.0, lo_exp=12.
           fs=FS_DEFAULT, carrier=CARRIER_DEFAULT, half_width=64, beta=8.0)
 LONG_DWELL = dict(name="long_dwell_64x2^24", seed=5, pulses=64, n=1 << 24, fs=FS_DEFAULT,
           carrier=CARRIER_DEFAULT, half_width=128, beta=8.0)
+# the timing setup of the paper's ionospheric correction during pulse compression (Sec. II-D):
+# 2^19 I/Q samples at 2.048 GHz, an LFM from 413 MHz over 18 MHz lasting 100 us, 100 TECU
+COMPRESS = dict(name="pulse_compression_2^19", n=1 << 19, fs=2.048e9, f0=413e6, bandwidth=18e6,
+                pulse_s=100e-6, tec=100 * TECU, carrier=0.0, delay=50000)
 
 
 def batch_pulse(p: int, n: int | None = None) -> np.ndarray:
