@@ -23,6 +23,20 @@ namespace rc {
 
 namespace {
 
+// A value every lane of the wave holds alike (a job descriptor of a block), moved into scalar
+// registers so that it costs no vector registers while it stays live.
+template <class T> __device__ __forceinline__ T wave_uniform(const T &x)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole dwords only");
+    T y;
+    const int *src = reinterpret_cast<const int *>(&x);
+    int *dst = reinterpret_cast<int *>(&y);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i)
+        dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return y;
+}
+
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
@@ -505,15 +519,45 @@ __device__ __forceinline__ void row4096(float2 *v, float2 *lds, int j, const flo
     __syncthreads();  // LDS free for the next transform
 }
 
-// Contiguous level of 4096 points, one row per block: forward DFT, phase, inverse DFT.
-__global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
+// Row position l of row r of a 4096-point contiguous level holds bin kout + mult l, where kout is
+// the digit-reversed row index and mult = n / 4096.
+__device__ __forceinline__ void row_bin_origin(const RowArgs &a, int64_t r, int &kout, int &mult)
+{
+    int64_t ko = 0, m = 1, rr = r;
+    int64_t digits[kFftMaxLevels];
+    for (int i = a.levels - 2; i >= 0; --i) {
+        digits[i] = rr & (a.len[i] - 1);
+        rr >>= __ffs(a.len[i]) - 1;
+    }
+    for (int i = 0; i < a.levels - 1; ++i) {
+        ko += digits[i] * m;
+        m *= a.len[i];
+    }
+    kout = (int)ko;  // n <= 2^24
+    mult = (int)m;
+}
+
+// Dispersive phase of the bin at row position l (see row_bin_origin), with the signed frequency
+// index of the bins above n / 2.
+__device__ __forceinline__ float2 row_phase(const PhaseK &pk, int kout, int mult, int l, int n)
+{
+    const int k = kout + mult * l;
+    return phase_at(pk, k < (n + 1) / 2 ? k : k - n);
+}
+
+// Contiguous level of 4096 points, one row per block: forward DFT, the per-bin factor, inverse
+// DFT.  F selects the factor (see RowFactor).  The correlation variant holds the table across the
+// forward transform and evaluates the phases after it: it needs more than 128 registers, so it
+// runs at three blocks per CU instead of four.
+template <int F>
+__global__ void __launch_bounds__(kFftThreads, F == kRowTablePhase ? 3 : 4) k_fft_row4096_iono(RowArgs a)
 {
     __shared__ float2 lds[kLdsSlots];
     const int j = threadIdx.x;
     const int64_t g = blockIdx.x;
     const int p = (int)(g >> a.log2rpp);
     const int64_t r = g & ((int64_t(1) << a.log2rpp) - 1);
-    const IonoJob jb = a.jobs ? gload(a.jobs, p) : a.inl;
+    const IonoJob jb = wave_uniform(a.jobs ? gload(a.jobs, p) : a.inl);
     const auto src = gmem(a.from_x ? jb.x : jb.y) + (r << 12);
     float2 v[16];
 #pragma unroll
@@ -528,45 +572,25 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
         b2[t] = tw[((16 * (j & 15)) << t) & (kFftTile - 1)];
         b3[t] = tw[(j << t) & (kFftTile - 1)];
     }
-    // The per-bin factors (the dispersive phase, or a convolution's table) depend on bin indices
-    // only: they are computed (or loaded) while the row's samples are still in flight.
+    // The per-bin factors depend on bin indices only: the phases are computed (or the table read)
+    // while the row's samples are still in flight.  With both (F == kRowTablePhase) the table is
+    // read here and the phase evaluated after the forward transform.
     float2 ph[16];
     if (!a.fwd_only) {
-        // bin of row position l: k = kout(r) + (n / 4096) l, kout = digit-reversed row index
-        int64_t kout = 0, mult = 1;
-        {
-            int64_t rr = r;
-            int64_t digits[kFftMaxLevels];
-            for (int i = a.levels - 2; i >= 0; --i) {
-                digits[i] = rr & (a.len[i] - 1);
-                rr >>= __ffs(a.len[i]) - 1;
-            }
-            for (int i = 0; i < a.levels - 1; ++i) {
-                kout += digits[i] * mult;
-                mult *= a.len[i];
-            }
-        }
-        if (jb.mult) {  // a convolution or correlation: the table is in this row's native order
+        if (F == kRowTablePhase || jb.mult) {  // the table is in this row's native order
             const auto tab = gmem(jb.mult) + (r << 12);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
+            for (int q = 0; q < 16; ++q)
                 ph[q] = tab[j + 256 * q];
-                if (jb.conj_mult)
-                    ph[q].y = -ph[q].y;
-            }
-        }
-        if (jb.phase_num != 0.0) {
+        } else {
+            int kout, mult;
+            row_bin_origin(a, r, kout, mult);
             const PhaseK pk = phase_consts(jb, a.n);
-            const int n = (int)a.n, half = (n + 1) / 2;  // n <= 2^24
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int k = (int)kout + (int)mult * (j + 256 * q);
-                const float2 w = phase_at(pk, k < half ? k : k - n);
-                ph[q] = jb.mult ? cmul(ph[q], w) : w;
-            }
+            for (int q = 0; q < 16; ++q)
+                ph[q] = row_phase(pk, kout, mult, j + 256 * q, (int)a.n);
         }
     }
-    const bool scaled = jb.mult || jb.phase_num != 0.0;  // else every factor is 1 (uniform)
     row4096<-1>(v, lds, j, b2, b3);
     if (a.fwd_only) {
         const auto dst = gmem(jb.y) + (r << 12);
@@ -575,7 +599,25 @@ __global__ void __launch_bounds__(kFftThreads, 4) k_fft_row4096_iono(RowArgs a)
             dst[j + 256 * q] = make_float2(v[q].x * a.scale, v[q].y * a.scale);
         return;  // uniform over the workgroup
     }
-    if (scaled) {
+    if constexpr (F == kRowTablePhase) {
+        // a correlation: the table (conjugated if asked) times the phase, four bins at a time,
+        // fenced from the scheduler so that the float64 evaluations do not pile up and spill
+        int kout, mult;
+        row_bin_origin(a, r, kout, mult);
+        const PhaseK pk = phase_consts(jb, a.n);
+#pragma unroll
+        for (int q0 = 0; q0 < 16; q0 += 4) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = q0; q < q0 + 4; ++q) {
+                float2 t = ph[q];
+                if (jb.conj_mult)
+                    t.y = -t.y;
+                v[q] = cmul(v[q], cmul(t, row_phase(pk, kout, mult, j + 256 * q, (int)a.n)));
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    } else {
 #pragma unroll
         for (int q = 0; q < 16; ++q)
             v[q] = cmul(v[q], ph[q]);
@@ -708,7 +750,8 @@ hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs)
 namespace {
 
 hipError_t launch_fft_impl(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
-                           const IonoJob *job_inline, int njobs, bool fwd_only, hipStream_t s, Profiler *prof)
+                           const IonoJob *job_inline, int njobs, bool fwd_only, int factor, hipStream_t s,
+                           Profiler *prof)
 {
     if (njobs <= 0)
         return hipSuccess;
@@ -795,7 +838,12 @@ hipError_t launch_fft_impl(const FftPlan &plan, const float2 *tw4096, const Iono
             const int64_t blocks = (int64_t)njobs << a.log2rpp;
             if (blocks > 0x7fffffff)
                 return hipErrorInvalidValue;
-            hipLaunchKernelGGL(k_fft_row4096_iono, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);
+            if (factor == kRowTablePhase)
+                hipLaunchKernelGGL(k_fft_row4096_iono<kRowTablePhase>, dim3((unsigned)blocks), dim3(kFftThreads), 0,
+                                   s, a);
+            else
+                hipLaunchKernelGGL(k_fft_row4096_iono<kRowPhaseOrTable>, dim3((unsigned)blocks), dim3(kFftThreads), 0,
+                                   s, a);
         } else {
             const int64_t blocks = ((int64_t)njobs + (1 << a.log2C) - 1) >> a.log2C;
             hipLaunchKernelGGL(k_fft_rows_iono, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);
@@ -913,15 +961,15 @@ int64_t bluestein_m(int64_t n)
 }
 
 hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
-                       const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof)
+                       const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof, int factor)
 {
-    return launch_fft_impl(plan, tw4096, jobs_dev, job_inline, njobs, false, s, prof);
+    return launch_fft_impl(plan, tw4096, jobs_dev, job_inline, njobs, false, factor, s, prof);
 }
 
 hipError_t launch_fft_forward(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
                               const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof)
 {
-    return launch_fft_impl(plan, tw4096, jobs_dev, job_inline, njobs, true, s, prof);
+    return launch_fft_impl(plan, tw4096, jobs_dev, job_inline, njobs, true, kRowPhaseOrTable, s, prof);
 }
 
 size_t bluestein_work_bytes(int64_t n) { return (size_t)bluestein_m(n) * 2 * sizeof(float2); }

@@ -562,7 +562,7 @@ rc_status compress_pulse(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n, 
     const IonoJob job{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y),
                       phase_numerator(tec_el_per_m2, direction), carrier_hz, fs_hz,
                       reinterpret_cast<const float2 *>(spec), 1};
-    const hipError_t e = rc::launch_iono(*plan, ctx->tw4096, nullptr, &job, 1, s, prof_of(ctx));
+    const hipError_t e = rc::launch_iono(*plan, ctx->tw4096, nullptr, &job, 1, s, prof_of(ctx), rc::kRowTablePhase);
     if (e != hipSuccess)
         return device_fail(ctx, e, "compress_pulse launch");
     return RC_OK;

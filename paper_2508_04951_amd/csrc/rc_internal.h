@@ -223,10 +223,16 @@ struct FftPlan {
 hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs);
 hipError_t make_base_twiddles(float2 **dev);  // exp(-2 pi i q / 4096), q < 4096
 
+// What the contiguous FFT pass multiplies each bin by: the dispersive phase (the ionospheric
+// operator) or, for a job with a `mult` table, the table alone (a convolution); or the table,
+// conjugated if the job says so, times the phase (a correlation with the correction).  Every job
+// of one launch takes the same kind.
+enum RowFactor { kRowPhaseOrTable = 0, kRowTablePhase = 1 };
 // Full ionospheric operator for njobs pulses of the same length plan.n: forward FFT, the
-// per-bin factor (dispersive phase, or the job's `mult` table), inverse FFT with 1/n.
+// per-bin factor, inverse FFT with 1/n.
 hipError_t launch_iono(const FftPlan &plan, const float2 *tw4096, const IonoJob *jobs_dev,
-                       const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof);
+                       const IonoJob *job_inline, int njobs, hipStream_t s, Profiler *prof,
+                       int factor = kRowPhaseOrTable);
 // Forward FFT only, the spectrum left in the native bin order of the multi-level transform:
 // bin k sits at (row r) * L + l where L is the last level and row r holds bins
 // kout(r) + (n / L) l (kout = the digit-reversed row index).  For a one-level plan the order
