@@ -363,6 +363,66 @@ def run_compress(args, torch, rc):
     print(json.dumps(out), flush=True)
 
 
+def run_paper_sinc(args, torch, rc):
+    """The paper's windowed-sinc timing setup: one 2^19-sample correct_doppler call with a
+    25-sample nearest-centred untapered window (its best kernel: about 45 us on an H100)."""
+    c = wf.PAPER_SINC
+    n, fs = c["n"], c["fs"]
+    alpha = alpha_exact(c["v_r"])
+    sinc = rc.Sinc(c["half_width"], c["window"], 0.0)
+    log(f"[bench] paper_sinc: {n} samples, N_window = {2 * c['half_width'] + 1}, alpha = {alpha!r}")
+    xh = wf.lfm_rf(n, fs, c["f0"], c["bandwidth"])
+    ctx = rc.Context(0)
+    x = torch.from_numpy(xh).cuda()
+    y = torch.empty_like(x)
+
+    def call():
+        ctx.correct_doppler(x, alpha, sinc, out=y)
+
+    calls = max(1000, args.steps * 40)
+    warm = max(100, args.warmup * 4)
+    for _ in range(warm):
+        call()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for a, b in ev:
+        a.record()
+        call()
+        b.record()
+    torch.cuda.synchronize()
+    dev_us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        call()
+    torch.cuda.synchronize()
+    back_to_back_us = (time.perf_counter() - t0) / calls * 1e6
+    ms, kt, kernels = timed(torch, ctx, call, 200, 20)
+    cpu, err = None, None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        t1 = time.perf_counter()
+        ref = oracle.doppler(xh, alpha, half_width=c["half_width"], window=c["window"])
+        dt = time.perf_counter() - t1
+        err = float(np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref))
+        cpu = {"value": round(n / dt, 1), "unit": "samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"one {n}-sample resample, {dt:.2f} s"}
+    p50 = float(np.percentile(dev_us, 50))
+    out = {"metric": "windowed-sinc resample (N_window = 25, paper mode), device time per 2^19-sample call",
+           "value": round(p50, 2), "unit": "us", "n_gpus": 1, "steps": calls, "warmup": warm,
+           "ms_per_step": round(p50 * 1e-3, 5), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": round(p50 / 45.0, 4), "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{n} samples at 2.048 GHz: LFM 413-431 MHz over the record, v_r = 1 km/s, "
+                                  "25-sample window centred on the nearest input, untapered", "samples": n},
+           "device_us": {"p50": round(p50, 2), "p99": round(float(np.percentile(dev_us, 99)), 2),
+                         "mean": round(float(dev_us.mean()), 2)},
+           "back_to_back_us_per_call": round(back_to_back_us, 2),
+           "samples_per_s_p50": round(n / (p50 * 1e-6), 1), "kernels": kernels,
+           "paper_h100_us": 45.0, "roofline": None, "cpu_baseline": cpu, "rel_err": err}
+    print(json.dumps(out), flush=True)
+
+
 def run_long(args, torch, rc):
     """64 pulses of 2^24 samples at H = 128: Doppler then the 2^24-point ionospheric FFT."""
     c = wf.LONG_DWELL
@@ -526,10 +586,13 @@ def main():
                          "HBM traffic counters)")
     ap.add_argument("--engine", choices=["auto", "valu", "direct"], default="auto",
                     help="resampling engine (auto: matrix cores where eligible)")
-    ap.add_argument("--workload", choices=["batch", "bank", "long", "serving", "single", "compress"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "bank", "long", "serving", "single", "compress", "paper_sinc"],
+                    default="batch",
                     help="batch: 1024 x 65536 pulses (the headline); bank: one 2^20-sample pulse x 256 "
                          "Doppler hypotheses; long: 64 x 2^24-sample pulses at H = 128; serving: Poisson "
-                         "arrivals at 2000 pulses/s, lengths 2^12..2^22, through the server")
+                         "arrivals at 2000 pulses/s, lengths 2^12..2^22, through the server; single: one "
+                         "4096-sample LFM, full sinc then ionosphere; compress: pulse compression with the "
+                         "correction, 2^19 samples; paper_sinc: one 2^19-sample resample, 25-sample window")
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -551,6 +614,8 @@ def main():
         return run_single(args, torch, rc)
     if args.workload == "compress":
         return run_compress(args, torch, rc)
+    if args.workload == "paper_sinc":
+        return run_paper_sinc(args, torch, rc)
     if args.workload == "serving":
         return run_serving(args, torch, rc)
     dev = torch.device("cuda:0")

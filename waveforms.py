@@ -120,6 +120,11 @@ LONG_DWELL = dict(name="long_dwell_64x2^24", seed=5, pulses=64, n=1 << 24, fs=FS
 # 2^19 I/Q samples at 2.048 GHz, an LFM from 413 MHz over 18 MHz lasting 100 us, 100 TECU
 COMPRESS = dict(name="pulse_compression_2^19", n=1 << 19, fs=2.048e9, f0=413e6, bandwidth=18e6,
                 pulse_s=100e-6, tec=100 * TECU, carrier=0.0, delay=50000)
+# The paper's sinc-resampler timing setup (Sec. III-B, Fig. 7; App. C, Fig. 9): 2^19 samples,
+# a 25-sample window centred on the nearest input, no taper.  The waveform is not specified there:
+# the Fig. 2 LFM band (413-431 MHz) over the whole record, sampled at 2.048 GHz, at v_r = 1 km/s.
+PAPER_SINC = dict(name="paper_sinc_2^19", n=1 << 19, fs=2.048e9, f0=413e6, bandwidth=18e6,
+                  half_width=12, window="paper", v_r=1000.0)
 
 
 def batch_pulse(p: int, n: int | None = None) -> np.ndarray:
