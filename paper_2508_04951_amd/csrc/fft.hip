@@ -289,15 +289,24 @@ struct StridedArgs {
     const float2 *tw4096;
     int log2nsub;           // log2(L * inner)
     bool from_x;            // first pass reads job.x
+    bool reverse;           // walk the blocks from the last (see pass_order)
     float scale;            // applied after an inverse pass (1/n in the last one)
 };
+
+// Consecutive passes walk the batch in opposite directions: a pass then starts on the samples
+// the previous one wrote last, which are still in the memory-side cache.  The block order is
+// the only difference; every block does the same work either way.
+__device__ __forceinline__ int64_t pass_order(bool reverse)
+{
+    return reverse ? (int64_t)gridDim.x - 1 - (int64_t)blockIdx.x : (int64_t)blockIdx.x;
+}
 
 // Strided level of length L <= 16 (one radix stage): each thread owns one column and keeps
 // its L samples in registers -- no LDS, no barrier.  A block covers 256 adjacent columns.
 template <int R, int S>
 __global__ void __launch_bounds__(kFftThreads) k_fft_strided_reg(StridedArgs a)
 {
-    const int64_t blk = blockIdx.x;
+    const int64_t blk = pass_order(a.reverse);
     const int p = (int)(blk >> a.log2pp);
     const int64_t rem = blk & ((int64_t(1) << a.log2pp) - 1);
     const int64_t o = rem >> a.log2cb;
@@ -348,7 +357,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(StridedArgs a)
 {
     __shared__ float2 lds[kLdsSlots];
     const int tid = threadIdx.x;
-    const int64_t blk = blockIdx.x;
+    const int64_t blk = pass_order(a.reverse);
     const int p = (int)(blk >> a.log2pp);
     const int64_t rem = blk & ((int64_t(1) << a.log2pp) - 1);
     const int64_t o = rem >> a.log2cb;
@@ -400,6 +409,7 @@ struct RowArgs {
     const float2 *tw4096;
     bool from_x;
     bool fwd_only;            // store the spectrum (native order) after the forward transform
+    bool reverse;             // walk the rows from the last (see pass_order)
     float scale;              // 1/n when this is the only pass, else 1
 };
 
@@ -554,7 +564,7 @@ __global__ void __launch_bounds__(kFftThreads, F == kRowTablePhase ? 3 : 4) k_ff
 {
     __shared__ float2 lds[kLdsSlots];
     const int j = threadIdx.x;
-    const int64_t g = blockIdx.x;
+    const int64_t g = pass_order(a.reverse);
     const int p = (int)(g >> a.log2rpp);
     const int64_t r = g & ((int64_t(1) << a.log2rpp) - 1);
     const IonoJob jb = wave_uniform(a.jobs ? gload(a.jobs, p) : a.inl);
@@ -634,7 +644,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_iono(RowArgs a)
     __shared__ float2 lds[kLdsSlots];
     const int tid = threadIdx.x;
     const int L = 1 << a.log2L, C = 1 << a.log2C;
-    const int g0 = blockIdx.x * C;  // first pulse of the tile
+    const int g0 = (int)pass_order(a.reverse) * C;  // first pulse of the tile
     for (int e = tid; e < kFftTile; e += kFftThreads) {
         const int c = e >> a.log2L, l = e & (L - 1);
         const int g = g0 + c;
@@ -768,8 +778,10 @@ hipError_t launch_fft_impl(const FftPlan &plan, const float2 *tw4096, const Iono
             above *= plan.len[i];
         }
     }
+    int pass = 0;  // consecutive passes alternate their block order
     auto strided = [&](int i, bool inverse) -> hipError_t {
         StridedArgs a{};
+        a.reverse = (pass++ & 1) != 0;
         a.jobs = jobs_dev;
         a.inl = inl;
         a.njobs = njobs;
@@ -831,6 +843,7 @@ hipError_t launch_fft_impl(const FftPlan &plan, const float2 *tw4096, const Iono
         a.tw4096 = tw4096;
         a.from_x = (d == 1);
         a.fwd_only = fwd_only;
+        a.reverse = (pass++ & 1) != 0;
         a.scale = (d == 1 && !fwd_only) ? inv_n : 1.0f;
         if (prof)
             prof->begin(kKFftRowsIono, s);
