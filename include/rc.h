@@ -143,8 +143,10 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
  * Matched filtering is the circular cross-correlation with a replica r zero-padded to n:
  *   y = IDFT_n( DFT_n(x) * conj(DFT_n(r)) * exp(s i 4 pi K2 / (c f_k)) ),
  *   i.e. y[m] = sum_j xc[(j + m) mod n] conj(r[j]), xc the ionosphere-corrected x,
- * with f_k, s and the scaling as in correct_ionosphere.  n must be a power of two up to 2^24
- * (RC_ERR_UNSUPPORTED otherwise).
+ * with f_k, s and the scaling as in correct_ionosphere, and the same lengths: powers of two up
+ * to 2^24 in the multi-level FFT's row pass, other lengths up to 2^23 by Bluestein's chirp
+ * convolution with the correlation folded into its middle step (workspace from the context);
+ * longer pulses give RC_ERR_UNSUPPORTED.
  *
  * replica_spectrum writes DFT_n(r) (r: n_rep samples, 1 <= n_rep <= n) to spec, a caller-owned
  * device buffer of n samples, in the library's internal bin order: it is only for

@@ -913,7 +913,9 @@ __global__ void __launch_bounds__(256) k_bluestein_pre(const BluesteinJob *jobs,
     gmem(jb.a + M)[m] = bv;
 }
 
-// c (first convolution, in a) -> conj(c_k H_k) for k < N, zero above.
+// c (first convolution, in a) -> conj(c_k H_k) for k < N, zero above.  The forward DFT is
+// X_k = conj(w_k) c_k and the second convolution starts from conj(Y_k) conj(w_k), Y_k = X_k H_k,
+// which is conj(c_k H_k); with a correlation (Y_k = X_k conj(R_k) H_k) it is conj(c_k H_k) R_k.
 __global__ void __launch_bounds__(256) k_bluestein_mid(const BluesteinJob *jobs, BluesteinJob inl, int64_t M)
 {
     const BluesteinJob jb = jobs ? gload(jobs, blockIdx.y) : inl;
@@ -925,8 +927,21 @@ __global__ void __launch_bounds__(256) k_bluestein_mid(const BluesteinJob *jobs,
         const IonoJob ph{nullptr, nullptr, jb.phase_num, jb.carrier, jb.fs, nullptr};
         const float2 h = cmul(gload(jb.a, k), iono_phase(ph, k, N));
         v = make_float2(h.x, -h.y);
+        if (jb.corr)
+            v = cmul(v, gload(jb.corr, k));
     }
     gmem(jb.a)[k] = v;
+}
+
+// c (the convolution, in a) -> y_k = conj(w_k) c_k for k < N: the forward DFT alone.
+__global__ void __launch_bounds__(256) k_bluestein_fwd_post(const BluesteinJob *jobs, BluesteinJob inl)
+{
+    const BluesteinJob jb = jobs ? gload(jobs, blockIdx.y) : inl;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x, N = jb.n;
+    if (k >= N)
+        return;
+    const float2 w = chirp_w(k, N), c = gload(jb.a, k);
+    gmem(jb.y)[k] = make_float2(w.x * c.x + w.y * c.y, w.x * c.y - w.y * c.x);  // conj(w) c
 }
 
 // f (second convolution, in a) -> y_n = w_n conj(f_n) / N.
@@ -1023,6 +1038,37 @@ hipError_t launch_iono_bluestein(const FftPlan &mplan, const float2 *tw4096, con
         e = launch_iono(mplan, tw4096, fc, &conv, njobs, s, prof);
     if (e == hipSuccess)
         e = small(k_bluestein_post, gn);
+    return e;
+}
+
+hipError_t launch_bluestein_forward(const FftPlan &mplan, const float2 *tw4096, const BluesteinJob &inl,
+                                    hipStream_t s, Profiler *prof)
+{
+    const int64_t M = mplan.n;
+    if (inl.n < 2 || bluestein_m(inl.n) > M || !inl.a)
+        return hipErrorInvalidValue;
+    const dim3 gm((unsigned)((M + 255) / 256)), gn((unsigned)((inl.n + 255) / 256));
+    const BluesteinJob *none = nullptr;
+    if (prof)
+        prof->begin(kKBluestein, s);
+    hipLaunchKernelGGL(k_bluestein_pre, gm, dim3(256), 0, s, none, inl, M);
+    hipError_t e = hipGetLastError();
+    if (prof)
+        prof->end(s);
+    const IonoJob jb_b{inl.a + M, inl.a + M, 0.0, 0.0, 0.0, nullptr};
+    const IonoJob conv{inl.a, inl.a, 0.0, 0.0, 0.0, inl.a + M};
+    if (e == hipSuccess)
+        e = launch_fft_forward(mplan, tw4096, nullptr, &jb_b, 1, s, prof);
+    if (e == hipSuccess)
+        e = launch_iono(mplan, tw4096, nullptr, &conv, 1, s, prof);
+    if (e != hipSuccess)
+        return e;
+    if (prof)
+        prof->begin(kKBluestein, s);
+    hipLaunchKernelGGL(k_bluestein_fwd_post, gn, dim3(256), 0, s, none, inl);
+    e = hipGetLastError();
+    if (prof)
+        prof->end(s);
     return e;
 }
 

@@ -485,7 +485,8 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
         st = stage_descriptors(ctx, nullptr, 0, rc::bluestein_work_bytes(n), s, &dev);
         if (st != RC_OK)
             return st;
-        const rc::BluesteinJob jb{xf, yf, static_cast<float2 *>(const_cast<void *>(dev)), n, phase, carrier_hz, fs_hz};
+        const rc::BluesteinJob jb{xf, yf, static_cast<float2 *>(const_cast<void *>(dev)), n, phase, carrier_hz, fs_hz,
+                                  nullptr};
         e = rc::launch_iono_bluestein(*plan, ctx->tw4096, nullptr, nullptr, jb, 1, n, s, prof_of(ctx));
         st = mark_descriptors_used(ctx, s);
         if (e == hipSuccess && st != RC_OK)
@@ -509,19 +510,31 @@ rc_status replica_spectrum(rc_context ctx, const rc_c64 *replica, int64_t n_rep,
         return fail(ctx, RC_ERR_INVALID_ARG, "need 1 <= n_rep <= n");
     if (overlaps(replica, n_rep * 8, spec, n * 8))
         return fail(ctx, RC_ERR_INVALID_ARG, "replica and spectrum overlap");
-    if (!is_pow2(n) || n > kMaxIonoLength)
-        return fail(ctx, RC_ERR_UNSUPPORTED, "pulse compression lengths are powers of two up to 2^24");
+    if (n > kMaxIonoLength)
+        return fail(ctx, RC_ERR_UNSUPPORTED, "n above 2^24 (power of two) or 2^23 (other lengths)");
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const FftPlan *plan = nullptr;
-    rc_status st = get_plan(ctx, n, &plan);
+    rc_status st = get_plan(ctx, iono_plan_length(n), &plan);
     if (st != RC_OK)
         return st;
     float2 *sp = reinterpret_cast<float2 *>(spec);
     hipError_t e = rc::launch_pad(reinterpret_cast<const float2 *>(replica), n_rep, sp, n, s);
-    if (e == hipSuccess) {
+    if (e == hipSuccess && is_pow2(n)) {
+        // the transform's native bin order, which the row pass of compress_pulse multiplies in
         const IonoJob jb{sp, sp, 0.0, 0.0, 0.0, nullptr, 0};
         e = rc::launch_fft_forward(*plan, ctx->tw4096, nullptr, &jb, 1, s, prof_of(ctx));
+    } else if (e == hipSuccess) {
+        // natural bin order, which Bluestein's middle step of compress_pulse multiplies in
+        const void *dev = nullptr;
+        st = stage_descriptors(ctx, nullptr, 0, rc::bluestein_work_bytes(n), s, &dev);
+        if (st != RC_OK)
+            return st;
+        const rc::BluesteinJob jb{sp, sp, static_cast<float2 *>(const_cast<void *>(dev)), n, 0.0, 0.0, 0.0, nullptr};
+        e = rc::launch_bluestein_forward(*plan, ctx->tw4096, jb, s, prof_of(ctx));
+        st = mark_descriptors_used(ctx, s);
+        if (e == hipSuccess && st != RC_OK)
+            return st;
     }
     if (e != hipSuccess)
         return device_fail(ctx, e, "replica_spectrum launch");
@@ -551,18 +564,34 @@ rc_status compress_pulse(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n, 
         return fail(ctx, RC_ERR_INVALID_ARG, "x and y partially overlap");
     if (overlaps(spec, n * 8, y, n * 8))
         return fail(ctx, RC_ERR_INVALID_ARG, "the spectrum overlaps y");
-    if (!is_pow2(n) || n > kMaxIonoLength)
-        return fail(ctx, RC_ERR_UNSUPPORTED, "pulse compression lengths are powers of two up to 2^24");
+    if (n > kMaxIonoLength)
+        return fail(ctx, RC_ERR_UNSUPPORTED, "n above 2^24 (power of two) or 2^23 (other lengths)");
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const FftPlan *plan = nullptr;
-    rc_status st = get_plan(ctx, n, &plan);
+    rc_status st = get_plan(ctx, iono_plan_length(n), &plan);
     if (st != RC_OK)
         return st;
-    const IonoJob job{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y),
-                      phase_numerator(tec_el_per_m2, direction), carrier_hz, fs_hz,
-                      reinterpret_cast<const float2 *>(spec), 1};
-    const hipError_t e = rc::launch_iono(*plan, ctx->tw4096, nullptr, &job, 1, s, prof_of(ctx), rc::kRowTablePhase);
+    const float2 *xf = reinterpret_cast<const float2 *>(x);
+    float2 *yf = reinterpret_cast<float2 *>(y);
+    const float2 *sp = reinterpret_cast<const float2 *>(spec);
+    const double phase = phase_numerator(tec_el_per_m2, direction);
+    hipError_t e;
+    if (is_pow2(n)) {
+        const IonoJob job{xf, yf, phase, carrier_hz, fs_hz, sp, 1};
+        e = rc::launch_iono(*plan, ctx->tw4096, nullptr, &job, 1, s, prof_of(ctx), rc::kRowTablePhase);
+    } else {
+        const void *dev = nullptr;
+        st = stage_descriptors(ctx, nullptr, 0, rc::bluestein_work_bytes(n), s, &dev);
+        if (st != RC_OK)
+            return st;
+        const rc::BluesteinJob jb{xf, yf, static_cast<float2 *>(const_cast<void *>(dev)), n, phase, carrier_hz,
+                                  fs_hz, sp};
+        e = rc::launch_iono_bluestein(*plan, ctx->tw4096, nullptr, nullptr, jb, 1, n, s, prof_of(ctx));
+        st = mark_descriptors_used(ctx, s);
+        if (e == hipSuccess && st != RC_OK)
+            return st;
+    }
     if (e != hipSuccess)
         return device_fail(ctx, e, "compress_pulse launch");
     return RC_OK;
@@ -692,7 +721,7 @@ rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, 
                 iono[p.n_out].push_back(IonoJob{src, p.y, ph, p.carrier, p.fs_hz, nullptr});
             else
                 blue[rc::bluestein_m(p.n_out)].push_back(
-                    rc::BluesteinJob{src, p.y, nullptr, p.n_out, ph, p.carrier, p.fs_hz});
+                    rc::BluesteinJob{src, p.y, nullptr, p.n_out, ph, p.carrier, p.fs_hz, nullptr});
         }
     }
     if (mfma.size() > 65535 || fast.size() > 65535 || direct.size() > 65535)

@@ -252,6 +252,9 @@ struct BluesteinJob {
     float2 *a;        // workspace: a[0, m) and b = a + m
     int64_t n;
     double phase_num, carrier, fs;  // as in IonoJob
+    // When set, the spectrum is also multiplied by conj(corr[k]) (natural bin order, n values):
+    // the cross-correlation with the signal whose spectrum corr holds (pulse compression).
+    const float2 *corr;
 };
 int64_t bluestein_m(int64_t n);
 size_t bluestein_work_bytes(int64_t n);  // 2 m complex values
@@ -262,6 +265,10 @@ size_t bluestein_work_bytes(int64_t n);  // 2 m complex values
 hipError_t launch_iono_bluestein(const FftPlan &mplan, const float2 *tw4096, const BluesteinJob *jobs_dev,
                                  const IonoJob *ffts_dev, const BluesteinJob &inl, int njobs, int64_t max_n,
                                  hipStream_t s, Profiler *prof);
+// The forward DFT alone of one job by Bluestein's chirp convolution: y[k] = DFT_n(x)[k] in natural
+// bin order, unnormalised (phase and corr unused).  y may equal x.
+hipError_t launch_bluestein_forward(const FftPlan &mplan, const float2 *tw4096, const BluesteinJob &inl,
+                                    hipStream_t s, Profiler *prof);
 
 }  // namespace rc
 

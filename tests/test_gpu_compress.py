@@ -52,7 +52,9 @@ def host(t):
 
 
 @pytest.mark.parametrize("n,n_rep", [(16, 5), (256, 256), (4096, 1000), (8192, 3000), (65536, 20000),
-                                     (1 << 19, 204800), (1 << 20, 1000)])
+                                     (1 << 19, 204800), (1 << 20, 1000),
+                                     # other lengths: Bluestein, the correlation in its middle step
+                                     (3, 2), (1000, 300), (3001, 3001), (65537, 20000), (300001, 100000)])
 @pytest.mark.parametrize("direction", ["correct", "distort"])
 def test_compress_matches_oracle(torch, ctx, orc, n, n_rep, direction):
     x = wf.bandlimited_noise(n, wf.rng_for(161, n))
@@ -111,10 +113,9 @@ def test_replica_from_correct_doppler(torch, ctx, orc):
 def test_compress_argument_errors(torch, ctx):
     import paper_2508_04951_amd as rc
 
-    x = torch.zeros(1000, dtype=torch.complex64, device="cuda")
     r = torch.ones(16, dtype=torch.complex64, device="cuda")
     with pytest.raises(rc.RcError) as ei:
-        ctx.replica_spectrum(r, 1000)  # not a power of two
+        ctx.replica_spectrum(r, (1 << 23) + 1)  # other lengths stop at 2^23
     assert ei.value.status == 2
     with pytest.raises(ValueError):
         ctx.replica_spectrum(r, 8)  # replica longer than n

@@ -199,9 +199,9 @@ def test_compress_autocorrelation_peak_is_the_energy(orc):
     assert np.abs(y[1:]).max() <= np.abs(y[0]) * (1 + 1e-12)  # Cauchy-Schwarz
 
 
-def test_compress_naive_and_fast_agree(orc):
+@pytest.mark.parametrize("n", [4096, 3001])  # the radix-2 and the Bluestein transforms
+def test_compress_naive_and_fast_agree(orc, n):
     rng = wf.rng_for(155, 0)
-    n = 4096
     x = wf.bandlimited_noise(n, rng)
     r = wf.lfm(1000, FS, 5e6)
     a = orc.compress(x, r, FS, FC, 80 * wf.TECU, naive=True)
