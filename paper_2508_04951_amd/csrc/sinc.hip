@@ -12,7 +12,8 @@
 //    the complex MAC.  The input span of a 1024-output workgroup is staged once in LDS.
 //    An output whose position is an exact integer returns that input sample.
 //  * k_sinc_direct -- any taper, any alpha > 0, and the full (H = 0) sum: float64 position,
-//    float64 weights and accumulation, 1..64 lanes per output with a shuffle reduction.
+//    float64 weights (one reciprocal and one Newton step per tap) and accumulation, 1..64 lanes
+//    per output with a shuffle reduction.
 #include <cmath>
 
 #include "rc_internal.h"
@@ -235,7 +236,13 @@ k_sinc_direct(const SincJob *__restrict__ jobs, SincJob inl, int H, int window, 
             const double inv_h = H > 0 ? 1.0 / (double)H : 0.0;
             for (int64_t n = lo + sub; n <= hi; n += G) {
                 const double u = t - (double)n;
-                double w = (((n - fi) & 1) ? -sp : sp) / (kPi * u);
+                // 1 / (pi u) from the hardware reciprocal (relative error below 2^-24) and one
+                // Newton step (below 2^-47): far below the float32 output, at a fraction of the
+                // cost of an IEEE division per tap
+                const double d = kPi * u;
+                double r = __builtin_amdgcn_rcp(d);
+                r = fma(r, fma(-d, r, 1.0), r);
+                double w = (((n - fi) & 1) ? -sp : sp) * r;
                 if (taper)
                     w *= kaiser_at(kp, u * inv_h);
                 const float2 v = gmem(jb.x)[n];
