@@ -11,9 +11,9 @@
 //    (broadcast LDS reads); per tap and output the work is 2 FMAs for the weight and 2 for
 //    the complex MAC.  The input span of a 1024-output workgroup is staged once in LDS.
 //    An output whose position is an exact integer returns that input sample.
-//  * k_sinc_direct -- any taper, any alpha > 0, and the full (H = 0) sum: float64 position,
-//    float64 weights (one reciprocal and one Newton step per tap) and accumulation, 1..64 lanes
-//    per output with a shuffle reduction.
+//  * k_sinc_direct -- any taper, any alpha > 0, and the full (H = 0) sum: float64 position and
+//    sin(pi mu), float32 tap weights (one reciprocal per tap) and accumulation, 1..64 lanes per
+//    output with a shuffle reduction.
 #include <cmath>
 
 #include "rc_internal.h"
@@ -201,7 +201,7 @@ k_sinc_direct(const SincJob *__restrict__ jobs, SincJob inl, int H, int window, 
     const int64_t m = gid >> log2g;
     const int sub = (int)(gid & (G - 1));
     int mode = 0;  // 0 idle, 1 exact sample, 2 weighted sum
-    double re = 0.0, im = 0.0;
+    float re = 0.f, im = 0.f;
     if (m < jb.n_out) {
         const double t = __dmul_rn(jb.alpha, (double)m);
         const double f = floor(t);
@@ -231,24 +231,25 @@ k_sinc_direct(const SincJob *__restrict__ jobs, SincJob inl, int H, int window, 
                 lo = 0;
             if (hi > jb.n_in - 1)
                 hi = jb.n_in - 1;
-            const double sp = sinpi(t - f);
+            // sinc(u) = (-1)^(n - fi) sin(pi mu) / (pi u), mu = t - fi: the common factor
+            // sin(pi mu) / pi in float64 once, then per tap u = t - n (float64, rounded once to
+            // float32: relative error 2^-24 whatever its size) and its float32 reciprocal
+            const float spf = (float)(sinpi(t - f) * (1.0 / kPi));
             const bool taper = (H > 0 && window == RC_WIN_KAISER);
             const double inv_h = H > 0 ? 1.0 / (double)H : 0.0;
             for (int64_t n = lo + sub; n <= hi; n += G) {
-                const double u = t - (double)n;
-                // 1 / (pi u) from the hardware reciprocal (relative error below 2^-24) and one
-                // Newton step (below 2^-47): far below the float32 output, at a fraction of the
-                // cost of an IEEE division per tap
-                const double d = kPi * u;
-                double r = __builtin_amdgcn_rcp(d);
-                r = fma(r, fma(-d, r, 1.0), r);
-                double w = (((n - fi) & 1) ? -sp : sp) * r;
+                const double ud = t - (double)n;
+                float w = __builtin_amdgcn_rcpf((float)ud);
+                if ((n - fi) & 1)
+                    w = -w;
                 if (taper)
-                    w *= kaiser_at(kp, u * inv_h);
+                    w *= (float)kaiser_at(kp, ud * inv_h);
                 const float2 v = gmem(jb.x)[n];
-                re = fma((double)v.x, w, re);
-                im = fma((double)v.y, w, im);
+                re = fmaf(v.x, w, re);
+                im = fmaf(v.y, w, im);
             }
+            re *= spf;
+            im *= spf;
         }
     }
     for (int o = G >> 1; o > 0; o >>= 1) {
@@ -256,7 +257,7 @@ k_sinc_direct(const SincJob *__restrict__ jobs, SincJob inl, int H, int window, 
         im += __shfl_xor(im, o, 64);
     }
     if (mode != 0 && sub == 0)
-        gmem(jb.y)[m] = make_float2((float)re, (float)im);
+        gmem(jb.y)[m] = make_float2(re, im);
 }
 
 }  // namespace
