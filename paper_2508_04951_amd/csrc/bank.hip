@@ -24,7 +24,7 @@ namespace rc {
 namespace {
 
 constexpr int kR = kFarrowOrders;
-constexpr int kBankM = 512;        // outputs per workgroup and hypothesis
+constexpr int kBankM = 256;        // outputs per workgroup and hypothesis
 constexpr int kBankThreads = 256;
 
 __device__ __forceinline__ double kaiser_series(const KaiserPoly &kp, double x)
