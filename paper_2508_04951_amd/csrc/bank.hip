@@ -76,46 +76,119 @@ __global__ void __launch_bounds__(256) k_farrow_coef(KaiserPoly kp, int H, int t
         gmem(coef)[tap * kR + k] = (float)d[k];
 }
 
-// Z[f][r] for f in [0, F): one workgroup per 256 positions; the input span and the
-// coefficients are staged in LDS.  Dynamic LDS: 2H R floats, then 256 + 2H - 1 samples.
+// Z[f][r] for f in [0, F) on the matrix cores: for 16 consecutive positions p0 + i the filter
+// bank is the product of the Hankel matrix A[i][t] = x[p0 + i - H + 1 + t] (16 x 2H) and the
+// coefficient matrix C[t][r] (2H x 8), taken 32 taps per v_mfma_f32_16x16x32_f16.  Both operands
+// are split into float16 hi + lo parts after exact power-of-two scaling (the samples by a
+// workgroup-wide exponent, the coefficients by 2^kZCoefExp).  The B operand holds C_hi in columns
+// 0..7 and C_lo in columns 8..15, so the two products A_hi B and A_lo B of one accumulator give
+// A (C_hi + C_lo) once the column halves are added: A_hi C_hi + A_hi C_lo + A_lo C_hi (+ A_lo C_lo)
+// in float32, about 22 bits per product.  A row i of the Hankel matrix starts at span offset i,
+// which is 16-byte aligned only for i % 8 == 0, so the span is staged as 8 copies shifted by
+// 0..7 samples and row i reads copy i % 8 at the aligned offset i - i % 8.
+constexpr int kZPos = 256;                                   // positions per workgroup
+constexpr int kZMaxSteps = (2 * kFarrowMaxHalfWidth + 31) / 32;  // 32-tap steps at the largest H
+constexpr int kZCoefExp = 12;
+
+__host__ __device__ constexpr int farrow_z_steps(int H) { return (2 * H + 31) / 32; }
+// staged span (samples) of one workgroup: kZPos + 32 steps, plus 8 for the shifted copies
+__host__ __device__ constexpr int farrow_z_span(int H) { return kZPos + 32 * farrow_z_steps(H); }
+size_t farrow_z_lds_bytes(int H)
+{
+    const size_t L = (size_t)farrow_z_span(H);
+    return (L + 8) * sizeof(float2) + 8 * 4 * L * sizeof(_Float16) + 16;
+}
+
+typedef _Float16 zhalf8 __attribute__((ext_vector_type(8)));
+typedef float zfloatx4 __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(256) k_farrow_z(const float2 *__restrict__ x, int64_t n, int64_t F, int H,
                                                   const float *__restrict__ coef, float2 *__restrict__ Z)
 {
-    extern __shared__ __attribute__((aligned(16))) float smem_z[];
-    float *cs = smem_z;
-    float2 *xs = reinterpret_cast<float2 *>(smem_z + 2 * H * kR);
-    const int tid = threadIdx.x;
-    const int64_t f0 = (int64_t)blockIdx.x * 256;
-    for (int i = tid; i < 2 * H * kR; i += 256)
-        cs[i] = gload(coef, i);
-    const int span = 256 + 2 * H - 1;
-    for (int e = tid; e < span; e += 256) {
-        const int64_t g = f0 - H + 1 + e;
-        xs[e] = (g >= 0 && g < n) ? gload(x, g) : make_float2(0.f, 0.f);
+    extern __shared__ __attribute__((aligned(16))) float2 smem_z[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ksteps = farrow_z_steps(H), L = farrow_z_span(H);
+    float2 *stage = smem_z;                                                  // L + 8 samples
+    _Float16 *copies = reinterpret_cast<_Float16 *>(stage + L + 8);          // [8 shifts][4 planes][L]
+    float *wmax = reinterpret_cast<float *>(copies + 8 * 4 * L);             // 4 wave maxima
+    const int64_t f0 = (int64_t)blockIdx.x * kZPos;
+    const int64_t g0 = f0 - H + 1;  // span sample k is x[g0 + k]; zero outside [0, n)
+    float m = 0.f;
+    for (int k = tid; k < L + 8; k += 256) {
+        const int64_t g = g0 + k;
+        const float2 v = (g >= 0 && g < n) ? gload(x, g) : make_float2(0.f, 0.f);
+        stage[k] = v;
+        m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
-    __syncthreads();
-    const int64_t f = f0 + tid;
-    if (f >= F)
-        return;
-    float ar[kR], ai[kR];
+    for (int o = 32; o > 0; o >>= 1)
+        m = fmaxf(m, __shfl_xor(m, o, 64));
+    if (lane == 0)
+        wmax[wave] = m;
+    // B fragments (this lane's column: order r = col % 8, hi part for col < 8, lo part above),
+    // built from the coefficients while the span loads are in flight
+    const int col = lane & 15, q = lane >> 4;
+    zhalf8 bfrag[kZMaxSteps];
 #pragma unroll
-    for (int r = 0; r < kR; ++r)
-        ar[r] = ai[r] = 0.f;
-    for (int t = 0; t < 2 * H; ++t) {
-        const float2 v = xs[tid + t];
-        const float4 c0 = *reinterpret_cast<const float4 *>(cs + t * kR);
-        const float4 c1 = *reinterpret_cast<const float4 *>(cs + t * kR + 4);
-        const float c[kR] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    for (int st = 0; st < kZMaxSteps; ++st) {
+        if (st < ksteps) {
 #pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            ar[r] = fmaf(v.x, c[r], ar[r]);
-            ai[r] = fmaf(v.y, c[r], ai[r]);
+            for (int j = 0; j < 8; ++j) {
+                const int t = 32 * st + 8 * q + j;
+                const float c = t < 2 * H ? ldexpf(gload(coef, (int64_t)t * kR + (col & 7)), kZCoefExp) : 0.f;
+                const _Float16 hi = (_Float16)c;
+                bfrag[st][j] = col < 8 ? hi : (_Float16)(c - (float)hi);
+            }
         }
     }
-    const auto zg = gmem(reinterpret_cast<float4 *>(Z + f * kR));
+    __syncthreads();
+    int ex = 0;
+    (void)frexpf(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])), &ex);
+    const int sexp = 14 - ex;  // scaled samples below 2^14 in magnitude
+    // the shifted fp16 copies: copy c, plane (re hi, re lo, im hi, im lo), entry k = span[k + c]
+    for (int k = tid; k < L; k += 256) {
 #pragma unroll
-    for (int r = 0; r < kR; r += 2)
-        zg[r / 2] = make_float4(ar[r], ai[r], ar[r + 1], ai[r + 1]);
+        for (int c = 0; c < 8; ++c) {
+            const float2 v = stage[k + c];
+            const float re = ldexpf(v.x, sexp), im = ldexpf(v.y, sexp);
+            const _Float16 rh = (_Float16)re, ih = (_Float16)im;
+            _Float16 *cp = copies + (size_t)c * 4 * L + k;
+            cp[0] = rh;
+            cp[L] = (_Float16)(re - (float)rh);
+            cp[2 * L] = ih;
+            cp[3 * L] = (_Float16)(im - (float)ih);
+        }
+    }
+    __syncthreads();
+    const float unscale = ldexpf(1.f, -(sexp + kZCoefExp));
+    const int i = col;  // A row (position within the tile) of this lane
+    const _Float16 *cbase = copies + (size_t)(i & 7) * 4 * L + (i & ~7) + 8 * q;
+#pragma unroll 1
+    for (int tile = wave; tile < kZPos / 16; tile += 4) {
+        zfloatx4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < kZMaxSteps; ++st) {
+            if (st < ksteps) {
+                const int off = 16 * tile + 32 * st;  // a multiple of 8 halves: 16-byte aligned
+                const zhalf8 arh = *reinterpret_cast<const zhalf8 *>(cbase + off);
+                const zhalf8 arl = *reinterpret_cast<const zhalf8 *>(cbase + L + off);
+                const zhalf8 aih = *reinterpret_cast<const zhalf8 *>(cbase + 2 * L + off);
+                const zhalf8 ail = *reinterpret_cast<const zhalf8 *>(cbase + 3 * L + off);
+                acc_re = __builtin_amdgcn_mfma_f32_16x16x32_f16(arh, bfrag[st], acc_re, 0, 0, 0);
+                acc_im = __builtin_amdgcn_mfma_f32_16x16x32_f16(aih, bfrag[st], acc_im, 0, 0, 0);
+                acc_re = __builtin_amdgcn_mfma_f32_16x16x32_f16(arl, bfrag[st], acc_re, 0, 0, 0);
+                acc_im = __builtin_amdgcn_mfma_f32_16x16x32_f16(ail, bfrag[st], acc_im, 0, 0, 0);
+            }
+        }
+        // lane (col, q) holds rows 4 q + k of column col: add the lo half (col + 8) to the hi half
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float zr = acc_re[k] + __shfl_xor(acc_re[k], 8, 64);
+            const float zi = acc_im[k] + __shfl_xor(acc_im[k], 8, 64);
+            const int64_t f = f0 + 16 * tile + 4 * q + k;
+            if (col < 8 && f < F)
+                gmem(Z)[f * kR + col] = make_float2(zr * unscale, zi * unscale);
+        }
+    }
 }
 
 // One group of hypotheses (consecutive in alpha order) for kBankM outputs: the Z rows the
@@ -342,10 +415,13 @@ hipError_t launch_farrow_bank(const FarrowPlan &p, const float2 *x, int64_t n, f
             return e;
         attr[dev] = true;
     }
-    const size_t zlds = ((size_t)2 * H * kR * sizeof(float) + 15) / 16 * 16 + (size_t)(256 + 2 * H - 1) * 8;
+    const size_t zlds = farrow_z_lds_bytes(H);
+    if (zlds > 64 * 1024)
+        return hipErrorInvalidValue;
     if (prof)
         prof->begin(kKFarrowZ, s);
-    hipLaunchKernelGGL(k_farrow_z, dim3((unsigned)((p.F + 255) / 256)), dim3(256), zlds, s, x, n, p.F, H, coef, Z);
+    hipLaunchKernelGGL(k_farrow_z, dim3((unsigned)((p.F + kZPos - 1) / kZPos)), dim3(256), zlds, s, x, n, p.F, H, coef,
+                       Z);
     e = hipGetLastError();
     if (prof)
         prof->end(s);
