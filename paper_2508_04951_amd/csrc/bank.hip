@@ -87,7 +87,6 @@ __global__ void __launch_bounds__(256) k_farrow_coef(KaiserPoly kp, int H, int t
 // which is 16-byte aligned only for i % 8 == 0, so the span is staged as 8 copies shifted by
 // 0..7 samples and row i reads copy i % 8 at the aligned offset i - i % 8.
 constexpr int kZPos = 256;                                   // positions per workgroup
-constexpr int kZMaxSteps = (2 * kFarrowMaxHalfWidth + 31) / 32;  // 32-tap steps at the largest H
 constexpr int kZCoefExp = 12;
 
 __host__ __device__ constexpr int farrow_z_steps(int H) { return (2 * H + 31) / 32; }
@@ -102,30 +101,37 @@ size_t farrow_z_lds_bytes(int H)
 typedef _Float16 zhalf8 __attribute__((ext_vector_type(8)));
 typedef float zfloatx4 __attribute__((ext_vector_type(4)));
 
+// Persistent: each workgroup builds its B fragments once, then walks blocks of kZPos positions
+// (blockIdx.x, + gridDim.x, ...), loading the next block's span into registers while the
+// current block's products run.  KS bounds the 32-tap steps (4, 8 or 16: H <= 64, 128, 256),
+// which sets the registers the fragments and the prefetch hold.
+template <int KS>
 __global__ void __launch_bounds__(256) k_farrow_z(const float2 *__restrict__ x, int64_t n, int64_t F, int H,
                                                   const float *__restrict__ coef, float2 *__restrict__ Z)
 {
+    constexpr int kZMaxSteps = KS;
+    constexpr int kZPrefetch = (kZPos + 32 * KS + 8 + 255) / 256;  // span samples per thread
     extern __shared__ __attribute__((aligned(16))) float2 smem_z[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ksteps = farrow_z_steps(H), L = farrow_z_span(H);
     float2 *stage = smem_z;                                                  // L + 8 samples
     _Float16 *copies = reinterpret_cast<_Float16 *>(stage + L + 8);          // [8 shifts][4 planes][L]
     float *wmax = reinterpret_cast<float *>(copies + 8 * 4 * L);             // 4 wave maxima
-    const int64_t f0 = (int64_t)blockIdx.x * kZPos;
-    const int64_t g0 = f0 - H + 1;  // span sample k is x[g0 + k]; zero outside [0, n)
-    float m = 0.f;
-    for (int k = tid; k < L + 8; k += 256) {
-        const int64_t g = g0 + k;
-        const float2 v = (g >= 0 && g < n) ? gload(x, g) : make_float2(0.f, 0.f);
-        stage[k] = v;
-        m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
-    }
-    for (int o = 32; o > 0; o >>= 1)
-        m = fmaxf(m, __shfl_xor(m, o, 64));
-    if (lane == 0)
-        wmax[wave] = m;
+    const int64_t nblk = (F + kZPos - 1) / kZPos;
+    // the span of block b: sample k is x[b kZPos - H + 1 + k], zero outside [0, n)
+    float2 pre[kZPrefetch];
+    auto fetch = [&](int64_t b) {
+        const int64_t g0 = b * kZPos - H + 1;
+#pragma unroll
+        for (int u = 0; u < kZPrefetch; ++u) {
+            const int k = tid + 256 * u;
+            const int64_t g = g0 + k;
+            pre[u] = (k < L + 8 && g >= 0 && g < n) ? gload(x, g) : make_float2(0.f, 0.f);
+        }
+    };
+    fetch(blockIdx.x);
     // B fragments (this lane's column: order r = col % 8, hi part for col < 8, lo part above),
-    // built from the coefficients while the span loads are in flight
+    // built once while the first span is in flight
     const int col = lane & 15, q = lane >> 4;
     zhalf8 bfrag[kZMaxSteps];
 #pragma unroll
@@ -140,54 +146,73 @@ __global__ void __launch_bounds__(256) k_farrow_z(const float2 *__restrict__ x, 
             }
         }
     }
-    __syncthreads();
-    int ex = 0;
-    (void)frexpf(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])), &ex);
-    const int sexp = 14 - ex;  // scaled samples below 2^14 in magnitude
-    // the shifted fp16 copies: copy c, plane (re hi, re lo, im hi, im lo), entry k = span[k + c]
-    for (int k = tid; k < L; k += 256) {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float2 v = stage[k + c];
-            const float re = ldexpf(v.x, sexp), im = ldexpf(v.y, sexp);
-            const _Float16 rh = (_Float16)re, ih = (_Float16)im;
-            _Float16 *cp = copies + (size_t)c * 4 * L + k;
-            cp[0] = rh;
-            cp[L] = (_Float16)(re - (float)rh);
-            cp[2 * L] = ih;
-            cp[3 * L] = (_Float16)(im - (float)ih);
-        }
-    }
-    __syncthreads();
-    const float unscale = ldexpf(1.f, -(sexp + kZCoefExp));
-    const int i = col;  // A row (position within the tile) of this lane
+    const int i = col;  // A row (position within a tile) of this lane
     const _Float16 *cbase = copies + (size_t)(i & 7) * 4 * L + (i & ~7) + 8 * q;
-#pragma unroll 1
-    for (int tile = wave; tile < kZPos / 16; tile += 4) {
-        zfloatx4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        float m = 0.f;
 #pragma unroll
-        for (int st = 0; st < kZMaxSteps; ++st) {
-            if (st < ksteps) {
-                const int off = 16 * tile + 32 * st;  // a multiple of 8 halves: 16-byte aligned
-                const zhalf8 arh = *reinterpret_cast<const zhalf8 *>(cbase + off);
-                const zhalf8 arl = *reinterpret_cast<const zhalf8 *>(cbase + L + off);
-                const zhalf8 aih = *reinterpret_cast<const zhalf8 *>(cbase + 2 * L + off);
-                const zhalf8 ail = *reinterpret_cast<const zhalf8 *>(cbase + 3 * L + off);
-                acc_re = __builtin_amdgcn_mfma_f32_16x16x32_f16(arh, bfrag[st], acc_re, 0, 0, 0);
-                acc_im = __builtin_amdgcn_mfma_f32_16x16x32_f16(aih, bfrag[st], acc_im, 0, 0, 0);
-                acc_re = __builtin_amdgcn_mfma_f32_16x16x32_f16(arl, bfrag[st], acc_re, 0, 0, 0);
-                acc_im = __builtin_amdgcn_mfma_f32_16x16x32_f16(ail, bfrag[st], acc_im, 0, 0, 0);
+        for (int u = 0; u < kZPrefetch; ++u) {
+            const int k = tid + 256 * u;
+            if (k < L + 8) {
+                stage[k] = pre[u];
+                m = fmaxf(m, fmaxf(fabsf(pre[u].x), fabsf(pre[u].y)));
             }
         }
-        // lane (col, q) holds rows 4 q + k of column col: add the lo half (col + 8) to the hi half
+        for (int o = 32; o > 0; o >>= 1)
+            m = fmaxf(m, __shfl_xor(m, o, 64));
+        if (lane == 0)
+            wmax[wave] = m;
+        if (b + gridDim.x < nblk)
+            fetch(b + gridDim.x);
+        __syncthreads();
+        int ex = 0;
+        (void)frexpf(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])), &ex);
+        const int sexp = 14 - ex;  // scaled samples below 2^14 in magnitude
+        // the shifted fp16 copies: copy c, plane (re hi, re lo, im hi, im lo), entry k = span[k + c]
+        for (int k = tid; k < L; k += 256) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float zr = acc_re[k] + __shfl_xor(acc_re[k], 8, 64);
-            const float zi = acc_im[k] + __shfl_xor(acc_im[k], 8, 64);
-            const int64_t f = f0 + 16 * tile + 4 * q + k;
-            if (col < 8 && f < F)
-                gmem(Z)[f * kR + col] = make_float2(zr * unscale, zi * unscale);
+            for (int c = 0; c < 8; ++c) {
+                const float2 v = stage[k + c];
+                const float re = ldexpf(v.x, sexp), im = ldexpf(v.y, sexp);
+                const _Float16 rh = (_Float16)re, ih = (_Float16)im;
+                _Float16 *cp = copies + (size_t)c * 4 * L + k;
+                cp[0] = rh;
+                cp[L] = (_Float16)(re - (float)rh);
+                cp[2 * L] = ih;
+                cp[3 * L] = (_Float16)(im - (float)ih);
+            }
         }
+        __syncthreads();
+        const float unscale = ldexpf(1.f, -(sexp + kZCoefExp));
+        const int64_t f0 = b * kZPos;
+#pragma unroll 1
+        for (int tile = wave; tile < kZPos / 16; tile += 4) {
+            zfloatx4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < kZMaxSteps; ++st) {
+                if (st < ksteps) {
+                    const int off = 16 * tile + 32 * st;  // a multiple of 8 halves: 16-byte aligned
+                    const zhalf8 arh = *reinterpret_cast<const zhalf8 *>(cbase + off);
+                    const zhalf8 arl = *reinterpret_cast<const zhalf8 *>(cbase + L + off);
+                    const zhalf8 aih = *reinterpret_cast<const zhalf8 *>(cbase + 2 * L + off);
+                    const zhalf8 ail = *reinterpret_cast<const zhalf8 *>(cbase + 3 * L + off);
+                    acc_re = __builtin_amdgcn_mfma_f32_16x16x32_f16(arh, bfrag[st], acc_re, 0, 0, 0);
+                    acc_im = __builtin_amdgcn_mfma_f32_16x16x32_f16(aih, bfrag[st], acc_im, 0, 0, 0);
+                    acc_re = __builtin_amdgcn_mfma_f32_16x16x32_f16(arl, bfrag[st], acc_re, 0, 0, 0);
+                    acc_im = __builtin_amdgcn_mfma_f32_16x16x32_f16(ail, bfrag[st], acc_im, 0, 0, 0);
+                }
+            }
+            // lane (col, q) holds rows 4 q + k of column col: add the lo half (col + 8) to the hi half
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float zr = acc_re[k] + __shfl_xor(acc_re[k], 8, 64);
+                const float zi = acc_im[k] + __shfl_xor(acc_im[k], 8, 64);
+                const int64_t f = f0 + 16 * tile + 4 * q + k;
+                if (col < 8 && f < F)
+                    gmem(Z)[f * kR + col] = make_float2(zr * unscale, zi * unscale);
+            }
+        }
+        __syncthreads();  // stage, copies and wmax are rewritten for the next block
     }
 }
 
@@ -420,8 +445,21 @@ hipError_t launch_farrow_bank(const FarrowPlan &p, const float2 *x, int64_t n, f
         return hipErrorInvalidValue;
     if (prof)
         prof->begin(kKFarrowZ, s);
-    hipLaunchKernelGGL(k_farrow_z, dim3((unsigned)((p.F + kZPos - 1) / kZPos)), dim3(256), zlds, s, x, n, p.F, H, coef,
-                       Z);
+    // persistent workgroups: as many as fit on the device at once, at most one per block
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess)
+        return e;
+    const int64_t zblocks = (p.F + kZPos - 1) / kZPos;
+    const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)zlds);
+    const int64_t zgrid = std::min<int64_t>(zblocks, (int64_t)std::max(cus, 1) * std::min<int64_t>(per_cu, 4));
+    const int ks = farrow_z_steps(H);
+    if (ks <= 4)
+        hipLaunchKernelGGL(k_farrow_z<4>, dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H, coef, Z);
+    else if (ks <= 8)
+        hipLaunchKernelGGL(k_farrow_z<8>, dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H, coef, Z);
+    else
+        hipLaunchKernelGGL(k_farrow_z<16>, dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H, coef, Z);
     e = hipGetLastError();
     if (prof)
         prof->end(s);
