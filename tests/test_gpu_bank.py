@@ -53,7 +53,8 @@ def host(t):
 VS = [-8000.0, -5123.4, -17.0, 0.0, 3.3, 2999.9, 8000.0]
 
 
-@pytest.mark.parametrize("hw,window", [(64, "kaiser"), (128, "kaiser"), (16, "kaiser"), (24, "rect")])
+@pytest.mark.parametrize("hw,window", [(64, "kaiser"), (128, "kaiser"), (16, "kaiser"), (24, "rect"),
+                                       (256, "kaiser"), (5, "kaiser")])
 @pytest.mark.parametrize("n,n_out", [(5000, 5000), (5000, 6100), (1, 40), (777, 300)])
 def test_bank_matches_oracle(torch, ctx, orc, hw, window, n, n_out):
     import paper_2508_04951_amd as rc
@@ -68,6 +69,21 @@ def test_bank_matches_oracle(torch, ctx, orc, hw, window, n, n_out):
             assert np.array_equal(y[h], ref.astype(np.complex64)), h
         else:
             assert rel_l2(y[h], ref) <= TOL, (h, rel_l2(y[h], ref))
+
+
+@pytest.mark.parametrize("scale", [1e-30, 1e-8, 1e8, 1e30])
+def test_bank_input_scale(torch, ctx, orc, scale):
+    """The filter bank's half-precision products scale their inputs by powers of two: samples
+    far outside float16's range (either way) give the same relative accuracy."""
+    import paper_2508_04951_amd as rc
+
+    n = 3000
+    x = (wf.polyphase_code(n, wf.rng_for(203, n)).astype(np.complex128) * scale).astype(np.complex64)
+    alphas = [alpha_exact(v) for v in (-6000.0, 41.0, 7500.0)]
+    y = host(ctx.correct_doppler_bank(dev(torch, x), alphas, rc.Sinc(64, "kaiser", 8.0), mode="farrow"))
+    for h, a in enumerate(alphas):
+        ref = orc.doppler(x, a, 64, "kaiser", 8.0)
+        assert rel_l2(y[h], ref) <= TOL, (scale, h, rel_l2(y[h], ref))
 
 
 def test_bank_rows_follow_the_given_order(torch, ctx):
