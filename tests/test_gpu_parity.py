@@ -127,7 +127,7 @@ def test_doppler_engines_on_small_and_scaled_inputs(torch, ctx, orc, engine):
     """Every engine on short pulses (a partial workgroup tile) and on inputs scaled far from
     unit power (the matrix-core path rescales by powers of two before its fp16 split)."""
     a = alpha_exact(-7000.0)
-    for n, scale in [(100, 1.0), (1023, 1.0), (1025, 3e-9), (5000, 7e5), (3000, 0.0)]:
+    for n, scale in [(100, 1.0), (1023, 1.0), (1025, 3e-9), (5000, 7e5), (3000, 0.0), (5000, 1e-30), (5000, 1e30)]:
         x = (wf.bandlimited_noise(n, wf.rng_for(110, n)) * np.float32(scale)).astype(np.complex64)
         y = host(ctx.correct_doppler(dev(torch, x), a, sinc(64)))
         ref = orc.doppler(x, a, 64, "kaiser", 8.0)
