@@ -893,6 +893,15 @@ __device__ __forceinline__ float2 chirp_w(int64_t m, int64_t N)
 }
 
 // a = x conj(w) zero-padded to M; b = the chirp placed circularly (b_m = b_{M-m} = w_m, m < N).
+// The chirp b is stored scaled by 2^-(log2(M) / 2), about 1/sqrt(M): its spectrum then has
+// magnitude about 1 instead of sqrt(M), which keeps the convolutions' float32 intermediates
+// (the transform of a times the chirp spectrum, then the inverse transform's sums) a factor
+// sqrt(M) further from overflow.  The steps after each convolution undo the exact power of two.
+__device__ __forceinline__ float chirp_scale_inv(int64_t M)
+{
+    return ldexpf(1.f, (63 - __clzll((unsigned long long)M)) / 2);
+}
+
 // One job per blockIdx.y.
 __global__ void __launch_bounds__(256) k_bluestein_pre(const BluesteinJob *jobs, BluesteinJob inl, int64_t M)
 {
@@ -909,8 +918,9 @@ __global__ void __launch_bounds__(256) k_bluestein_pre(const BluesteinJob *jobs,
     } else if (M - m < N) {
         bv = chirp_w(M - m, N);
     }
+    const float sb = 1.f / chirp_scale_inv(M);  // exact: a power of two
     gmem(jb.a)[m] = av;
-    gmem(jb.a + M)[m] = bv;
+    gmem(jb.a + M)[m] = make_float2(bv.x * sb, bv.y * sb);
 }
 
 // c (first convolution, in a) -> conj(c_k H_k) for k < N, zero above.  The forward DFT is
@@ -925,7 +935,9 @@ __global__ void __launch_bounds__(256) k_bluestein_mid(const BluesteinJob *jobs,
     float2 v = make_float2(0.f, 0.f);
     if (k < N) {
         const IonoJob ph{nullptr, nullptr, jb.phase_num, jb.carrier, jb.fs, nullptr};
-        const float2 h = cmul(gload(jb.a, k), iono_phase(ph, k, N));
+        const float si = chirp_scale_inv(M);  // the convolution carries the chirp's scale
+        const float2 c = gload(jb.a, k);
+        const float2 h = cmul(make_float2(c.x * si, c.y * si), iono_phase(ph, k, N));
         v = make_float2(h.x, -h.y);
         if (jb.corr)
             v = cmul(v, gload(jb.corr, k));
@@ -934,25 +946,26 @@ __global__ void __launch_bounds__(256) k_bluestein_mid(const BluesteinJob *jobs,
 }
 
 // c (the convolution, in a) -> y_k = conj(w_k) c_k for k < N: the forward DFT alone.
-__global__ void __launch_bounds__(256) k_bluestein_fwd_post(const BluesteinJob *jobs, BluesteinJob inl)
+__global__ void __launch_bounds__(256) k_bluestein_fwd_post(const BluesteinJob *jobs, BluesteinJob inl, int64_t M)
 {
     const BluesteinJob jb = jobs ? gload(jobs, blockIdx.y) : inl;
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x, N = jb.n;
     if (k >= N)
         return;
+    const float si = chirp_scale_inv(M);
     const float2 w = chirp_w(k, N), c = gload(jb.a, k);
-    gmem(jb.y)[k] = make_float2(w.x * c.x + w.y * c.y, w.x * c.y - w.y * c.x);  // conj(w) c
+    gmem(jb.y)[k] = make_float2((w.x * c.x + w.y * c.y) * si, (w.x * c.y - w.y * c.x) * si);  // conj(w) c
 }
 
 // f (second convolution, in a) -> y_n = w_n conj(f_n) / N.
-__global__ void __launch_bounds__(256) k_bluestein_post(const BluesteinJob *jobs, BluesteinJob inl)
+__global__ void __launch_bounds__(256) k_bluestein_post(const BluesteinJob *jobs, BluesteinJob inl, int64_t M)
 {
     const BluesteinJob jb = jobs ? gload(jobs, blockIdx.y) : inl;
     const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x, N = jb.n;
     if (n >= N)
         return;
     const float2 w = chirp_w(n, N), v = gload(jb.a, n);
-    const float sc = (float)(1.0 / (double)N);
+    const float sc = (float)(1.0 / (double)N) * chirp_scale_inv(M);  // the chirp's scale undone exactly
     // w conj(v)
     gmem(jb.y)[n] = make_float2((w.x * v.x + w.y * v.y) * sc, (w.y * v.x - w.x * v.y) * sc);
 }
@@ -1037,7 +1050,7 @@ hipError_t launch_iono_bluestein(const FftPlan &mplan, const float2 *tw4096, con
     if (e == hipSuccess)
         e = launch_iono(mplan, tw4096, fc, &conv, njobs, s, prof);
     if (e == hipSuccess)
-        e = small(k_bluestein_post, gn);
+        e = small(k_bluestein_post, gn, M);
     return e;
 }
 
@@ -1065,7 +1078,7 @@ hipError_t launch_bluestein_forward(const FftPlan &mplan, const float2 *tw4096, 
         return e;
     if (prof)
         prof->begin(kKBluestein, s);
-    hipLaunchKernelGGL(k_bluestein_fwd_post, gn, dim3(256), 0, s, none, inl);
+    hipLaunchKernelGGL(k_bluestein_fwd_post, gn, dim3(256), 0, s, none, inl, M);
     e = hipGetLastError();
     if (prof)
         prof->end(s);

@@ -179,6 +179,17 @@ def test_iono_parity_any_length(torch, ctx, orc, n, direction):
         assert err <= TOL, (n, direction, tec_tecu, fc, err)
 
 
+@pytest.mark.parametrize("n", [65536, 70001])
+@pytest.mark.parametrize("scale", [1e-30, 1e30])
+def test_iono_scaled_inputs(torch, ctx, orc, n, scale):
+    """The float32 transforms keep their relative accuracy far from unit power (powers of two
+    and Bluestein)."""
+    x = (wf.bandlimited_noise(n, wf.rng_for(119, n)).astype(np.complex128) * scale).astype(np.complex64)
+    y = host(ctx.correct_ionosphere(dev(torch, x), 10e6, 450e6, 60 * wf.TECU))
+    ref = orc.ionosphere(x, 10e6, 450e6, 60 * wf.TECU, "correct", naive=False)
+    assert rel_l2(y, ref) <= TOL, (n, scale, rel_l2(y, ref))
+
+
 def test_iono_any_length_in_place_and_round_trip(torch, ctx, orc):
     """Bluestein in place equals out of place bit for bit; at 2^22 + 12345 (the longest serving
     lengths) distort then correct is the identity and the norm is kept."""
