@@ -180,10 +180,12 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
  * during the call only.  mode:
  *   RC_BANK_FARROW           a Farrow filter bank: the 2H-tap FIR of each of 8 Chebyshev
  *                            coefficients of the tap weight in the fractional position runs
- *                            once per input position, then each (hypothesis, output) costs
- *                            an 8-term sum.  Needs a Kaiser or rectangular window,
- *                            1 <= H <= 256 and every alpha in (0, 2]; else RC_ERR_UNSUPPORTED.
- *                            Within ~4e-7 rel-L2 of the direct sum at H = 64 and 128.
+ *                            once per input position (a dense contraction, on the matrix
+ *                            cores: float16 hi/lo split products, float32 accumulation), then
+ *                            each (hypothesis, output) costs an 8-term sum.  Needs a Kaiser or
+ *                            rectangular window, 1 <= H <= 256 and every alpha in (0, 2]; else
+ *                            RC_ERR_UNSUPPORTED.  Within ~4e-7 rel-L2 of the direct sum at
+ *                            H = 64 and 128.
  *   RC_BANK_PER_HYPOTHESIS   every hypothesis as a pulse of correct_pulse_batch (the
  *                            resampling engines of correct_doppler).
  *   RC_BANK_AUTO             the filter bank where it applies, else per hypothesis.
