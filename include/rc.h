@@ -243,14 +243,22 @@ rc_status rc_server_destroy(rc_server srv);
 /* Resampling engine (rc_set_sinc_engine).  Every engine computes the same sum of Eq (17):
  *   RC_SINC_AUTO   matrix cores for the Kaiser taper at H = 64 or 128 and |alpha - 1| <= 6e-5,
  *                  else the vector tile kernel (Kaiser, H <= 256, |alpha - 1| <= 1e-4), else the
- *                  direct float64 sum;
+ *                  direct sum (float64 positions, float32 tap weights and accumulation);
  *   RC_SINC_VALU   never the matrix cores;
- *   RC_SINC_DIRECT always the direct float64 sum (reference-speed path). */
+ *   RC_SINC_DIRECT always the direct sum (reference-speed path). */
 enum { RC_SINC_AUTO = 0, RC_SINC_VALU = 1, RC_SINC_DIRECT = 2 };
 
 /* Select the resampling engine of the context's later calls; RC_ERR_INVALID_ARG for an
  * unknown engine.  The default is RC_SINC_AUTO. */
 rc_status rc_set_sinc_engine(rc_context ctx, int32_t engine);
+
+/* Cap the context's device workspace at `bytes` (0: no cap, the default).  The workspace is
+ * the scratch the calls stage lazily and keep for reuse: descriptor tables, the matrix-core
+ * tile lists, Bluestein's convolution buffers and the filter bank's Z rows.  Twiddle tables,
+ * FFT plans and kernel tables are not counted.  A call whose workspace would grow past the cap
+ * fails with RC_ERR_OUT_OF_MEMORY; workspace already held is kept (a lower cap only stops
+ * further growth).  bytes < 0 gives RC_ERR_INVALID_ARG. */
+rc_status rc_set_mem_budget(rc_context ctx, int64_t bytes);
 
 /* Kernel timing for benchmarks.  While enabled, every kernel the context launches is
  * bracketed by a pair of HIP events recorded on the launch stream.  rc_profile_read waits for

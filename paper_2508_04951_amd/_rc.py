@@ -26,7 +26,8 @@ SYMBOLS = (
     "rc_k2_per_tec", "rc_sync", "correct_doppler", "correct_ionosphere", "correct_pulse_batch",
     "correct_doppler_bank", "rc_server_create", "rc_server_submit", "rc_server_poll", "rc_server_wait",
     "rc_server_stats", "rc_server_reset_stats", "rc_server_destroy",
-    "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine", "replica_spectrum", "compress_pulse",
+    "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine", "rc_set_mem_budget", "replica_spectrum",
+    "compress_pulse",
 )
 KERNELS = ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono",
            "k_fft_strided_inv", "k_mf_tile_list", "k_bluestein", "k_farrow_z", "k_farrow_bank")
@@ -124,6 +125,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.rc_profile_read.restype = c_i32
         lib.rc_set_sinc_engine.argtypes = [p, c_i32]
         lib.rc_set_sinc_engine.restype = c_i32
+        lib.rc_set_mem_budget.argtypes = [p, ctypes.c_int64]
+        lib.rc_set_mem_budget.restype = c_i32
         lib.rc_server_create.argtypes = [p, ctypes.POINTER(RcSinc), c_i64, c_i32, ctypes.POINTER(p)]
         lib.rc_server_submit.argtypes = [p, ctypes.POINTER(RcRequest), ctypes.POINTER(c_i64)]
         lib.rc_server_poll.argtypes = [p, c_i64, ctypes.POINTER(c_i32)]
@@ -222,6 +225,12 @@ class Context:
         st = self._lib.rc_sync(self._h, self._stream(stream))
         if st != RC_OK:
             self._raise(st, "rc_sync")
+
+    def set_mem_budget(self, nbytes: int = 0):
+        """Cap the context's device workspace at nbytes (0: no cap); see rc_set_mem_budget."""
+        st = self._lib.rc_set_mem_budget(self._h, int(nbytes))
+        if st != RC_OK:
+            self._raise(st, "rc_set_mem_budget")
 
     def set_sinc_engine(self, engine: str = "auto"):
         """Resampling engine for later calls: "auto" (matrix cores where eligible), "valu" or

@@ -120,11 +120,25 @@ rc_status reserve_descriptors(rc_context ctx, size_t bytes, size_t extra, void *
         slot.host_cap = cap;
     }
     if (dev_bytes > slot.dev_cap) {
+        size_t cap = grow(dev_bytes);
+        if (ctx->mem_budget > 0) {
+            // the other slots keep their workspace; this one is replaced
+            size_t others = 0;
+            for (int i = 0; i < rc_context_s::kDescSlots; ++i)
+                if (i != ctx->desc_next)
+                    others += ctx->desc[i].dev_cap;
+            const size_t budget = (size_t)ctx->mem_budget;
+            if (others + cap > budget)
+                cap = dev_bytes;  // no rounding up when the budget is tight
+            if (others + cap > budget)
+                return fail(ctx, RC_ERR_OUT_OF_MEMORY,
+                            "workspace of " + std::to_string(others + cap) + " bytes would exceed the memory budget of " +
+                                std::to_string(budget) + " (rc_set_mem_budget)");
+        }
         if (slot.dev)
             (void)hipFree(slot.dev);
         slot.dev = nullptr;
         slot.dev_cap = 0;
-        const size_t cap = grow(dev_bytes);
         if (hipMalloc(&slot.dev, cap) != hipSuccess)
             return fail(ctx, RC_ERR_OUT_OF_MEMORY, "descriptor workspace allocation failed");
         slot.dev_cap = cap;
@@ -1363,6 +1377,17 @@ rc_status rc_set_sinc_engine(rc_context ctx, int32_t engine)
         return fail(ctx, RC_ERR_INVALID_ARG, "unknown sinc engine");
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->sinc_engine = engine;
+    return RC_OK;
+}
+
+rc_status rc_set_mem_budget(rc_context ctx, int64_t bytes)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    if (bytes < 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "the memory budget must be >= 0");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->mem_budget = bytes;
     return RC_OK;
 }
 

@@ -304,4 +304,5 @@ struct rc_context_s {
     int desc_next = 0;
     rc::Profiler prof;
     int sinc_engine = 0;  // RC_SINC_AUTO / RC_SINC_VALU / RC_SINC_DIRECT
+    int64_t mem_budget = 0;  // cap on the slots' device workspace in bytes (rc_set_mem_budget); 0: none
 };

@@ -190,6 +190,28 @@ def test_iono_scaled_inputs(torch, ctx, orc, n, scale):
     assert rel_l2(y, ref) <= TOL, (n, scale, rel_l2(y, ref))
 
 
+def test_memory_budget_caps_the_workspace(torch, orc):
+    """A context capped at 1 MiB of workspace refuses a Bluestein transform that needs 4 MiB
+    (RC_ERR_OUT_OF_MEMORY), still runs a power of two, and runs the Bluestein call once the
+    cap is lifted."""
+    import paper_2508_04951_amd as rc
+
+    c = rc.Context(0)
+    with pytest.raises(ValueError):
+        c.set_mem_budget(-1)
+    c.set_mem_budget(1 << 20)
+    x = wf.bandlimited_noise(70001, wf.rng_for(120, 0))  # M = 2^18: 2 M complex64 = 4 MiB
+    with pytest.raises(rc.RcError) as ei:
+        c.correct_ionosphere(dev(torch, x), 10e6, 450e6, 60 * wf.TECU)
+    assert ei.value.status == 3
+    p2 = wf.bandlimited_noise(4096, wf.rng_for(120, 1))
+    y2 = host(c.correct_ionosphere(dev(torch, p2), 10e6, 450e6, 60 * wf.TECU))
+    assert rel_l2(y2, orc.ionosphere(p2, 10e6, 450e6, 60 * wf.TECU)) <= TOL
+    c.set_mem_budget(0)
+    y = host(c.correct_ionosphere(dev(torch, x), 10e6, 450e6, 60 * wf.TECU))
+    assert rel_l2(y, orc.ionosphere(x, 10e6, 450e6, 60 * wf.TECU, naive=False)) <= TOL
+
+
 def test_iono_any_length_in_place_and_round_trip(torch, ctx, orc):
     """Bluestein in place equals out of place bit for bit; at 2^22 + 12345 (the longest serving
     lengths) distort then correct is the identity and the norm is kept."""
