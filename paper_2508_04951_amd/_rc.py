@@ -146,6 +146,16 @@ def alpha_from_vr(v_r: float) -> float:
     return float(load_library().rc_alpha_from_vr(float(v_r)))
 
 
+def _alpha_or_vr(alpha, v_r) -> float:
+    if (alpha is None) == (v_r is None):
+        raise ValueError("give exactly one of alpha and v_r")
+    if alpha is None:
+        alpha = alpha_from_vr(v_r)
+        if alpha != alpha:  # NaN: |v_r| >= c
+            raise ValueError("|v_r| must be below the speed of light")
+    return float(alpha)
+
+
 def k2_per_tec() -> float:
     """Eq (3): K2/E = e^2/(8 pi^2 m_e eps0) in m^3 s^-2 (librc)."""
     return float(load_library().rc_k2_per_tec())
@@ -256,10 +266,12 @@ class Context:
             out[name] = (ms.value, n.value)
         return out
 
-    def correct_doppler(self, x, alpha: float, sinc: Sinc | None = None, n_out: int | None = None,
-                        fs: float = 1.0, out=None, stream=None):
-        """y[m] = sum_n x[n] h(alpha m - n) (Eq 2 / Eq 17) for m < n_out."""
+    def correct_doppler(self, x, alpha: float | None = None, sinc: Sinc | None = None, n_out: int | None = None,
+                        fs: float = 1.0, out=None, stream=None, *, v_r: float | None = None):
+        """y[m] = sum_n x[n] h(alpha m - n) (Eq 2 / Eq 17) for m < n_out.  Give alpha, or the range
+        rate v_r in m/s (alpha from Eq (1) by rc_alpha_from_vr), not both."""
         torch = _torch()
+        alpha = _alpha_or_vr(alpha, v_r)
         _check_samples(x, "x")
         n_out = x.numel() if n_out is None else int(n_out)
         if out is None:
@@ -334,8 +346,8 @@ class Context:
 
     def correct_pulse_batch(self, x_packed, y_packed, pulses, sinc: Sinc | None = None, stream=None):
         """Per-pulse Doppler then ionosphere over packed buffers; `pulses` is a sequence of
-        dicts with keys off_in, n_in, off_out, n_out, fs, alpha, tec, carrier and optional
-        flags (default Doppler|iono) and direction ("correct"), or a table from pulse_table."""
+        dicts with keys off_in, n_in, off_out, n_out, fs, alpha (or v_r in m/s), tec, carrier and
+        optional flags (default Doppler|iono) and direction ("correct"), or a table from pulse_table."""
         _check_samples(x_packed, "x_packed")
         _check_samples(y_packed, "y_packed")
         arr = pulse_array(pulses)
@@ -469,8 +481,9 @@ def pulse_array(pulses):
     arr = (RcPulse * len(pulses))()
     for i, p in enumerate(pulses):
         d = p.get("direction", "correct")
+        alpha = _alpha_or_vr(p.get("alpha"), p.get("v_r")) if ("alpha" in p or "v_r" in p) else 1.0
         arr[i] = RcPulse(int(p["off_in"]), int(p["n_in"]), int(p["off_out"]), int(p["n_out"]),
-                         float(p["fs"]), float(p.get("alpha", 1.0)), float(p.get("tec", 0.0)),
+                         float(p["fs"]), alpha, float(p.get("tec", 0.0)),
                          float(p.get("carrier", 0.0)), int(p.get("flags", DO_DOPPLER | DO_IONO)),
                          DIRECTIONS[d] if isinstance(d, str) else int(d))
     return arr

@@ -103,6 +103,19 @@ def test_pulse_table_matches_the_dict_packing():
     assert rc.pulse_array(t) is t  # passed through without a copy
 
 
+def test_pulse_dicts_take_a_range_rate():
+    """A pulse may give v_r (m/s) instead of alpha: the library's Eq (1) fills alpha; giving
+    both, or |v_r| >= c, is an argument error."""
+    base = dict(off_in=0, n_in=16, off_out=0, n_out=16, fs=10e6)
+    arr = rc.pulse_array([dict(base, v_r=7500.0), dict(base, alpha=1.25), dict(base)])
+    assert arr[0].alpha == rc.alpha_from_vr(7500.0)
+    assert arr[1].alpha == 1.25 and arr[2].alpha == 1.0
+    with pytest.raises(ValueError):
+        rc.pulse_array([dict(base, v_r=10.0, alpha=1.0)])
+    with pytest.raises(ValueError):
+        rc.pulse_array([dict(base, v_r=3e8)])
+
+
 def test_pulse_table_rejects_other_layouts():
     import numpy as np
 

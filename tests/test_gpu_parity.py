@@ -190,6 +190,18 @@ def test_iono_scaled_inputs(torch, ctx, orc, n, scale):
     assert rel_l2(y, ref) <= TOL, (n, scale, rel_l2(y, ref))
 
 
+def test_doppler_by_range_rate(torch, ctx):
+    """correct_doppler(x, v_r=...) is correct_doppler(x, alpha_from_vr(v_r)), bit for bit."""
+    import paper_2508_04951_amd as rc
+
+    x = dev(torch, wf.bandlimited_noise(5000, wf.rng_for(121, 0)))
+    a = host(ctx.correct_doppler(x, rc.alpha_from_vr(-6500.0), sinc(64)))
+    b = host(ctx.correct_doppler(x, sinc=sinc(64), v_r=-6500.0))
+    assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        ctx.correct_doppler(x, 1.0, sinc(64), v_r=10.0)
+
+
 def test_memory_budget_caps_the_workspace(torch, orc):
     """A context capped at 1 MiB of workspace refuses a Bluestein transform that needs 4 MiB
     (RC_ERR_OUT_OF_MEMORY), still runs a power of two, and runs the Bluestein call once the
