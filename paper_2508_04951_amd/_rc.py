@@ -360,13 +360,16 @@ class Context:
             self._raise(st, "correct_pulse_batch")
         return y_packed
 
-    def correct_doppler_bank(self, x, alphas, sinc: Sinc | None = None, n_out: int | None = None,
-                             mode: str = "auto", fs: float = 1.0, out=None, stream=None):
-        """Row h of the (len(alphas), n_out) result is correct_doppler(x, alphas[h])."""
+    def correct_doppler_bank(self, x, alphas=None, sinc: Sinc | None = None, n_out: int | None = None,
+                             mode: str = "auto", fs: float = 1.0, out=None, stream=None, *, v_r=None):
+        """Row h of the (len(alphas), n_out) result is correct_doppler(x, alphas[h]).  Give the
+        alphas, or the range rates v_r in m/s (Eq (1) by rc_alpha_from_vr), not both."""
         torch = _torch()
         _check_samples(x, "x")
         n_out = x.numel() if n_out is None else int(n_out)
-        a = _bank_alphas(alphas)
+        if (alphas is None) == (v_r is None):
+            raise ValueError("give exactly one of alphas and v_r")
+        a = _bank_alphas(alphas if alphas is not None else [_alpha_or_vr(None, v) for v in v_r])
         if out is None:
             out = torch.empty((len(a), n_out), dtype=torch.complex64, device=x.device)
         _check_samples(out, "out")

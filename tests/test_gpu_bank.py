@@ -86,6 +86,18 @@ def test_bank_input_scale(torch, ctx, orc, scale):
         assert rel_l2(y[h], ref) <= TOL, (scale, h, rel_l2(y[h], ref))
 
 
+def test_bank_by_range_rates(torch, ctx):
+    import paper_2508_04951_amd as rc
+
+    x = dev(torch, wf.polyphase_code(4000, wf.rng_for(204, 0)))
+    v = [-7000.0, 0.0, 123.4, 8000.0]
+    a = host(ctx.correct_doppler_bank(x, [rc.alpha_from_vr(q) for q in v], rc.Sinc(64, "kaiser", 8.0)))
+    b = host(ctx.correct_doppler_bank(x, sinc=rc.Sinc(64, "kaiser", 8.0), v_r=v))
+    assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        ctx.correct_doppler_bank(x, [1.0], v_r=[0.0])
+
+
 def test_bank_rows_follow_the_given_order(torch, ctx):
     """Hypotheses in any order land in their own rows (the filter bank sorts them internally)."""
     import paper_2508_04951_amd as rc
