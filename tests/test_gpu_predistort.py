@@ -57,6 +57,20 @@ def test_gpu_correction_is_the_cubic_predistortion(torch, ctx, orc, waves):
     assert abs(loss_gpu - loss_orc) < 1e-5  # float32 transforms: ~1e-7 relative per sample
 
 
+def test_gpu_bluestein_correction_is_the_cubic_predistortion(torch, ctx, orc):
+    """The same check on a record of 500000 samples, which takes Bluestein's path."""
+    n = 500000
+    n0 = n // 4
+    k2 = pd.k2_from_tec(E)
+    lfm = pd.lfm(n, n0, FS, F0, BW, T).astype(np.complex64)
+    cubic = pd.cubic_waveform(n, n0, FS, F0, BW, T, k2)
+    y = host(torch, ctx.correct_ionosphere(dev(torch, lfm), FS, 0.0, E, "correct"))
+    loss_gpu = pd.snr_loss_db(cubic, y)
+    loss_orc = pd.snr_loss_db(cubic, orc.ionosphere(lfm, FS, 0.0, E, "correct", naive=False))
+    assert loss_gpu < LOSS_MAX_DB
+    assert abs(loss_gpu - loss_orc) < 1e-5
+
+
 def test_gpu_distortion_of_the_predistortion_is_the_lfm(torch, ctx, waves):
     y = host(torch, ctx.correct_ionosphere(dev(torch, waves["cubic"]), FS, 0.0, E, "distort"))
     assert pd.snr_loss_db(waves["lfm"].astype(np.complex128), y) < LOSS_MAX_DB
