@@ -57,6 +57,20 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_c_example() -> str:
+    """tests/c_abi_example.c -> tests/c_abi_example, linked against librc.so (rpath relative to
+    the executable) and the HIP runtime."""
+    src = os.path.join(ROOT, "tests", "c_abi_example.c")
+    exe = os.path.join(ROOT, "tests", "c_abi_example")
+    cmd = [hipcc(), "-x", "c", "-std=c11", "-O2", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE, "-I", "/opt/rocm/include",
+           src, "-x", "none", "-o", exe, "-L", PKG, "-lrc", "-L", "/opt/rocm/lib", "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN/../paper_2508_04951_amd", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"building the C example failed:\n{r.stderr}")
+    return exe
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
