@@ -266,3 +266,100 @@ def test_doppler_at_matches_full(orc):
     a = orc.alpha_from_vr(-6000.0)
     idx = np.array([0, 1, 5, 700, 2047, 1500])
     np.testing.assert_array_equal(orc.doppler_at(x, idx, a, 64), orc.doppler(x, a, 64)[idx])
+
+
+# --- Impulse responses: the tap sets of Eq (17) / App. C written from the definitions ---------
+
+def _impulse_expected(n, n0, alpha, hw, window, beta):
+    """Output of a unit impulse at n0, from the definitions alone: numpy's sinc and I0.
+
+    full sum (hw = 0): sinc(t - n0);
+    Kaiser: sinc(t - n0) K((t - n0)/H) when |t - n0| < H (the 2H inputs floor(t)-H+1 ..
+      floor(t)+H are exactly those within H of t), else 0;
+    rect: sinc(t - n0) on the same 2H inputs;
+    paper mode (App. C, Fig. 10: N_w = 2H+1 inputs centred on the nearest sample c = floor(t + 1/2)):
+      sinc(t - n0) when |c - n0| <= H, else 0.
+    An exact sample instant t = n0 gives 1, any other integer t gives 0."""
+    y = np.zeros(n)
+    for m in range(n):
+        t = alpha * m
+        if t == math.floor(t):
+            y[m] = 1.0 if t == n0 else 0.0
+            continue
+        u = t - n0
+        if hw == 0:
+            y[m] = np.sinc(u)
+        elif window == "paper":
+            y[m] = np.sinc(u) if abs(math.floor(t + 0.5) - n0) <= hw else 0.0
+        elif abs(u) < hw:
+            w = np.sinc(u)
+            if window == "kaiser":
+                w *= np.i0(beta * math.sqrt(1.0 - (u / hw) ** 2)) / np.i0(beta)
+            y[m] = w
+    return y
+
+
+IMPULSE_KERNELS = [(0, "kaiser"), (1, "kaiser"), (3, "kaiser"), (8, "kaiser"), (1, "rect"), (2, "rect"),
+                   (5, "rect"), (1, "paper"), (2, "paper"), (3, "paper"), (12, "paper")]
+IMPULSE_ALPHAS = [1.3, 0.77, 1.00005, 2.5, 0.999]
+
+
+def _impulse_deviation(doppler):
+    """Largest |oracle - definition| over every kernel, alpha and impulse position."""
+    n, worst = 64, 0.0
+    for hw, window in IMPULSE_KERNELS:
+        for alpha in IMPULSE_ALPHAS:
+            for n0 in (0, 1, 20, 41, 62, 63):
+                x = np.zeros(n, np.complex128)
+                x[n0] = 1.0
+                got = doppler(x, alpha, hw, window, 6.0)
+                exp = _impulse_expected(n, n0, alpha, hw, window, 6.0)
+                worst = max(worst, float(np.max(np.abs(got - exp))))
+    return worst
+
+
+def test_impulse_response_is_the_kernel(orc):
+    """Every output of a unit impulse is the kernel of Eq (17) at t - n0, with the tap set of
+    its window (2H inputs around t; 2H + 1 around the nearest input in paper mode)."""
+    assert _impulse_deviation(lambda x, a, h, w, b: orc.doppler(x, a, h, w, b)) <= 1e-13
+
+
+def _mutant_doppler(tmp_path, old, new):
+    """The oracle's C with one planted mistake, built on the CPU into a private library."""
+    import ctypes
+    import os
+    import subprocess
+
+    import oracle
+
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "rc_oracle.c")).read()
+    assert src.count(old) == 1, old
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-o", str(so),
+                    str(path), "-lm"], check=True)
+    lib = ctypes.CDLL(str(so))
+    p, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.rco_doppler.restype = i32
+    lib.rco_doppler.argtypes = [p, i64, p, i64, d, i32, i32, d]
+
+    def doppler(x, alpha, hw, window, beta):
+        xin = np.ascontiguousarray(x, np.complex128)
+        y = np.zeros(xin.size, np.complex128)
+        assert lib.rco_doppler(xin.ctypes.data, xin.size, y.ctypes.data, y.size, alpha, hw,
+                               oracle.WINDOWS[window], beta) == 0
+        return y
+
+    return doppler
+
+
+@pytest.mark.parametrize("old,new", [
+    ("(int64_t)floor(t + 0.5)", "(int64_t)floor(t)"),          # paper-mode centre at floor(t)
+    ("lo = c - half_width;", "lo = c - half_width + 1;"),       # paper mode one tap short
+    ("lo = (int64_t)f - half_width + 1;", "lo = (int64_t)f - half_width;"),  # 2H+1 taps
+    ("hi = (int64_t)f + half_width;", "hi = (int64_t)f + half_width - 1;"),  # 2H-1 taps
+])
+def test_impulse_pin_catches_planted_tap_set_mistakes(tmp_path, old, new):
+    """The impulse pin fails for an oracle with a planted one-tap mistake in its tap sets."""
+    assert _impulse_deviation(_mutant_doppler(tmp_path, old, new)) > 1e-3
