@@ -442,18 +442,21 @@ __device__ __forceinline__ PhaseK phase_consts(const IonoJob &jb, int64_t n)
 __device__ __forceinline__ float2 phase_at(const PhaseK &P, int64_t kk)
 {
     const double f = fma(P.fs_n, (double)kk, P.carrier);
-    // 1/f from the hardware reciprocal (relative error below 2^-24 on gfx950) and one Newton step,
-    // which squares that error: below 2^-48, i.e. under 1e-9 quarter turn for |t4| < 2^17 (the IEEE
-    // division sequence costs ~70 extra registers here).  The phase t4 = c4 / f, in quarter turns
-    // (|t4| is ~1e2..1e5), is split in float64 into a whole number n4 and a remainder w in
-    // [-1/2, 1/2] (exact); cis(pi w / 2) in float32 is then turned by n4 quarter turns.
+    // The phase t4 = c4 / f in quarter turns.  1/f comes from the hardware reciprocal (relative
+    // error below 2^-24 on gfx950) and one Newton step (below 2^-48); the quotient then takes one
+    // residual correction, t4 += (c4 - t4 f) / f, which leaves it within a few ulp of c4 / f (the
+    // IEEE division sequence costs ~70 extra registers here).  Near f = 0 (a carrier below fs/2)
+    // |t4| reaches ~1e12, where 2^-48 alone would be ~4e-3 quarter turn.
     double rf = __builtin_amdgcn_rcp(f);
     rf = fma(rf, fma(-f, rf, 1.0), rf);
-    const double t4 = P.c4 * rf;
+    double t4 = P.c4 * rf;
+    t4 = fma(fma(-t4, f, P.c4), rf, t4);
+    // t4 splits exactly into a whole number n4 and a remainder w in [-1/2, 1/2] (both exact for
+    // |t4| < 2^52); cis(pi w / 2) in float32 is then turned by n4 quarter turns.
     const double n4 = rint(t4);
     const float2 w = cis_quarter((float)(t4 - n4));
-    // n4 mod 4 (beyond 2^30 quarter turns the float64 phase has no fractional bits left anyway)
-    const int quad = (int)fmin(fmax(n4, -0x1p30), 0x1p30) & 3;
+    // n4 mod 4, exact in float64: n4/4, its floor and 4 floor(n4/4) are all exact integers.
+    const int quad = (int)(n4 - 4.0 * floor(0.25 * n4));
     const float c = (quad & 1) ? -w.y : w.x;  // (c, s) turned by quad * 90 degrees
     const float sn = (quad & 1) ? w.x : w.y;
     if (f == 0.0)

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import waveforms as wf
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -78,15 +79,55 @@ def test_server_mixed_stream_equals_single_calls(torch, ctx, orc):
     assert st["batches"] >= 1 and 1.0 <= st["mean_batch"] <= 7.0
     assert 0.0 < st["latency_ms_p50"] <= st["latency_ms_p99"] <= st["latency_ms_max"]
     assert st["samples_per_s"] > 0
-    # spot-check two requests against the oracle
-    for i in (0, 4):
+    # every request against the oracle
+    for i in range(len(reqs)):
         r, x, y = reqs[i]
         xh = x.cpu().numpy()
         ref = orc.correct_pulse(xh, 10e6, r["alpha"], r["tec"], 450e6, n_out=r["n_out"], half_width=64,
                                 doppler_on=bool(r["flags"] & rc.DO_DOPPLER), iono_on=bool(r["flags"] & rc.DO_IONO),
                                 direction=r["direction"])
         got = y.cpu().numpy()
-        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5, i
+        check(got, ref, what=i)
+    srv.close()
+
+
+def test_server_long_requests_against_the_oracle(torch, ctx, orc):
+    """Requests up to the serving workload's longest length (2^22) and lengths that are not
+    powers of two, submitted back to back so that they share batches: every request against the
+    oracle (the full pulse, or, for the two longest Doppler-only requests, sampled outputs of the
+    direct sum) and bit for bit against its single-pulse calls."""
+    import paper_2508_04951_amd as rc
+
+    rng = wf.rng_for(303, 0)
+    lens = [1 << 22, (1 << 22) - 12345, 1 << 20, 3000001, 70001, 1 << 16, 4096, 262143]
+    flag_set = [rc.DO_DOPPLER | rc.DO_IONO, rc.DO_DOPPLER, rc.DO_IONO, rc.DO_DOPPLER | rc.DO_IONO, rc.DO_IONO,
+                rc.DO_DOPPLER | rc.DO_IONO, rc.DO_DOPPLER, rc.DO_DOPPLER | rc.DO_IONO]
+    k = rc.Sinc(64, "kaiser", 8.0)
+    srv = rc.Server(ctx, k, mem_budget_bytes=1 << 33, max_batch=16)
+    reqs = []
+    for i, (n, flags) in enumerate(zip(lens, flag_set)):
+        r = dict(n=n, n_out=n, alpha=alpha_exact(rng.uniform(-8000, 8000)), tec=rng.uniform(5, 100) * wf.TECU,
+                 flags=flags, direction="distort" if i == 4 else "correct")
+        xh = wf.bandlimited_noise(n, wf.rng_for(303, i + 1))
+        x = dev(torch, xh)
+        y = torch.full((n,), complex("nan"), dtype=torch.complex64, device="cuda")
+        torch.cuda.synchronize()
+        srv.submit(x, y, alpha=r["alpha"], tec=r["tec"], carrier=450e6, fs=10e6, flags=flags,
+                   direction=r["direction"])
+        reqs.append((r, xh, x, y))
+    srv.wait()
+    for i, (r, xh, x, y) in enumerate(reqs):
+        got = y.cpu().numpy()
+        assert np.array_equal(got, alone(torch, ctx, x, r, k)), i
+        if r["flags"] == rc.DO_DOPPLER and r["n"] > (1 << 18):
+            idx = np.concatenate([np.arange(3000), np.arange(r["n"] - 3000, r["n"]),
+                                  wf.rng_for(303, 100 + i).integers(0, r["n"], 6000)])
+            check(got[idx], orc.doppler_at(xh, idx, r["alpha"], 64, "kaiser", 8.0), what=i)
+        else:
+            ref = orc.correct_pulse(xh, 10e6, r["alpha"], r["tec"], 450e6, n_out=r["n_out"], half_width=64,
+                                    doppler_on=bool(r["flags"] & rc.DO_DOPPLER),
+                                    iono_on=bool(r["flags"] & rc.DO_IONO), direction=r["direction"])
+            check(got, ref, what=i)
     srv.close()
 
 
