@@ -174,28 +174,41 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
 
 /* A bank of Doppler hypotheses on one pulse (many alpha on the same input):
  *   y[h * n_out + m] = sum_n x[n] h(alphas[h] m - n),  h < n_hyp, m < n_out,
- * each row exactly the correct_doppler result for its alpha up to float32 rounding (the same
- * Eq (17) sum; the exact-integer rule is kept).  x: n device samples; y: n_hyp * n_out device
- * samples, must not overlap x; alphas: HOST array of n_hyp values, finite and > 0, read
- * during the call only.  mode:
- *   RC_BANK_FARROW           a Farrow filter bank: the 2H-tap FIR of each of 8 Chebyshev
- *                            coefficients of the tap weight in the fractional position runs
- *                            once per input position (a dense contraction, on the matrix
- *                            cores: float16 hi/lo split products, float32 accumulation), then
- *                            each (hypothesis, output) costs an 8-term sum.  Needs a Kaiser or
- *                            rectangular window, 1 <= H <= 256 and every alpha in (0, 2]; else
- *                            RC_ERR_UNSUPPORTED.  Within ~4e-7 rel-L2 of the direct sum at
- *                            H = 64 and 128.
- *   RC_BANK_PER_HYPOTHESIS   every hypothesis as a pulse of correct_pulse_batch (the
- *                            resampling engines of correct_doppler).
- *   RC_BANK_AUTO             the filter bank where it applies, else per hypothesis.
- * The filter bank's workspace (8 complex values per input position) comes from the context.
- * This extends the paper (one alpha per pulse) to the hypothesis search of a
- * Doppler-ambiguous return; the operator per row is Eq (2) with Eq (17). */
-enum { RC_BANK_AUTO = 0, RC_BANK_FARROW = 1, RC_BANK_PER_HYPOTHESIS = 2 };
+ * each row the correct_doppler result for its alpha (the same Eq (17) sum; the exact-integer
+ * rule is kept).  x: n device samples; y: n_hyp * n_out device samples, must not overlap x;
+ * alphas: HOST array of n_hyp values, finite and > 0, read during the call only.
+ *
+ * The filter bank: each tap weight h(mu - j) is a degree-7 polynomial in the fractional position
+ * mu, so the 2H-tap FIR of each of its 8 coefficients runs once per input position (a dense
+ * contraction on the matrix cores) and every (hypothesis, output) then costs an 8-term sum.  It
+ * needs a Kaiser or rectangular window, 1 <= H <= 256 and every alpha in (0, 2]; elsewhere the bank
+ * runs every hypothesis as a pulse of correct_pulse_batch (see rc_set_bank_engine).
+ *
+ * precision selects the arithmetic of the filter bank's contraction (float32 accumulation in all
+ * three; the per-output sums are float32):
+ *   RC_BANK_FP16X3  samples and coefficients split into float16 hi + lo after power-of-two scaling,
+ *                   hi*hi + hi*lo + lo*hi (+ lo*lo) products: ~3e-7 rel-L2 against the float64
+ *                   direct sum at H = 64 and 128 (the default, and the fastest);
+ *   RC_BANK_BF16X3  the same split in bfloat16 (float32's exponent range, 8-bit significands):
+ *                   ~4e-6 rel-L2;
+ *   RC_BANK_FP32    float32 products on the float32 matrix cores: ~3e-7 rel-L2.
+ * The per-hypothesis engine ignores precision (float32-accurate resampling engines).
+ * Every mode stays within 1e-5 rel-L2 of the float64 direct sum.  The filter bank's workspace
+ * (8 complex values per input position) comes from the context.  This extends the paper (one
+ * alpha per pulse) to the hypothesis search of a Doppler-ambiguous return; the operator per row
+ * is Eq (2) with Eq (17). */
+enum { RC_BANK_FP16X3 = 0, RC_BANK_BF16X3 = 1, RC_BANK_FP32 = 2 };
 rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c64 *y,
                                int64_t n_out, double fs_hz, const double *alphas, int32_t n_hyp,
-                               const rc_sinc *k, int32_t mode, void *stream);
+                               const rc_sinc *k, int32_t precision, void *stream);
+
+/* Engine of the context's later correct_doppler_bank calls:
+ *   RC_BANK_ENGINE_AUTO            the filter bank where it applies, else per hypothesis (default);
+ *   RC_BANK_ENGINE_FARROW          always the filter bank: RC_ERR_UNSUPPORTED where it does not apply;
+ *   RC_BANK_ENGINE_PER_HYPOTHESIS  every hypothesis as a pulse of correct_pulse_batch.
+ * RC_ERR_INVALID_ARG for an unknown engine. */
+enum { RC_BANK_ENGINE_AUTO = 0, RC_BANK_ENGINE_FARROW = 1, RC_BANK_ENGINE_PER_HYPOTHESIS = 2 };
+rc_status rc_set_bank_engine(rc_context ctx, int32_t engine);
 
 /* Serving: a continuous-batching server over independent requests (the paper corrects one
  * pulse at a time; a radar front end sees a stream of them).  Each request is one pulse,

@@ -26,12 +26,13 @@ SYMBOLS = (
     "rc_k2_per_tec", "rc_sync", "correct_doppler", "correct_ionosphere", "correct_pulse_batch",
     "correct_doppler_bank", "rc_server_create", "rc_server_submit", "rc_server_poll", "rc_server_wait",
     "rc_server_stats", "rc_server_reset_stats", "rc_server_destroy",
-    "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine", "rc_set_mem_budget", "replica_spectrum",
-    "compress_pulse",
+    "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine", "rc_set_bank_engine", "rc_set_mem_budget",
+    "replica_spectrum", "compress_pulse",
 )
 KERNELS = ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono",
            "k_fft_strided_inv", "k_mf_tile_list", "k_bluestein", "k_farrow_z", "k_farrow_bank")
-BANK_MODES = {"auto": 0, "farrow": 1, "per_hypothesis": 2}
+BANK_PRECISIONS = {"fp16x3": 0, "bf16x3": 1, "fp32": 2}
+BANK_ENGINES = {"auto": 0, "farrow": 1, "per_hypothesis": 2}
 SINC_ENGINES = {"auto": 0, "valu": 1, "direct": 2}
 
 
@@ -125,6 +126,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.rc_profile_read.restype = c_i32
         lib.rc_set_sinc_engine.argtypes = [p, c_i32]
         lib.rc_set_sinc_engine.restype = c_i32
+        lib.rc_set_bank_engine.argtypes = [p, c_i32]
+        lib.rc_set_bank_engine.restype = c_i32
         lib.rc_set_mem_budget.argtypes = [p, ctypes.c_int64]
         lib.rc_set_mem_budget.restype = c_i32
         lib.rc_server_create.argtypes = [p, ctypes.POINTER(RcSinc), c_i64, c_i32, ctypes.POINTER(p)]
@@ -244,10 +247,21 @@ class Context:
 
     def set_sinc_engine(self, engine: str = "auto"):
         """Resampling engine for later calls: "auto" (matrix cores where eligible), "valu" or
-        "direct" (the float64 direct sum)."""
+        "direct" (the direct sum: float64 positions, float32 tap weights)."""
+        if engine not in SINC_ENGINES:
+            raise ValueError(f"engine must be one of {list(SINC_ENGINES)}")
         st = self._lib.rc_set_sinc_engine(self._h, SINC_ENGINES[engine])
         if st != RC_OK:
             self._raise(st, "rc_set_sinc_engine")
+
+    def set_bank_engine(self, engine: str = "auto"):
+        """Engine of later correct_doppler_bank calls: "auto" (the filter bank where it applies),
+        "farrow" (always the filter bank; RcError where it does not apply) or "per_hypothesis"."""
+        if engine not in BANK_ENGINES:
+            raise ValueError(f"engine must be one of {list(BANK_ENGINES)}")
+        st = self._lib.rc_set_bank_engine(self._h, BANK_ENGINES[engine])
+        if st != RC_OK:
+            self._raise(st, "rc_set_bank_engine")
 
     def profile(self, enable: bool = True):
         """Bracket every kernel launch with HIP events on its stream (for benchmarks)."""
@@ -361,9 +375,11 @@ class Context:
         return y_packed
 
     def correct_doppler_bank(self, x, alphas=None, sinc: Sinc | None = None, n_out: int | None = None,
-                             mode: str = "auto", fs: float = 1.0, out=None, stream=None, *, v_r=None):
+                             precision: str = "fp16x3", fs: float = 1.0, out=None, stream=None, *, v_r=None):
         """Row h of the (len(alphas), n_out) result is correct_doppler(x, alphas[h]).  Give the
-        alphas, or the range rates v_r in m/s (Eq (1) by rc_alpha_from_vr), not both."""
+        alphas, or the range rates v_r in m/s (Eq (1) by rc_alpha_from_vr), not both.  precision
+        is the filter bank's contraction: "fp16x3", "bf16x3" or "fp32" (set_bank_engine picks the
+        filter bank or per-hypothesis resampling)."""
         torch = _torch()
         _check_samples(x, "x")
         n_out = x.numel() if n_out is None else int(n_out)
@@ -375,11 +391,12 @@ class Context:
         _check_samples(out, "out")
         if out.numel() < len(a) * n_out:
             raise ValueError("out is shorter than len(alphas) * n_out")
-        if mode not in BANK_MODES:
-            raise ValueError(f"mode must be one of {list(BANK_MODES)}")
+        if precision not in BANK_PRECISIONS:
+            raise ValueError(f"precision must be one of {list(BANK_PRECISIONS)}")
         k = (sinc or Sinc()).c()
         st = self._lib.correct_doppler_bank(self._h, x.data_ptr(), x.numel(), out.data_ptr(), n_out, float(fs), a,
-                                            len(a), ctypes.byref(k), BANK_MODES[mode], self._stream(stream))
+                                            len(a), ctypes.byref(k), BANK_PRECISIONS[precision],
+                                            self._stream(stream))
         if st != RC_OK:
             self._raise(st, "correct_doppler_bank")
         return out

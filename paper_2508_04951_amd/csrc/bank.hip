@@ -78,14 +78,19 @@ __global__ void __launch_bounds__(256) k_farrow_coef(KaiserPoly kp, int H, int t
 
 // Z[f][r] for f in [0, F) on the matrix cores: for 16 consecutive positions p0 + i the filter
 // bank is the product of the Hankel matrix A[i][t] = x[p0 + i - H + 1 + t] (16 x 2H) and the
-// coefficient matrix C[t][r] (2H x 8), taken 32 taps per v_mfma_f32_16x16x32_f16.  Both operands
-// are split into float16 hi + lo parts after exact power-of-two scaling (the samples by a
-// workgroup-wide exponent, the coefficients by 2^kZCoefExp).  The B operand holds C_hi in columns
-// 0..7 and C_lo in columns 8..15, so the two products A_hi B and A_lo B of one accumulator give
-// A (C_hi + C_lo) once the column halves are added: A_hi C_hi + A_hi C_lo + A_lo C_hi (+ A_lo C_lo)
-// in float32, about 22 bits per product.  A row i of the Hankel matrix starts at span offset i,
-// which is 16-byte aligned only for i % 8 == 0, so the span is staged as 8 copies shifted by
-// 0..7 samples and row i reads copy i % 8 at the aligned offset i - i % 8.
+// coefficient matrix C[t][r] (2H x 8).  Three precisions (rc_bank_precision):
+//   FP16X3, BF16X3  32 taps per v_mfma_f32_16x16x32_f16 / _bf16.  Both operands are split into
+//                   half-precision hi + lo parts after exact power-of-two scaling (the samples by a
+//                   workgroup-wide exponent, the coefficients by 2^kZCoefExp).  The B operand holds
+//                   C_hi in columns 0..7 and C_lo in columns 8..15, so the two products A_hi B and
+//                   A_lo B of one accumulator give A (C_hi + C_lo) once the column halves are added:
+//                   A_hi C_hi + A_hi C_lo + A_lo C_hi (+ A_lo C_lo) in float32, about 22 bits per
+//                   product with float16 (11-bit significands) and about 16 with bfloat16 (8-bit).
+//                   A row i of the Hankel matrix starts at span offset i, which is 16-byte aligned
+//                   only for i % 8 == 0, so the span is staged as 8 copies shifted by 0..7 samples
+//                   and row i reads copy i % 8 at the aligned offset i - i % 8.
+//   FP32            4 taps per v_mfma_f32_16x16x4_f32 on the float32 samples and coefficients
+//                   (k_farrow_z_f32), columns 8..15 of B unused.
 constexpr int kZPos = 256;                                   // positions per workgroup
 constexpr int kZCoefExp = 12;
 
@@ -98,24 +103,47 @@ size_t farrow_z_lds_bytes(int H)
     return (L + 8) * sizeof(float2) + 8 * 4 * L * sizeof(_Float16) + 16;
 }
 
-typedef _Float16 zhalf8 __attribute__((ext_vector_type(8)));
 typedef float zfloatx4 __attribute__((ext_vector_type(4)));
+
+// The half-precision element, its 8-wide MFMA operand and the 16x16x32 product of a precision.
+template <int P>
+struct ZHalf;
+template <>
+struct ZHalf<RC_BANK_FP16X3> {
+    typedef _Float16 T;
+    typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+    static __device__ __forceinline__ zfloatx4 mfma(v8 a, v8 b, zfloatx4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct ZHalf<RC_BANK_BF16X3> {
+    typedef __bf16 T;
+    typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+    static __device__ __forceinline__ zfloatx4 mfma(v8 a, v8 b, zfloatx4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
 
 // Persistent: each workgroup builds its B fragments once, then walks blocks of kZPos positions
 // (blockIdx.x, + gridDim.x, ...), loading the next block's span into registers while the
 // current block's products run.  KS bounds the 32-tap steps (4, 8 or 16: H <= 64, 128, 256),
-// which sets the registers the fragments and the prefetch hold.
-template <int KS>
+// which sets the registers the fragments and the prefetch hold; P the half precision.
+template <int KS, int P>
 __global__ void __launch_bounds__(256) k_farrow_z(const float2 *__restrict__ x, int64_t n, int64_t F, int H,
                                                   const float *__restrict__ coef, float2 *__restrict__ Z)
 {
+    typedef typename ZHalf<P>::T half_t;
+    typedef typename ZHalf<P>::v8 half8;
     constexpr int kZMaxSteps = KS;
     constexpr int kZPrefetch = (kZPos + 32 * KS + 8 + 255) / 256;  // span samples per thread
     extern __shared__ __attribute__((aligned(16))) float2 smem_z[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ksteps = farrow_z_steps(H), L = farrow_z_span(H);
     float2 *stage = smem_z;                                                  // L + 8 samples
-    _Float16 *copies = reinterpret_cast<_Float16 *>(stage + L + 8);          // [8 shifts][4 planes][L]
+    half_t *copies = reinterpret_cast<half_t *>(stage + L + 8);              // [8 shifts][4 planes][L]
     float *wmax = reinterpret_cast<float *>(copies + 8 * 4 * L);             // 4 wave maxima
     const int64_t nblk = (F + kZPos - 1) / kZPos;
     // the span of block b: sample k is x[b kZPos - H + 1 + k], zero outside [0, n)
@@ -133,7 +161,7 @@ __global__ void __launch_bounds__(256) k_farrow_z(const float2 *__restrict__ x, 
     // B fragments (this lane's column: order r = col % 8, hi part for col < 8, lo part above),
     // built once while the first span is in flight
     const int col = lane & 15, q = lane >> 4;
-    zhalf8 bfrag[kZMaxSteps];
+    half8 bfrag[kZMaxSteps];
 #pragma unroll
     for (int st = 0; st < kZMaxSteps; ++st) {
         if (st < ksteps) {
@@ -141,13 +169,13 @@ __global__ void __launch_bounds__(256) k_farrow_z(const float2 *__restrict__ x, 
             for (int j = 0; j < 8; ++j) {
                 const int t = 32 * st + 8 * q + j;
                 const float c = t < 2 * H ? ldexpf(gload(coef, (int64_t)t * kR + (col & 7)), kZCoefExp) : 0.f;
-                const _Float16 hi = (_Float16)c;
-                bfrag[st][j] = col < 8 ? hi : (_Float16)(c - (float)hi);
+                const half_t hi = (half_t)c;
+                bfrag[st][j] = col < 8 ? hi : (half_t)(c - (float)hi);
             }
         }
     }
     const int i = col;  // A row (position within a tile) of this lane
-    const _Float16 *cbase = copies + (size_t)(i & 7) * 4 * L + (i & ~7) + 8 * q;
+    const half_t *cbase = copies + (size_t)(i & 7) * 4 * L + (i & ~7) + 8 * q;
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         float m = 0.f;
 #pragma unroll
@@ -174,12 +202,12 @@ __global__ void __launch_bounds__(256) k_farrow_z(const float2 *__restrict__ x, 
             for (int c = 0; c < 8; ++c) {
                 const float2 v = stage[k + c];
                 const float re = ldexpf(v.x, sexp), im = ldexpf(v.y, sexp);
-                const _Float16 rh = (_Float16)re, ih = (_Float16)im;
-                _Float16 *cp = copies + (size_t)c * 4 * L + k;
+                const half_t rh = (half_t)re, ih = (half_t)im;
+                half_t *cp = copies + (size_t)c * 4 * L + k;
                 cp[0] = rh;
-                cp[L] = (_Float16)(re - (float)rh);
+                cp[L] = (half_t)(re - (float)rh);
                 cp[2 * L] = ih;
-                cp[3 * L] = (_Float16)(im - (float)ih);
+                cp[3 * L] = (half_t)(im - (float)ih);
             }
         }
         __syncthreads();
@@ -192,14 +220,14 @@ __global__ void __launch_bounds__(256) k_farrow_z(const float2 *__restrict__ x, 
             for (int st = 0; st < kZMaxSteps; ++st) {
                 if (st < ksteps) {
                     const int off = 16 * tile + 32 * st;  // a multiple of 8 halves: 16-byte aligned
-                    const zhalf8 arh = *reinterpret_cast<const zhalf8 *>(cbase + off);
-                    const zhalf8 arl = *reinterpret_cast<const zhalf8 *>(cbase + L + off);
-                    const zhalf8 aih = *reinterpret_cast<const zhalf8 *>(cbase + 2 * L + off);
-                    const zhalf8 ail = *reinterpret_cast<const zhalf8 *>(cbase + 3 * L + off);
-                    acc_re = __builtin_amdgcn_mfma_f32_16x16x32_f16(arh, bfrag[st], acc_re, 0, 0, 0);
-                    acc_im = __builtin_amdgcn_mfma_f32_16x16x32_f16(aih, bfrag[st], acc_im, 0, 0, 0);
-                    acc_re = __builtin_amdgcn_mfma_f32_16x16x32_f16(arl, bfrag[st], acc_re, 0, 0, 0);
-                    acc_im = __builtin_amdgcn_mfma_f32_16x16x32_f16(ail, bfrag[st], acc_im, 0, 0, 0);
+                    const half8 arh = *reinterpret_cast<const half8 *>(cbase + off);
+                    const half8 arl = *reinterpret_cast<const half8 *>(cbase + L + off);
+                    const half8 aih = *reinterpret_cast<const half8 *>(cbase + 2 * L + off);
+                    const half8 ail = *reinterpret_cast<const half8 *>(cbase + 3 * L + off);
+                    acc_re = ZHalf<P>::mfma(arh, bfrag[st], acc_re);
+                    acc_im = ZHalf<P>::mfma(aih, bfrag[st], acc_im);
+                    acc_re = ZHalf<P>::mfma(arl, bfrag[st], acc_re);
+                    acc_im = ZHalf<P>::mfma(ail, bfrag[st], acc_im);
                 }
             }
             // lane (col, q) holds rows 4 q + k of column col: add the lo half (col + 8) to the hi half
@@ -213,6 +241,54 @@ __global__ void __launch_bounds__(256) k_farrow_z(const float2 *__restrict__ x, 
             }
         }
         __syncthreads();  // stage, copies and wmax are rewritten for the next block
+    }
+}
+
+// Z[f][r] in float32 on the matrix cores: per 16-position tile, v_mfma_f32_16x16x4_f32 over 4 taps
+// at a time, lane (i, q) = (lane % 16, lane / 16) holding A[i][4 st + q] = x[p0 + i - H + 1 + 4 st + q]
+// and B[4 st + q][col] = C[4 st + q][col] (zero for col >= 8).  One workgroup per block of kZPos
+// positions: the span and the coefficient matrix are staged in LDS once.
+size_t farrow_z_f32_lds_bytes(int H)
+{
+    return (size_t)(kZPos + 2 * H + 4) * sizeof(float2) + (size_t)(2 * H + 4) * kR * sizeof(float);
+}
+
+__global__ void __launch_bounds__(256) k_farrow_z_f32(const float2 *__restrict__ x, int64_t n, int64_t F, int H,
+                                                      const float *__restrict__ coef, float2 *__restrict__ Z)
+{
+    extern __shared__ __attribute__((aligned(16))) float2 smem_z32[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int taps = 2 * H, steps = (taps + 3) / 4;
+    const int L = kZPos + 4 * steps;                                          // span samples
+    float2 *span = smem_z32;
+    float *cl = reinterpret_cast<float *>(span + L);                          // [4 steps][8], zero-padded
+    const int64_t f0 = (int64_t)blockIdx.x * kZPos, g0 = f0 - H + 1;
+    for (int k = tid; k < L; k += 256) {
+        const int64_t g = g0 + k;
+        span[k] = (g >= 0 && g < n) ? gload(x, g) : make_float2(0.f, 0.f);
+    }
+    for (int e = tid; e < 4 * steps * kR; e += 256)
+        cl[e] = e < taps * kR ? gload(coef, (int64_t)e) : 0.f;
+    __syncthreads();
+    const int col = lane & 15, q = lane >> 4, i = col;
+#pragma unroll 1
+    for (int tile = wave; tile < kZPos / 16; tile += 4) {
+        zfloatx4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
+        const float2 *arow = span + 16 * tile + i + q;
+        const float *bcol = cl + q * kR + (col & 7);
+#pragma unroll 4
+        for (int st = 0; st < steps; ++st) {
+            const float2 a = arow[4 * st];
+            const float b = col < 8 ? bcol[4 * st * kR] : 0.f;
+            acc_re = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b, acc_re, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b, acc_im, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t f = f0 + 16 * tile + 4 * q + k;
+            if (col < 8 && f < F)
+                gmem(Z)[f * kR + col] = make_float2(acc_re[k], acc_im[k]);
+        }
     }
 }
 
@@ -416,7 +492,8 @@ void farrow_pack_desc(const FarrowPlan &p, char *host)
 }
 
 hipError_t launch_farrow_bank(const FarrowPlan &p, const float2 *x, int64_t n, float2 *y, int64_t n_out, int H,
-                              const float *coef, const void *desc_dev, void *z_work, hipStream_t s, Profiler *prof)
+                              int precision, const float *coef, const void *desc_dev, void *z_work, hipStream_t s,
+                              Profiler *prof)
 {
     if (p.lds_bytes > 160 * 1024 || n_out <= 0 || p.groups.empty())
         return hipErrorInvalidValue;
@@ -440,7 +517,7 @@ hipError_t launch_farrow_bank(const FarrowPlan &p, const float2 *x, int64_t n, f
             return e;
         attr[dev] = true;
     }
-    const size_t zlds = farrow_z_lds_bytes(H);
+    const size_t zlds = precision == RC_BANK_FP32 ? farrow_z_f32_lds_bytes(H) : farrow_z_lds_bytes(H);
     if (zlds > 64 * 1024)
         return hipErrorInvalidValue;
     if (prof)
@@ -454,12 +531,28 @@ hipError_t launch_farrow_bank(const FarrowPlan &p, const float2 *x, int64_t n, f
     const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)zlds);
     const int64_t zgrid = std::min<int64_t>(zblocks, (int64_t)std::max(cus, 1) * std::min<int64_t>(per_cu, 4));
     const int ks = farrow_z_steps(H);
-    if (ks <= 4)
-        hipLaunchKernelGGL(k_farrow_z<4>, dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H, coef, Z);
+    if (zblocks > 0x7fffffff)
+        return hipErrorInvalidValue;
+    if (precision == RC_BANK_FP32)
+        hipLaunchKernelGGL(k_farrow_z_f32, dim3((unsigned)zblocks), dim3(256), zlds, s, x, n, p.F, H, coef, Z);
+    else if (precision == RC_BANK_BF16X3 && ks <= 4)
+        hipLaunchKernelGGL((k_farrow_z<4, RC_BANK_BF16X3>), dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H,
+                           coef, Z);
+    else if (precision == RC_BANK_BF16X3 && ks <= 8)
+        hipLaunchKernelGGL((k_farrow_z<8, RC_BANK_BF16X3>), dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H,
+                           coef, Z);
+    else if (precision == RC_BANK_BF16X3)
+        hipLaunchKernelGGL((k_farrow_z<16, RC_BANK_BF16X3>), dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H,
+                           coef, Z);
+    else if (ks <= 4)
+        hipLaunchKernelGGL((k_farrow_z<4, RC_BANK_FP16X3>), dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H,
+                           coef, Z);
     else if (ks <= 8)
-        hipLaunchKernelGGL(k_farrow_z<8>, dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H, coef, Z);
+        hipLaunchKernelGGL((k_farrow_z<8, RC_BANK_FP16X3>), dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H,
+                           coef, Z);
     else
-        hipLaunchKernelGGL(k_farrow_z<16>, dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H, coef, Z);
+        hipLaunchKernelGGL((k_farrow_z<16, RC_BANK_FP16X3>), dim3((unsigned)zgrid), dim3(256), zlds, s, x, n, p.F, H,
+                           coef, Z);
     e = hipGetLastError();
     if (prof)
         prof->end(s);

@@ -935,7 +935,8 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
 }
 
 rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c64 *y, int64_t n_out, double fs_hz,
-                               const double *alphas, int32_t n_hyp, const rc_sinc *k, int32_t mode, void *stream)
+                               const double *alphas, int32_t n_hyp, const rc_sinc *k, int32_t precision,
+                               void *stream)
 {
     if (!ctx)
         return RC_ERR_INVALID_ARG;
@@ -950,8 +951,8 @@ rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c6
         return fail(ctx, RC_ERR_INVALID_ARG, "n, n_out and n_hyp must be > 0");
     if (!(std::isfinite(fs_hz) && fs_hz > 0.0))
         return fail(ctx, RC_ERR_INVALID_ARG, "fs_hz must be finite and > 0");
-    if (mode != RC_BANK_AUTO && mode != RC_BANK_FARROW && mode != RC_BANK_PER_HYPOTHESIS)
-        return fail(ctx, RC_ERR_INVALID_ARG, "unknown bank mode");
+    if (precision != RC_BANK_FP16X3 && precision != RC_BANK_BF16X3 && precision != RC_BANK_FP32)
+        return fail(ctx, RC_ERR_INVALID_ARG, "unknown bank precision");
     for (int32_t h = 0; h < n_hyp; ++h)
         if (!(std::isfinite(alphas[h]) && alphas[h] > 0.0))
             return fail(ctx, RC_ERR_INVALID_ARG, "hypothesis " + std::to_string(h) + ": alpha must be finite and > 0");
@@ -959,8 +960,9 @@ rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c6
         return fail(ctx, RC_ERR_INVALID_ARG, "output size overflows");
     if (overlaps(x, n * 8, y, n_out * n_hyp * 8))
         return fail(ctx, RC_ERR_INVALID_ARG, "x and y overlap");
-    const bool farrow = mode != RC_BANK_PER_HYPOTHESIS && rc::farrow_eligible(*k, alphas, n_hyp);
-    if (mode == RC_BANK_FARROW && !farrow)
+    const int mode = ctx->bank_engine;
+    const bool farrow = mode != RC_BANK_ENGINE_PER_HYPOTHESIS && rc::farrow_eligible(*k, alphas, n_hyp);
+    if (mode == RC_BANK_ENGINE_FARROW && !farrow)
         return fail(ctx, RC_ERR_UNSUPPORTED,
                     "the filter bank needs a Kaiser or rectangular window, 1 <= H <= 256 and 0 < alpha <= 2");
     DeviceGuard g(ctx->device);
@@ -997,7 +999,8 @@ rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c6
         return st;
     char *devc = static_cast<char *>(const_cast<void *>(dev));
     hipError_t e = rc::launch_farrow_bank(plan, reinterpret_cast<const float2 *>(x), n, reinterpret_cast<float2 *>(y),
-                                          n_out, k->half_width, coef, devc, devc + ((desc.size() + 255) & ~(size_t)255),
+                                          n_out, k->half_width, precision, coef, devc,
+                                          devc + ((desc.size() + 255) & ~(size_t)255),
                                           s, prof_of(ctx));
     st = mark_descriptors_used(ctx, s);
     if (e != hipSuccess)
@@ -1373,10 +1376,21 @@ rc_status rc_set_sinc_engine(rc_context ctx, int32_t engine)
 {
     if (!ctx)
         return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     if (engine != RC_SINC_AUTO && engine != RC_SINC_VALU && engine != RC_SINC_DIRECT)
         return fail(ctx, RC_ERR_INVALID_ARG, "unknown sinc engine");
-    std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->sinc_engine = engine;
+    return RC_OK;
+}
+
+rc_status rc_set_bank_engine(rc_context ctx, int32_t engine)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (engine != RC_BANK_ENGINE_AUTO && engine != RC_BANK_ENGINE_FARROW && engine != RC_BANK_ENGINE_PER_HYPOTHESIS)
+        return fail(ctx, RC_ERR_INVALID_ARG, "unknown bank engine");
+    ctx->bank_engine = engine;
     return RC_OK;
 }
 
@@ -1384,9 +1398,9 @@ rc_status rc_set_mem_budget(rc_context ctx, int64_t bytes)
 {
     if (!ctx)
         return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     if (bytes < 0)
         return fail(ctx, RC_ERR_INVALID_ARG, "the memory budget must be >= 0");
-    std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->mem_budget = bytes;
     return RC_OK;
 }

@@ -184,8 +184,10 @@ FarrowPlan plan_farrow_bank(int64_t n, int64_t n_out, int H, const double *alpha
 size_t farrow_desc_bytes(const FarrowPlan &p);
 void farrow_pack_desc(const FarrowPlan &p, char *host);
 // desc_dev: farrow_pack_desc() uploaded; z_work: p.z_bytes of device memory
+// precision: RC_BANK_FP16X3 | RC_BANK_BF16X3 | RC_BANK_FP32 (the Z filter's contraction)
 hipError_t launch_farrow_bank(const FarrowPlan &p, const float2 *x, int64_t n, float2 *y, int64_t n_out, int H,
-                              const float *coef, const void *desc_dev, void *z_work, hipStream_t s, Profiler *prof);
+                              int precision, const float *coef, const void *desc_dev, void *z_work, hipStream_t s,
+                              Profiler *prof);
 
 // ---------------------------------------------------------------------------------------
 // FFT / ionosphere
@@ -304,5 +306,6 @@ struct rc_context_s {
     int desc_next = 0;
     rc::Profiler prof;
     int sinc_engine = 0;  // RC_SINC_AUTO / RC_SINC_VALU / RC_SINC_DIRECT
+    int bank_engine = 0;  // RC_BANK_ENGINE_AUTO / _FARROW / _PER_HYPOTHESIS
     int64_t mem_budget = 0;  // cap on the slots' device workspace in bytes (rc_set_mem_budget); 0: none
 };
