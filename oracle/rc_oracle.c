@@ -30,6 +30,11 @@
  *     sinc(k) = 0 for every other integer k);
  *   - f_k = carrier + fs * fftfreq(N)[k] (numpy convention, bin N/2 negative);
  *     at f_k == 0 the response is 1;
+ *   - the phase 4 pi K2 / (c f_k) is a function of the double inputs (fs, carrier,
+ *     E) and of the CODATA constants as decimal numbers.  With a carrier below
+ *     fs/2 it reaches ~1e12 rad, where a float64 quotient is already uncertain by
+ *     ~1e-4 rad, so the phase alone is evaluated in long double (64-bit
+ *     significand) and reduced by cosl/sinl;
  *   - forward DFT unnormalised, inverse scaled by 1/N;
  *   - batch: Doppler first, then the ionosphere on the resampled samples.
  *
@@ -51,6 +56,12 @@
 #define RCO_M_E 9.1093837139e-31
 #define RCO_EPS0 8.8541878188e-12
 #define RCO_PI 3.14159265358979323846
+/* The same constants as long double literals, for the dispersive phase. */
+#define RCO_CL 299792458.0L
+#define RCO_E_CHARGEL 1.602176634e-19L
+#define RCO_M_EL 9.1093837139e-31L
+#define RCO_EPS0L 8.8541878188e-12L
+#define RCO_PIL 3.141592653589793238462643383279502884L
 
 enum { RCO_WIN_KAISER = 0, RCO_WIN_RECT = 1, RCO_WIN_PAPER = 2 };
 enum { RCO_CORRECT = 0, RCO_DISTORT = 1 };
@@ -317,18 +328,21 @@ int rco_iono_response(int64_t n, double fs, double carrier, double tec, int dire
 {
     if (!H || n <= 0 || !(fs > 0.0) || !isfinite(carrier) || !isfinite(tec))
         return 1;
-    double k2 = rco_k2_per_tec() * tec;
-    double s = (direction == RCO_DISTORT) ? 1.0 : -1.0;
+    /* K2 = e^2 E / (8 pi^2 m_e eps0) and f_k in long double: see the header note. */
+    long double k2 = RCO_E_CHARGEL * RCO_E_CHARGEL / (8.0L * RCO_PIL * RCO_PIL * RCO_M_EL * RCO_EPS0L)
+                     * (long double)tec;
+    long double s = (direction == RCO_DISTORT) ? 1.0L : -1.0L;
     for (int64_t k = 0; k < n; ++k) {
-        double f = rco_bin_frequency(k, n, fs, carrier);
-        if (f == 0.0) {
+        int64_t kk = (k < (n + 1) / 2) ? k : k - n;
+        long double f = (long double)carrier + (long double)fs * (long double)kk / (long double)n;
+        if (f == 0.0L) {
             H[2 * k] = 1.0;
             H[2 * k + 1] = 0.0;
             continue;
         }
-        double phi = s * 4.0 * RCO_PI * k2 / (RCO_C * f);
-        H[2 * k] = cos(phi);
-        H[2 * k + 1] = sin(phi);
+        long double phi = s * 4.0L * RCO_PIL * k2 / (RCO_CL * f);
+        H[2 * k] = (double)cosl(phi);
+        H[2 * k + 1] = (double)sinl(phi);
     }
     return 0;
 }

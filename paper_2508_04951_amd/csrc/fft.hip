@@ -430,31 +430,68 @@ __device__ __forceinline__ float2 cis_quarter(float w)
 
 // Per-job constants of the dispersive phase of Eq (15)/(16): in quarter turns the phase at bin
 // frequency f is c4 / f, with f = carrier + fs_n kk for the signed bin index kk (fs_n = fs / n).
+// With xprec the quotient is (c4 n) / (carrier n + fs kk) in double-double arithmetic: c4n and
+// cn are the exact products c4 n and carrier n as unevaluated sums hi + lo.
 struct PhaseK {
     double c4, carrier, fs_n;
+    double c4n_hi, c4n_lo, cn_hi, cn_lo, fs;
+    bool xprec;
 };
 
 __device__ __forceinline__ PhaseK phase_consts(const IonoJob &jb, int64_t n)
 {
-    return PhaseK{jb.phase_num * 0.63661977236758134308, jb.carrier, jb.fs * (1.0 / (double)n)};
+    PhaseK P;
+    const double nd = (double)n;
+    P.c4 = jb.phase.hi;
+    P.carrier = jb.carrier;
+    P.fs_n = jb.fs * (1.0 / nd);
+    P.fs = jb.fs;
+    P.xprec = jb.phase.xprec != 0;
+    P.c4n_hi = jb.phase.hi * nd;
+    P.c4n_lo = fma(jb.phase.hi, nd, -P.c4n_hi) + jb.phase.lo * nd;
+    P.cn_hi = jb.carrier * nd;
+    P.cn_lo = fma(jb.carrier, nd, -P.cn_hi);
+    return P;
 }
 
 __device__ __forceinline__ float2 phase_at(const PhaseK &P, int64_t kk)
 {
-    const double f = fma(P.fs_n, (double)kk, P.carrier);
-    // The phase t4 = c4 / f in quarter turns.  1/f comes from the hardware reciprocal (relative
-    // error below 2^-24 on gfx950) and one Newton step (below 2^-48); the quotient then takes one
-    // residual correction, t4 += (c4 - t4 f) / f, which leaves it within a few ulp of c4 / f (the
-    // IEEE division sequence costs ~70 extra registers here).  Near f = 0 (a carrier below fs/2)
-    // |t4| reaches ~1e12, where 2^-48 alone would be ~4e-3 quarter turn.
-    double rf = __builtin_amdgcn_rcp(f);
-    rf = fma(rf, fma(-f, rf, 1.0), rf);
-    double t4 = P.c4 * rf;
-    t4 = fma(fma(-t4, f, P.c4), rf, t4);
-    // t4 splits exactly into a whole number n4 and a remainder w in [-1/2, 1/2] (both exact for
-    // |t4| < 2^52); cis(pi w / 2) in float32 is then turned by n4 quarter turns.
+    double f, rf, t4, t4_lo = 0.0;
+    if (!P.xprec) {
+        f = fma(P.fs_n, (double)kk, P.carrier);
+        // t4 = c4 / f quarter turns.  1/f comes from the hardware reciprocal (relative error
+        // below 2^-24 on gfx950) and one Newton step (below 2^-48); the quotient then takes one
+        // residual correction, t4 += (c4 - t4 f) / f, which leaves it within a few ulp of c4 / f.
+        // Without xprec |t4| < 2^26, so that is within 2^-24 quarter turn.
+        rf = __builtin_amdgcn_rcp(f);
+        rf = fma(rf, fma(-f, rf, 1.0), rf);
+        t4 = P.c4 * rf;
+        t4 = fma(fma(-t4, f, P.c4), rf, t4);
+    } else {
+        // d = carrier n + fs kk as hi + lo: fs kk exactly (two products), then a two-sum with
+        // carrier n.  d is n f, so t4 = (c4 n) / d.
+        const double k = (double)kk;
+        const double p = P.fs * k;
+        const double pe = fma(P.fs, k, -p);
+        const double sm = P.cn_hi + p;
+        const double bb = sm - P.cn_hi;
+        const double l = ((P.cn_hi - (sm - bb)) + (p - bb)) + (pe + P.cn_lo);
+        f = sm + l;
+        const double f_lo = l - (f - sm);
+        rf = __builtin_amdgcn_rcp(f);
+        rf = fma(rf, fma(-f, rf, 1.0), rf);
+        t4 = P.c4n_hi * rf;
+        t4 = fma(fma(-t4, f, P.c4n_hi), rf, t4);
+        // The remainder c4n - t4 d, with the product t4 f_hi exact through the fma; the quotient
+        // is t4 + remainder / d to about 2^-100 relative.
+        double r = fma(-t4, f, P.c4n_hi) + P.c4n_lo;
+        r = fma(-t4, f_lo, r);
+        t4_lo = r * rf;
+    }
+    // t4 splits exactly into a whole number n4 and a remainder w in [-1/2, 1/2] (n4 and t4 - n4
+    // are exact for |t4| < 2^52); cis(pi w / 2) in float32 is then turned by n4 quarter turns.
     const double n4 = rint(t4);
-    const float2 w = cis_quarter((float)(t4 - n4));
+    const float2 w = cis_quarter((float)((t4 - n4) + t4_lo));
     // n4 mod 4, exact in float64: n4/4, its floor and 4 floor(n4/4) are all exact integers.
     const int quad = (int)(n4 - 4.0 * floor(0.25 * n4));
     const float c = (quad & 1) ? -w.y : w.x;  // (c, s) turned by quad * 90 degrees
@@ -480,7 +517,7 @@ __device__ __forceinline__ float2 bin_factor(const IonoJob &jb, int64_t t, int64
         if (jb.conj_mult)
             f.y = -f.y;
     }
-    if (jb.phase_num != 0.0) {
+    if (jb.phase.hi != 0.0) {
         const float2 w = iono_phase(jb, k, n);
         f = jb.mult ? cmul(f, w) : w;
     }
@@ -937,7 +974,7 @@ __global__ void __launch_bounds__(256) k_bluestein_mid(const BluesteinJob *jobs,
         return;
     float2 v = make_float2(0.f, 0.f);
     if (k < N) {
-        const IonoJob ph{nullptr, nullptr, jb.phase_num, jb.carrier, jb.fs, nullptr};
+        const IonoJob ph{nullptr, nullptr, jb.phase, jb.carrier, jb.fs, nullptr};
         const float si = chirp_scale_inv(M);  // the convolution carries the chirp's scale
         const float2 c = gload(jb.a, k);
         const float2 h = cmul(make_float2(c.x * si, c.y * si), iono_phase(ph, k, N));
@@ -1042,8 +1079,8 @@ hipError_t launch_iono_bluestein(const FftPlan &mplan, const float2 *tw4096, con
     if (e != hipSuccess)
         return e;
     // the chirp spectra, in the native bin order the convolutions multiply in
-    const IonoJob jb_b{inl.a + M, inl.a + M, 0.0, 0.0, 0.0, nullptr};
-    const IonoJob conv{inl.a, inl.a, 0.0, 0.0, 0.0, inl.a + M};
+    const IonoJob jb_b{inl.a + M, inl.a + M, PhaseNum{}, 0.0, 0.0, nullptr};
+    const IonoJob conv{inl.a, inl.a, PhaseNum{}, 0.0, 0.0, inl.a + M};
     const IonoJob *fb = jobs_dev ? ffts_dev : nullptr, *fc = jobs_dev ? ffts_dev + njobs : nullptr;
     e = launch_fft_forward(mplan, tw4096, fb, &jb_b, njobs, s, prof);
     if (e == hipSuccess)
@@ -1071,8 +1108,8 @@ hipError_t launch_bluestein_forward(const FftPlan &mplan, const float2 *tw4096, 
     hipError_t e = hipGetLastError();
     if (prof)
         prof->end(s);
-    const IonoJob jb_b{inl.a + M, inl.a + M, 0.0, 0.0, 0.0, nullptr};
-    const IonoJob conv{inl.a, inl.a, 0.0, 0.0, 0.0, inl.a + M};
+    const IonoJob jb_b{inl.a + M, inl.a + M, PhaseNum{}, 0.0, 0.0, nullptr};
+    const IonoJob conv{inl.a, inl.a, PhaseNum{}, 0.0, 0.0, inl.a + M};
     if (e == hipSuccess)
         e = launch_fft_forward(mplan, tw4096, nullptr, &jb_b, 1, s, prof);
     if (e == hipSuccess)

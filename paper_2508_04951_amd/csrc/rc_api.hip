@@ -19,6 +19,7 @@ namespace {
 
 using rc::FftPlan;
 using rc::IonoJob;
+using rc::PhaseNum;
 using rc::SincJob;
 
 rc_status fail(rc_context ctx, rc_status st, const std::string &why)
@@ -231,11 +232,46 @@ rc_status get_mfma_table(rc_context ctx, const rc_sinc &k, const void **out)
     return RC_OK;
 }
 
-double phase_numerator(double tec, int32_t direction)
+// K2 / E = e^2 / (8 pi^2 m_e eps0) (Eq 3, App. A) in long double, from the decimal constants.
+long double k2_per_tec_ld()
 {
-    const double k2 = rc_k2_per_tec() * tec;
-    const double s = (direction == RC_DISTORT) ? 1.0 : -1.0;
-    return s * 4.0 * rc::kPi * k2 / rc::kC;
+    const long double e = 1.602176634e-19L, me = 9.1093837139e-31L, eps0 = 8.8541878188e-12L;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    return e * e / (8.0L * pi * pi * me * eps0);
+}
+
+// The quarter-turn numerator s * 8 K2 / c of Eq (15)/(16) (see PhaseNum) for a pulse of n
+// samples at fs with this carrier.  Its 64-bit significand keeps the phase of the bin nearest
+// 0 Hz (up to ~1e12 rad with a carrier below fs/2) within ~1e-7 rad.
+PhaseNum phase_numerator(double tec, int32_t direction, double fs, double carrier, int64_t n)
+{
+    const long double s = (direction == RC_DISTORT) ? 1.0L : -1.0L;
+    const long double c4 = s * 8.0L * k2_per_tec_ld() * (long double)tec / (long double)rc::kC;
+    PhaseNum P{(double)c4, 0.0, 0};
+    P.lo = (double)(c4 - (long double)P.hi);
+    if (P.hi == 0.0)
+        return P;
+    // The bin frequencies carrier + fs kk / n, kk in [-(n/2), (n-1)/2], increase with kk; the
+    // smallest nonzero |f| sits at an end or next to the zero crossing.
+    const int64_t lo = -(n / 2), hi = (n - 1) / 2;
+    auto f_at = [&](int64_t kk) { return (long double)carrier + (long double)fs * (long double)kk / (long double)n; };
+    long double fmin;
+    if (f_at(lo) > 0.0L) {
+        fmin = f_at(lo);
+    } else if (f_at(hi) < 0.0L) {
+        fmin = -f_at(hi);
+    } else {
+        const long double k0 = std::floor(-(long double)carrier * (long double)n / (long double)fs);
+        fmin = INFINITY;
+        for (int d = -1; d <= 2; ++d) {
+            const long double kq = std::min(std::max(k0 + d, (long double)lo), (long double)hi);
+            const long double f = std::fabs(f_at((int64_t)kq));
+            if (f > 0.0L)
+                fmin = std::min(fmin, f);
+        }
+    }
+    P.xprec = std::fabs(c4) > std::ldexp(1.0L, 26) * fmin;
+    return P;
 }
 
 rc::Profiler *prof_of(rc_context ctx) { return ctx->prof.on ? &ctx->prof : nullptr; }
@@ -291,7 +327,7 @@ double rc_alpha_from_vr(double v_r_mps)
 
 double rc_k2_per_tec(void)
 {
-    return rc::kECharge * rc::kECharge / (8.0 * rc::kPi * rc::kPi * rc::kMe * rc::kEps0);
+    return (double)k2_per_tec_ld();
 }
 
 rc_status rc_create(int hip_device, rc_context *out)
@@ -482,7 +518,7 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
         return fail(ctx, RC_ERR_UNSUPPORTED, "n above 2^24 (power of two) or 2^23 (other lengths)");
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const double phase = phase_numerator(tec_el_per_m2, direction);
+    const PhaseNum phase = phase_numerator(tec_el_per_m2, direction, fs_hz, carrier_hz, n);
     const float2 *xf = reinterpret_cast<const float2 *>(x);
     float2 *yf = reinterpret_cast<float2 *>(y);
     const FftPlan *plan = nullptr;
@@ -536,7 +572,7 @@ rc_status replica_spectrum(rc_context ctx, const rc_c64 *replica, int64_t n_rep,
     hipError_t e = rc::launch_pad(reinterpret_cast<const float2 *>(replica), n_rep, sp, n, s);
     if (e == hipSuccess && is_pow2(n)) {
         // the transform's native bin order, which the row pass of compress_pulse multiplies in
-        const IonoJob jb{sp, sp, 0.0, 0.0, 0.0, nullptr, 0};
+        const IonoJob jb{sp, sp, PhaseNum{}, 0.0, 0.0, nullptr, 0};
         e = rc::launch_fft_forward(*plan, ctx->tw4096, nullptr, &jb, 1, s, prof_of(ctx));
     } else if (e == hipSuccess) {
         // natural bin order, which Bluestein's middle step of compress_pulse multiplies in
@@ -544,7 +580,7 @@ rc_status replica_spectrum(rc_context ctx, const rc_c64 *replica, int64_t n_rep,
         st = stage_descriptors(ctx, nullptr, 0, rc::bluestein_work_bytes(n), s, &dev);
         if (st != RC_OK)
             return st;
-        const rc::BluesteinJob jb{sp, sp, static_cast<float2 *>(const_cast<void *>(dev)), n, 0.0, 0.0, 0.0, nullptr};
+        const rc::BluesteinJob jb{sp, sp, static_cast<float2 *>(const_cast<void *>(dev)), n, PhaseNum{}, 0.0, 0.0, nullptr};
         e = rc::launch_bluestein_forward(*plan, ctx->tw4096, jb, s, prof_of(ctx));
         st = mark_descriptors_used(ctx, s);
         if (e == hipSuccess && st != RC_OK)
@@ -589,7 +625,7 @@ rc_status compress_pulse(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n, 
     const float2 *xf = reinterpret_cast<const float2 *>(x);
     float2 *yf = reinterpret_cast<float2 *>(y);
     const float2 *sp = reinterpret_cast<const float2 *>(spec);
-    const double phase = phase_numerator(tec_el_per_m2, direction);
+    const PhaseNum phase = phase_numerator(tec_el_per_m2, direction, fs_hz, carrier_hz, n);
     hipError_t e;
     if (is_pow2(n)) {
         const IonoJob job{xf, yf, phase, carrier_hz, fs_hz, sp, 1};
@@ -730,7 +766,7 @@ rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, 
         }
         if (p.flags & RC_DO_IONO) {
             const float2 *src = (p.flags & RC_DO_DOPPLER) ? p.y : p.x;
-            const double ph = phase_numerator(p.tec, p.direction);
+            const PhaseNum ph = phase_numerator(p.tec, p.direction, p.fs_hz, p.carrier, p.n_out);
             if (is_pow2(p.n_out))
                 iono[p.n_out].push_back(IonoJob{src, p.y, ph, p.carrier, p.fs_hz, nullptr});
             else
@@ -825,8 +861,8 @@ rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, 
             for (size_t q = 0; q < c.count; ++q) {
                 float2 *a = bw + (size_t)q * 2 * c.m, *b = a + c.m;
                 jobs[q].a = a;
-                ffts[q] = IonoJob{b, b, 0.0, 0.0, 0.0, nullptr};
-                ffts[c.count + q] = IonoJob{a, a, 0.0, 0.0, 0.0, b};
+                ffts[q] = IonoJob{b, b, PhaseNum{}, 0.0, 0.0, nullptr};
+                ffts[c.count + q] = IonoJob{a, a, PhaseNum{}, 0.0, 0.0, b};
             }
         }
         if (!blob.empty())

@@ -48,11 +48,9 @@ struct Profiler {
     void release();
 };
 
-// Physical constants: c exact (SI); e exact (2019 SI); m_e and eps0 CODATA 2022.
+// Speed of light, exact (SI).  e, m_e and eps0 (CODATA 2022) enter only K2 / E, evaluated on
+// the host in long double next to the dispersive phase.
 constexpr double kC = 299792458.0;
-constexpr double kECharge = 1.602176634e-19;
-constexpr double kMe = 9.1093837139e-31;
-constexpr double kEps0 = 8.8541878188e-12;
 constexpr double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------------------
@@ -198,17 +196,27 @@ constexpr int kFftTile = 4096;
 constexpr int kFftThreads = 256;
 constexpr int kFftMaxLevels = 4;
 
-// Per-pulse ionospheric parameters.  phase_num = s * 4 pi K2 / c (rad Hz), s = -1 for
-// correction (Eq 16) and +1 for distortion (Eq 15); f_k = carrier + fs * kk / n.
+// Numerator of the dispersive phase of Eq (15)/(16) in quarter turns: bin frequency f turns
+// by (hi + lo) / f quarter turns, hi + lo = s * 8 K2 / c (= s * 4 pi K2 / c over pi / 2), s = -1
+// for correction (Eq 16) and +1 for distortion (Eq 15), evaluated on the host in long double.
+// xprec asks for the quotient in double-double arithmetic: set when some bin's phase exceeds
+// 2^26 quarter turns (a carrier within about fs / 2 of 0 Hz), where a float64 quotient would be
+// uncertain by more than 1e-7 quarter turn.  hi == 0 means no phase.
+struct PhaseNum {
+    double hi, lo;
+    int xprec;
+};
+
+// Per-pulse ionospheric parameters; f_k = carrier + fs * kk / n.
 struct IonoJob {
     const float2 *x;  // input of the first pass (may equal y)
     float2 *y;        // output; every later pass runs in place on y
-    double phase_num;
+    PhaseNum phase;
     double carrier;
     double fs;
     // When set, the spectrum is also multiplied by this table (in the transform's native bin
     // order, see launch_fft_forward), conjugated if conj_mult: a circular convolution or, with
-    // the conjugate, a correlation.  The dispersive phase applies on top unless phase_num is 0.
+    // the conjugate, a correlation.  The dispersive phase applies on top unless phase.hi is 0.
     const float2 *mult;
     int conj_mult;
 };
@@ -253,7 +261,8 @@ struct BluesteinJob {
     float2 *y;        // output, n samples (may equal x)
     float2 *a;        // workspace: a[0, m) and b = a + m
     int64_t n;
-    double phase_num, carrier, fs;  // as in IonoJob
+    PhaseNum phase;                 // as in IonoJob
+    double carrier, fs;
     // When set, the spectrum is also multiplied by conj(corr[k]) (natural bin order, n values):
     // the cross-correlation with the signal whose spectrum corr holds (pulse compression).
     const float2 *corr;

@@ -79,6 +79,37 @@ def test_single_bin_tone_gets_exact_phase(orc, n, k0, direction, sign):
     np.testing.assert_allclose(y, expected, rtol=0, atol=1e-11)
 
 
+CODATA = dict(e="1.602176634e-19", m_e="9.1093837139e-31", eps0="8.8541878188e-12", c="299792458")
+
+
+@pytest.mark.parametrize("n,fs,carrier,tec_tecu", [(1 << 22, 10e6, 0.0, 100.0), (1 << 24, 10e6, 0.0, 100.0),
+                                                   (70001, 10e6, 0.0, 100.0), ((1 << 22) + 12345, 10e6, 0.0, 5.0),
+                                                   (1 << 21, 2.048e9, 0.0, 100.0), (4096, 10e6, 4.99e6, 100.0),
+                                                   (1 << 16, 10e6, 450e6, 50.0)])
+def test_large_phases_against_multiprecision(orc, n, fs, carrier, tec_tecu):
+    """With the carrier below fs/2 the lowest bins sit a few hertz from f = 0 and the phase
+    4 pi K2/(c f) of Eq (15)/(16) reaches ~1e12 rad.  The oracle's response there matches the
+    same formula evaluated with 50-digit arithmetic (mpmath) on the same double inputs and the
+    CODATA decimal constants, reduced mod 2 pi, to 1e-6 rad; a float64 quotient would miss by
+    ~1e-4 rad at the largest of these phases."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    tec = tec_tecu * wf.TECU
+    H = orc.iono_response(n, fs, carrier, tec, "correct")
+    k2 = mp.mpf(CODATA["e"]) ** 2 / (8 * mp.pi ** 2 * mp.mpf(CODATA["m_e"]) * mp.mpf(CODATA["eps0"])) * mp.mpf(tec)
+    worst = 0.0
+    for k in sorted({1, 2, 3, n // 2 - 1, n // 2, n - 1, n - 2, n // 3}):
+        kk = k if k < (n + 1) // 2 else k - n
+        f = mp.mpf(carrier) + mp.mpf(fs) * kk / n
+        phi = -4 * mp.pi * k2 / (mp.mpf(CODATA["c"]) * f)
+        ref = float(phi - 2 * mp.pi * mp.nint(phi / (2 * mp.pi)))
+        got = float(np.angle(H[k]))
+        d = abs((got - ref + np.pi) % (2 * np.pi) - np.pi)
+        worst = max(worst, d)
+        assert abs(abs(H[k]) - 1.0) < 1e-15
+    assert worst <= 1e-6, worst
+
+
 def test_zero_frequency_bin_is_left_alone(orc):
     """With the carrier at 0 (RF-sampled data) the DC bin has f = 0; its response is 1."""
     n = 64
