@@ -84,6 +84,18 @@ def _load():
     lib.rco_ionosphere.argtypes = [p, p, i64, d, d, d, i32, i32]
     lib.rco_compress.restype = i32
     lib.rco_compress.argtypes = [p, p, i64, p, i64, d, d, d, i32, i32]
+    lib.rco_doppler_lut.restype = i32
+    lib.rco_doppler_lut.argtypes = [p, i64, p, i64, d, i32, i32]
+    lib.rco_doppler_linear.restype = i32
+    lib.rco_doppler_linear.argtypes = [p, i64, p, i64, d]
+    lib.rco_doppler_tone.restype = i32
+    lib.rco_doppler_tone.argtypes = [p, i64, p, d, d, d]
+    lib.rco_resample_fft.restype = i32
+    lib.rco_resample_fft.argtypes = [p, i64, p, i64]
+    lib.rco_pq_length.restype = i64
+    lib.rco_pq_length.argtypes = [i64, d]
+    lib.rco_doppler_pq.restype = i32
+    lib.rco_doppler_pq.argtypes = [p, i64, p, i64, d, d, d, i32]
     lib.rco_pulse.restype = i32
     lib.rco_pulse.argtypes = [p, i64, p, i64, d, d, d, d, i32, i32, i32, i32, i32, d, i32]
     _lib = lib
@@ -155,6 +167,61 @@ def doppler_at(x, idx, alpha: float, half_width: int = 64, window: str = "kaiser
     rc = _load().rco_doppler_at(_ptr(xin), xin.size, _ptr(ii), ii.size, _ptr(y), float(alpha),
                                 int(half_width), WINDOWS[window], float(beta))
     _check(rc, "doppler_at")
+    return y
+
+
+def doppler_lut(x, alpha: float, half_width: int, lut_size: int, n_out: int | None = None) -> np.ndarray:
+    """App. C, Alg. 2: the paper's (2 half_width + 1)-tap nearest-centred window with sinc from a
+    table of lut_size values of its positive half (nearest entry)."""
+    xin = _c128(x)
+    n_out = xin.size if n_out is None else int(n_out)
+    y = np.zeros(n_out, dtype=np.complex128)
+    _check(_load().rco_doppler_lut(_ptr(xin), xin.size, _ptr(y), n_out, float(alpha), int(half_width),
+                                   int(lut_size)), "doppler_lut")
+    return y
+
+
+def doppler_linear(x, alpha: float, n_out: int | None = None) -> np.ndarray:
+    """Linear interpolation at t = alpha m (Sec. I, Table I)."""
+    xin = _c128(x)
+    n_out = xin.size if n_out is None else int(n_out)
+    y = np.zeros(n_out, dtype=np.complex128)
+    _check(_load().rco_doppler_linear(_ptr(xin), xin.size, _ptr(y), n_out, float(alpha)), "doppler_linear")
+    return y
+
+
+def doppler_tone(x, fs: float, alpha: float, f_ref: float) -> np.ndarray:
+    """Frequency conversion: x[m] exp(2 pi i (alpha - 1) f_ref m / fs) (Sec. I, Table I)."""
+    xin = _c128(x)
+    y = np.zeros_like(xin)
+    _check(_load().rco_doppler_tone(_ptr(xin), xin.size, _ptr(y), float(fs), float(alpha), float(f_ref)),
+           "doppler_tone")
+    return y
+
+
+def resample_fft(x, n_out: int) -> np.ndarray:
+    """FFT P/Q resampling of x to n_out samples (bins removed or zero bins added)."""
+    xin = _c128(x)
+    y = np.zeros(int(n_out), dtype=np.complex128)
+    _check(_load().rco_resample_fft(_ptr(xin), xin.size, _ptr(y), int(n_out)), "resample_fft")
+    return y
+
+
+def pq_length(n_in: int, alpha: float) -> int:
+    """Length of the P/Q-resampled record for dilation alpha (an even number of samples removed
+    or added)."""
+    return int(_load().rco_pq_length(int(n_in), float(alpha)))
+
+
+def doppler_pq(x, fs: float, alpha: float, f_ref: float = 0.0, tone: bool = False,
+               n_out: int | None = None) -> np.ndarray:
+    """Doppler correction by FFT P/Q resampling, optionally followed by frequency conversion of
+    the remaining dilation (Sec. III-A)."""
+    xin = _c128(x)
+    n_out = xin.size if n_out is None else int(n_out)
+    y = np.zeros(n_out, dtype=np.complex128)
+    _check(_load().rco_doppler_pq(_ptr(xin), xin.size, _ptr(y), n_out, float(fs), float(alpha), float(f_ref),
+                                  int(bool(tone))), "doppler_pq")
     return y
 
 

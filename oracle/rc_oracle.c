@@ -450,3 +450,183 @@ int rco_pulse(const double *x, int64_t n_in, double *y, int64_t n_out, double fs
     free(r);
     return rc;
 }
+
+/* ---------------------------------------------------------------------------------------
+ * The paper's other resampling methods (Sec. I list of methods, Table I, Sec. III-A, App. C),
+ * kept as references for the baseline engines.
+ * --------------------------------------------------------------------------------------- */
+
+/* App. C, Alg. 2: the paper's window (N_w = 2h + 1 inputs centred on the nearest input
+ * sample, untapered) with sinc taken from a table of its positive half.  The table holds
+ * lut_size values sinc(i dx), i = 0 .. lut_size-1, spanning the window's largest distance
+ * u_max = h + 1/2, so dx = u_max / (lut_size - 1); a tap at distance u = |t - n| takes entry
+ * floor(u / dx + 1/2) (nearest), computed as floor(u * inv_dx + 0.5) with inv_dx = 1 / dx.
+ * No exact-instant special case: the table sum is the method. */
+int rco_doppler_lut(const double *x, int64_t n_in, double *y, int64_t n_out, double alpha,
+                    int h, int lut_size)
+{
+    if (!x || !y || n_in <= 0 || n_out < 0 || !(alpha > 0.0) || !isfinite(alpha) || h < 0 ||
+        lut_size < 2)
+        return 1;
+    double *lut = malloc(sizeof(double) * (size_t)lut_size);
+    if (!lut)
+        return 2;
+    const double u_max = (double)h + 0.5;
+    const double dx = u_max / (double)(lut_size - 1);
+    const double inv_dx = (double)(lut_size - 1) / u_max;
+    for (int i = 0; i < lut_size; ++i)
+        lut[i] = rco_sinc((double)i * dx);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t m = 0; m < n_out; ++m) {
+        double t = alpha * (double)m;
+        int64_t c = (int64_t)floor(t + 0.5);
+        double re = 0.0, im = 0.0;
+        for (int64_t n = c - h; n <= c + h; ++n) {
+            if (n < 0 || n >= n_in)
+                continue;
+            double u = fabs(t - (double)n);
+            int64_t i = (int64_t)floor(u * inv_dx + 0.5);
+            double w = (i < lut_size) ? lut[i] : 0.0;
+            re += x[2 * n] * w;
+            im += x[2 * n + 1] * w;
+        }
+        y[2 * m] = re;
+        y[2 * m + 1] = im;
+    }
+    free(lut);
+    return 0;
+}
+
+/* Linear interpolation (Sec. I, Table I): y[m] = (1 - mu) x[f] + mu x[f + 1] with
+ * t = alpha m, f = floor(t), mu = t - f; x[n] = 0 outside [0, n_in). */
+int rco_doppler_linear(const double *x, int64_t n_in, double *y, int64_t n_out, double alpha)
+{
+    if (!x || !y || n_in <= 0 || n_out < 0 || !(alpha > 0.0) || !isfinite(alpha))
+        return 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < n_out; ++m) {
+        double t = alpha * (double)m;
+        double f = floor(t), mu = t - f;
+        int64_t k = (int64_t)f;
+        double a_re = (k >= 0 && k < n_in) ? x[2 * k] : 0.0;
+        double a_im = (k >= 0 && k < n_in) ? x[2 * k + 1] : 0.0;
+        double b_re = (k + 1 >= 0 && k + 1 < n_in) ? x[2 * (k + 1)] : 0.0;
+        double b_im = (k + 1 >= 0 && k + 1 < n_in) ? x[2 * (k + 1) + 1] : 0.0;
+        y[2 * m] = (1.0 - mu) * a_re + mu * b_re;
+        y[2 * m + 1] = (1.0 - mu) * a_im + mu * b_im;
+    }
+    return 0;
+}
+
+/* Frequency conversion (Sec. I, Table I): the dilation of Eq (2) replaced by the frequency
+ * shift it causes at one reference frequency f_ref (Hz, on the samples' own frequency axis):
+ * y[m] = x[m] exp(2 pi i (alpha - 1) f_ref m / fs).  Exact for a tone at f_ref only. */
+int rco_doppler_tone(const double *x, int64_t n, double *y, double fs, double alpha, double f_ref)
+{
+    if (!x || !y || n < 0 || !(fs > 0.0) || !(alpha > 0.0) || !isfinite(alpha) || !isfinite(f_ref))
+        return 1;
+    const double nu = (alpha - 1.0) * f_ref / fs; /* cycles per sample */
+#pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < n; ++m) {
+        double cyc = nu * (double)m;
+        cyc -= floor(cyc); /* whole cycles dropped exactly */
+        double c = cos(2.0 * RCO_PI * cyc), s = sin(2.0 * RCO_PI * cyc);
+        double re = x[2 * m], im = x[2 * m + 1]; /* y may be x */
+        y[2 * m] = re * c - im * s;
+        y[2 * m + 1] = re * s + im * c;
+    }
+    return 0;
+}
+
+/* FFT P/Q resampling (Sec. I, Sec. III-A): the DFT of the n_in samples has bins removed or
+ * zero bins added to reach n_out bins, then the inverse DFT of length n_out is taken:
+ *   y[m] = (1/n_in) sum_j Y_j exp(2 pi i j m / n_out),
+ * i.e. the samples' trigonometric interpolant, limited to the band both lengths hold, at
+ * t = m n_in / n_out input samples.  With K = min(n_in, n_out), signed bins |k| < K/2 are
+ * copied; for even K the bin k = K/2 is, when removing bins, the sum of the input bins +K/2
+ * and -K/2 (both alias onto the output's Nyquist bin), and, when adding bins, the input
+ * Nyquist bin split in halves between output bins +K/2 and -K/2. */
+int rco_resample_fft(const double *x, int64_t n_in, double *y, int64_t n_out)
+{
+    if (!x || !y || n_in <= 0 || n_out <= 0)
+        return 1;
+    double *X = malloc(sizeof(double) * 2 * (size_t)n_in);
+    double *Y = calloc(2 * (size_t)n_out, sizeof(double));
+    if (!X || !Y) {
+        free(X); free(Y);
+        return 2;
+    }
+    int rc = rco_fft(x, X, n_in, -1);
+    if (!rc) {
+        int64_t K = n_in < n_out ? n_in : n_out;
+        int64_t half = (K - 1) / 2; /* bins with |k| <= half are copied */
+        for (int64_t k = -half; k <= half; ++k) {
+            int64_t si = (k + n_in) % n_in, di = (k + n_out) % n_out;
+            Y[2 * di] = X[2 * si];
+            Y[2 * di + 1] = X[2 * si + 1];
+        }
+        if (K % 2 == 0) {
+            int64_t k = K / 2;
+            if (n_out < n_in) { /* output Nyquist bin: input bins +K/2 and -K/2 */
+                int64_t a = k % n_in, b = (n_in - k) % n_in;
+                Y[2 * k] = X[2 * a] + X[2 * b];
+                Y[2 * k + 1] = X[2 * a + 1] + X[2 * b + 1];
+            } else if (n_out > n_in) { /* input Nyquist bin split between +K/2 and -K/2 */
+                int64_t d1 = k, d2 = n_out - k;
+                Y[2 * d1] = 0.5 * X[2 * k];
+                Y[2 * d1 + 1] = 0.5 * X[2 * k + 1];
+                Y[2 * d2] = 0.5 * X[2 * k];
+                Y[2 * d2 + 1] = 0.5 * X[2 * k + 1];
+            } else { /* same length: the bin itself */
+                Y[2 * k] = X[2 * k];
+                Y[2 * k + 1] = X[2 * k + 1];
+            }
+        }
+        rc = rco_fft(Y, y, n_out, +1);
+        if (!rc)
+            for (int64_t j = 0; j < 2 * n_out; ++j)
+                y[j] /= (double)n_in;
+    }
+    free(X); free(Y);
+    return rc;
+}
+
+/* The P/Q length for a dilation alpha (Sec. III-A): the n_in / alpha samples the dilated
+ * record spans, rounded so that an even number of samples is removed or added,
+ * n_i = n_in - 2 round((n_in - n_in / alpha) / 2) (half-way cases away from zero).
+ * Then alpha_eff = n_in / n_i is the dilation P/Q performs exactly. */
+int64_t rco_pq_length(int64_t n_in, double alpha)
+{
+    double d = ((double)n_in - (double)n_in / alpha) / 2.0;
+    return n_in - 2 * (int64_t)llround(d);
+}
+
+/* Doppler correction by FFT P/Q resampling (Sec. III-A): y[m] = P/Q resample of x to
+ * n_i = rco_pq_length(n_in, alpha) samples for m < min(n_i, n_out), 0 beyond (past the end of
+ * the dilated record).  With tone != 0 (P/Q "with frequency conversion"), the remaining
+ * dilation alpha / alpha_eff is then applied as frequency conversion at the reference
+ * frequency, which P/Q has moved to alpha_eff f_ref. */
+int rco_doppler_pq(const double *x, int64_t n_in, double *y, int64_t n_out, double fs, double alpha,
+                   double f_ref, int tone)
+{
+    if (!x || !y || n_in <= 0 || n_out < 0 || !(alpha > 0.0) || !isfinite(alpha) || !(fs > 0.0))
+        return 1;
+    int64_t ni = rco_pq_length(n_in, alpha);
+    if (ni <= 0)
+        return 1;
+    double *r = malloc(sizeof(double) * 2 * (size_t)ni);
+    if (!r)
+        return 2;
+    int rc = rco_resample_fft(x, n_in, r, ni);
+    if (!rc && tone) {
+        double a_eff = (double)n_in / (double)ni;
+        rc = rco_doppler_tone(r, ni, r, fs, alpha / a_eff, a_eff * f_ref);
+    }
+    if (!rc)
+        for (int64_t m = 0; m < n_out; ++m) {
+            y[2 * m] = m < ni ? r[2 * m] : 0.0;
+            y[2 * m + 1] = m < ni ? r[2 * m + 1] : 0.0;
+        }
+    free(r);
+    return rc;
+}
