@@ -138,6 +138,20 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
                              double fs_hz, double carrier_hz, double tec_el_per_m2,
                              int32_t direction, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): correct_ionosphere with the same arguments, result
+ * and kernels, that allocates nothing.  A length that is not a power of two takes its Bluestein
+ * workspace (2 M complex values, M the power of two >= 2n - 1) from a static 32 MiB device array
+ * of the library, one per GPU, held until the process ends; so such lengths are limited to
+ * n <= 2^20 (larger: RC_ERR_UNSUPPORTED).  Powers of two up to 2^24 need no workspace.  Every
+ * call on one GPU shares that array, whatever its context or stream: calls that overlap on one
+ * GPU (different streams, contexts or threads, not ordered by the caller) race on it and give
+ * undefined results.  The context must have been created by rc_create (which looks up the
+ * array's device address); no FFT plan is cached and no profiling span is recorded. */
+rc_status correct_ionosphere_noalloc(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n,
+                                     double fs_hz, double carrier_hz, double tec_el_per_m2,
+                                     int32_t direction, void *stream);
+
 /* Pulse compression with the ionospheric operator in the same frequency-domain pass (Sec. II-B
  * bundles Eq (15)/(16) with other FFT work such as pulse compression; Sec. II-D times it).
  * Matched filtering is the circular cross-correlation with a replica r zero-padded to n:

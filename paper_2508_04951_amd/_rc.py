@@ -23,7 +23,8 @@ DO_DOPPLER, DO_IONO = 1, 2
 # exported symbols of include/rc.h
 SYMBOLS = (
     "rc_create", "rc_destroy", "rc_status_string", "rc_last_error", "rc_alpha_from_vr",
-    "rc_k2_per_tec", "rc_sync", "correct_doppler", "correct_ionosphere", "correct_pulse_batch",
+    "rc_k2_per_tec", "rc_sync", "correct_doppler", "correct_ionosphere", "correct_ionosphere_noalloc",
+    "correct_pulse_batch",
     "correct_doppler_bank", "rc_server_create", "rc_server_submit", "rc_server_poll", "rc_server_wait",
     "rc_server_stats", "rc_server_reset_stats", "rc_server_destroy",
     "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine", "rc_set_bank_engine", "rc_set_mem_budget",
@@ -113,6 +114,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.correct_doppler_bank.restype = c_i32
         lib.correct_ionosphere.argtypes = [p, p, p, c_i64, c_d, c_d, c_d, c_i32, p]
         lib.correct_ionosphere.restype = c_i32
+        lib.correct_ionosphere_noalloc.argtypes = [p, p, p, c_i64, c_d, c_d, c_d, c_i32, p]
+        lib.correct_ionosphere_noalloc.restype = c_i32
         lib.replica_spectrum.argtypes = [p, p, c_i64, c_i64, p, p]
         lib.replica_spectrum.restype = c_i32
         lib.compress_pulse.argtypes = [p, p, p, c_i64, p, c_d, c_d, c_d, c_i32, p]
@@ -317,6 +320,23 @@ class Context:
                                           self._stream(stream))
         if st != RC_OK:
             self._raise(st, "correct_ionosphere")
+        return out
+
+    def correct_ionosphere_noalloc(self, x, out, fs: float, carrier: float, tec: float,
+                                   direction: str = "correct", stream=None):
+        """correct_ionosphere into a caller-given `out` (may be x) through the entry point that
+        allocates no device memory (lengths that are not powers of two: n <= 2^20)."""
+        _check_samples(x, "x")
+        _check_samples(out, "out")
+        if out.numel() != x.numel():
+            raise ValueError("out must have as many samples as x")
+        if direction not in DIRECTIONS:
+            raise ValueError(f"direction must be one of {list(DIRECTIONS)}")
+        st = self._lib.correct_ionosphere_noalloc(self._h, x.data_ptr(), out.data_ptr(), x.numel(), float(fs),
+                                                  float(carrier), float(tec), DIRECTIONS[direction],
+                                                  self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "correct_ionosphere_noalloc")
         return out
 
     def replica_spectrum(self, replica, n: int, out=None, stream=None):

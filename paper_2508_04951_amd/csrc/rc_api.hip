@@ -276,6 +276,58 @@ PhaseNum phase_numerator(double tec, int32_t direction, double fs, double carrie
 
 rc::Profiler *prof_of(rc_context ctx) { return ctx->prof.on ? &ctx->prof : nullptr; }
 
+// Workspace of correct_ionosphere_noalloc: Bluestein's convolution buffer and chirp spectrum,
+// 2 M complex values for a length n that is not a power of two (M the power of two >= 2n - 1),
+// so M <= 2^21 and n <= 2^20.  Each device holds its own copy for the life of the process.
+// Host code never takes this array's address directly: its device address comes from
+// hipGetSymbolAddress, once per device with that device current (scratch_on_device).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+__device__ __align__(256) float2 scratch[kStaticScratchBytes / sizeof(float2)];
+
+std::mutex g_scratch_mu;
+constexpr int kMaxScratchDevices = 64;
+float2 *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The device address of `scratch` on the current device (which must be `device`).
+hipError_t scratch_on_device(int device, float2 **out)
+{
+    if (device < 0 || device >= kMaxScratchDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch_ptr[device] = static_cast<float2 *>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+// Argument checks shared by correct_ionosphere and correct_ionosphere_noalloc.
+rc_status check_iono_args(rc_context ctx, const rc_c64 *x, const rc_c64 *y, int64_t n, double fs_hz,
+                          double carrier_hz, double tec_el_per_m2, int32_t direction)
+{
+    if (!x || !y)
+        return fail(ctx, RC_ERR_INVALID_ARG, "NULL sample pointer");
+    if (n <= 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "n must be > 0");
+    if (!(std::isfinite(fs_hz) && fs_hz > 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "fs_hz must be finite and > 0");
+    if (!std::isfinite(carrier_hz))
+        return fail(ctx, RC_ERR_INVALID_ARG, "carrier_hz must be finite");
+    if (!(std::isfinite(tec_el_per_m2) && tec_el_per_m2 >= 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "tec must be finite and >= 0");
+    if (direction != RC_CORRECT && direction != RC_DISTORT)
+        return fail(ctx, RC_ERR_INVALID_ARG, "direction must be RC_CORRECT or RC_DISTORT");
+    if (x != y && overlaps(x, n * 8, y, n * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "x and y partially overlap");
+    if (n > kMaxIonoLength)
+        return fail(ctx, RC_ERR_UNSUPPORTED, "n above 2^24 (power of two) or 2^23 (other lengths)");
+    return RC_OK;
+}
+
 enum class SincPath { Mfma, Fast, Direct };
 
 SincPath sinc_path(rc_context ctx, double alpha, const rc_sinc &k)
@@ -356,6 +408,8 @@ rc_status rc_create(int hip_device, rc_context *out)
         e = hipStreamCreateWithFlags(&ctx->tile_stream, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&ctx->tiles_done, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = scratch_on_device(hip_device, &ctx->static_scratch);
     if (e != hipSuccess) {
         if (ctx->tiles_done)
             (void)hipEventDestroy(ctx->tiles_done);
@@ -500,22 +554,9 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
         return RC_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->last_error.clear();
-    if (!x || !y)
-        return fail(ctx, RC_ERR_INVALID_ARG, "NULL sample pointer");
-    if (n <= 0)
-        return fail(ctx, RC_ERR_INVALID_ARG, "n must be > 0");
-    if (!(std::isfinite(fs_hz) && fs_hz > 0.0))
-        return fail(ctx, RC_ERR_INVALID_ARG, "fs_hz must be finite and > 0");
-    if (!std::isfinite(carrier_hz))
-        return fail(ctx, RC_ERR_INVALID_ARG, "carrier_hz must be finite");
-    if (!(std::isfinite(tec_el_per_m2) && tec_el_per_m2 >= 0.0))
-        return fail(ctx, RC_ERR_INVALID_ARG, "tec must be finite and >= 0");
-    if (direction != RC_CORRECT && direction != RC_DISTORT)
-        return fail(ctx, RC_ERR_INVALID_ARG, "direction must be RC_CORRECT or RC_DISTORT");
-    if (x != y && overlaps(x, n * 8, y, n * 8))
-        return fail(ctx, RC_ERR_INVALID_ARG, "x and y partially overlap");
-    if (n > kMaxIonoLength)
-        return fail(ctx, RC_ERR_UNSUPPORTED, "n above 2^24 (power of two) or 2^23 (other lengths)");
+    rc_status vs = check_iono_args(ctx, x, y, n, fs_hz, carrier_hz, tec_el_per_m2, direction);
+    if (vs != RC_OK)
+        return vs;
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const PhaseNum phase = phase_numerator(tec_el_per_m2, direction, fs_hz, carrier_hz, n);
@@ -544,6 +585,47 @@ rc_status correct_ionosphere(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t
     }
     if (e != hipSuccess)
         return device_fail(ctx, e, "correct_ionosphere launch");
+    return RC_OK;
+}
+
+rc_status correct_ionosphere_noalloc(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n, double fs_hz,
+                                     double carrier_hz, double tec_el_per_m2, int32_t direction, void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    rc_status vs = check_iono_args(ctx, x, y, n, fs_hz, carrier_hz, tec_el_per_m2, direction);
+    if (vs != RC_OK)
+        return vs;
+    const bool pow2 = is_pow2(n);
+    if (!pow2 && rc::bluestein_work_bytes(n) > kStaticScratchBytes)
+        return fail(ctx, RC_ERR_UNSUPPORTED,
+                    "correct_ionosphere_noalloc: a length that is not a power of two must be at most 2^20 "
+                    "(its Bluestein workspace exceeds the static 32 MiB)");
+    if (!ctx->static_scratch)
+        return fail(ctx, RC_ERR_DEVICE, "the static workspace has no device address");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const PhaseNum phase = phase_numerator(tec_el_per_m2, direction, fs_hz, carrier_hz, n);
+    const float2 *xf = reinterpret_cast<const float2 *>(x);
+    float2 *yf = reinterpret_cast<float2 *>(y);
+    // the plan is rebuilt here rather than taken from (and inserted into) the context's cache;
+    // building one only fills the struct
+    FftPlan plan;
+    std::vector<void *> no_allocs;
+    hipError_t e = rc::build_fft_plan(iono_plan_length(n), plan, no_allocs);
+    if (e != hipSuccess)
+        return fail(ctx, RC_ERR_UNSUPPORTED, "transform length not supported");
+    if (pow2) {
+        const IonoJob job{xf, yf, phase, carrier_hz, fs_hz, nullptr};
+        e = rc::launch_iono(plan, ctx->tw4096, nullptr, &job, 1, s, nullptr);
+    } else {
+        const rc::BluesteinJob jb{xf, yf, ctx->static_scratch, n, phase, carrier_hz, fs_hz, nullptr};
+        e = rc::launch_iono_bluestein(plan, ctx->tw4096, nullptr, nullptr, jb, 1, n, s, nullptr);
+    }
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "correct_ionosphere_noalloc launch");
     return RC_OK;
 }
 

@@ -317,4 +317,7 @@ struct rc_context_s {
     int sinc_engine = 0;  // RC_SINC_AUTO / RC_SINC_VALU / RC_SINC_DIRECT
     int bank_engine = 0;  // RC_BANK_ENGINE_AUTO / _FARROW / _PER_HYPOTHESIS
     int64_t mem_budget = 0;  // cap on the slots' device workspace in bytes (rc_set_mem_budget); 0: none
+    // device address of this device's copy of the library's static workspace (the
+    // no-allocation entry point's Bluestein buffers), looked up once per device at rc_create
+    float2 *static_scratch = nullptr;
 };
