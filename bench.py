@@ -435,6 +435,133 @@ def run_paper_sinc(args, torch, rc):
     print(json.dumps(out), flush=True)
 
 
+def device_times_us(torch, call, calls: int, warm: int):
+    """Per-call device time (HIP events on torch's current stream, which the calls use)."""
+    for _ in range(warm):
+        call()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for a, b in ev:
+        a.record()
+        call()
+        b.record()
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+
+
+def run_ablation(args, torch, rc):
+    """The App. C ablation (Fig. 9) repeated here: one 2^19-sample resample with the paper's
+    25-sample window by its Alg. 1 (direct), Alg. 3 (tiled) and Alg. 2 (lookup table of 3000 and
+    of 300 entries) kernels, each launched with the paper's 32 blocks and with one output per
+    thread, beside this library's own paper-window kernel."""
+    c = wf.PAPER_SINC
+    n, fs = c["n"], c["fs"]
+    alpha = alpha_exact(c["v_r"])
+    h = c["half_width"]
+    xh = wf.lfm_rf(n, fs, c["f0"], c["bandwidth"])
+    ctx = rc.Context(0)
+    x = torch.from_numpy(xh).cuda()
+    y = torch.empty_like(x)
+    calls, warm = max(500, args.steps * 10), 50
+    import oracle
+
+    oracle.build()
+    exact = oracle.doppler(xh, alpha, half_width=h, window="paper")
+    paper_us = {"direct": 150.5, "tiled": 159.0, "lut3000": 60.5, "lut300": 59.3}
+    rows = {}
+    for name, variant, lut in (("direct", "direct", 0), ("tiled", "tiled", 0), ("lut3000", "lut", 3000),
+                               ("lut300", "lut", 300)):
+        for blocks in (32, 0):
+            def call():
+                ctx.correct_doppler_paper(x, alpha, 2 * h + 1, variant, lut_size=max(lut, 2), blocks=blocks, out=y)
+
+            us = device_times_us(torch, call, calls, warm)
+            got = y.cpu().numpy()
+            ref = oracle.doppler_lut(xh, alpha, h, lut) if variant == "lut" else exact
+            rows[f"{name}_blocks{blocks or 'full'}"] = {
+                "p50_us": round(float(np.percentile(us, 50)), 2), "p99_us": round(float(np.percentile(us, 99)), 2),
+                "rel_err_vs_own_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                "rel_err_vs_exact_window": float(np.linalg.norm(got - exact) / np.linalg.norm(exact)),
+                "paper_h100_us_32_blocks": paper_us[name]}
+            log(f"[bench] ablation {name} blocks={blocks or 'full'}: p50 {np.percentile(us, 50):.2f} us")
+    sinc = rc.Sinc(h, "paper", 0.0)
+
+    def lib_call():
+        ctx.correct_doppler(x, alpha, sinc, out=y)
+
+    us = device_times_us(torch, lib_call, calls, warm)
+    got = y.cpu().numpy()
+    rows["library_paper_window"] = {"p50_us": round(float(np.percentile(us, 50)), 2),
+                                    "p99_us": round(float(np.percentile(us, 99)), 2),
+                                    "rel_err_vs_exact_window": float(np.linalg.norm(got - exact) / np.linalg.norm(exact))}
+    best = min(v["p50_us"] for v in rows.values())
+    out = {"metric": "App. C ablation: device time per 2^19-sample resample, 25-sample window (best variant)",
+           "value": best, "unit": "us", "n_gpus": 1, "steps": calls, "warmup": warm, "ms_per_step": best * 1e-3,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{n} samples at 2.048 GHz: LFM 413-431 MHz, v_r = 1 km/s, 25-sample window; "
+                                  "the paper's Alg. 1/2/3 kernels at 32 blocks and at one output per thread",
+                      "samples": n},
+           "variants": rows, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+def run_methods(args, torch, rc):
+    """Error against velocity of the Doppler methods (Sec. III-A, Fig. 5): every method on the GPU
+    against the analytic dilated LFM, as SNR loss (dB) and relative L2 error, at velocities
+    0 .. 5 km/s; each method's device time at the largest velocity."""
+    c = wf.METHODS
+    fs, f0, B, T = c["fs"], c["f0"], c["bandwidth"], c["pulse_s"]
+    n = int(round(T * fs))
+    t = np.arange(n) / fs
+
+    def lfm(tt):
+        return np.where((tt >= 0) & (tt < T), np.exp(2j * np.pi * (f0 * tt + 0.5 * B / T * tt * tt)), 0)
+
+    xh = lfm(t).astype(np.complex64)
+    x = torch.from_numpy(xh).cuda()
+    ctx = rc.Context(0)
+    h = (c["n_window"] - 1) // 2
+    kaiser = rc.Sinc(64, "kaiser", 8.0)
+    paper = rc.Sinc(h, "paper", 0.0)
+    methods = {
+        "sinc_kaiser_h64": lambda a: ctx.correct_doppler(x, a, kaiser),
+        "sinc_paper_25": lambda a: ctx.correct_doppler(x, a, paper),
+        "sinc_paper_25_lut": lambda a: ctx.correct_doppler_paper(x, a, c["n_window"], "lut", lut_size=c["lut_size"]),
+        "linear": lambda a: ctx.correct_doppler_linear(x, a),
+        "frequency_conversion": lambda a: ctx.correct_doppler_tone(x, fs, a, c["f_ref"]),
+        "fft_pq": lambda a: ctx.correct_doppler_fft_pq(x, fs, a),
+        "fft_pq_tone": lambda a: ctx.correct_doppler_fft_pq(x, fs, a, f_ref=c["f_ref"], tone=True),
+    }
+    vs = np.linspace(0.0, c["v_max"], c["points"])
+    table = {k: {"snr_loss_db": [], "rel_l2": []} for k in methods}
+    for v in vs:
+        a = alpha_exact(v)
+        ref = lfm(a * t)
+        nr = np.linalg.norm(ref)
+        for k, f in methods.items():
+            got = f(a).cpu().numpy().astype(np.complex128)
+            rho = abs(np.vdot(ref, got)) / (nr * np.linalg.norm(got))
+            table[k]["snr_loss_db"].append(float(-20 * np.log10(min(rho, 1.0))))
+            table[k]["rel_l2"].append(float(np.linalg.norm(got - ref) / nr))
+    a_max = alpha_exact(c["v_max"])
+    for k, f in methods.items():
+        us = device_times_us(torch, lambda: f(a_max), 200, 20)
+        table[k]["p50_us_at_vmax"] = round(float(np.percentile(us, 50)), 2)
+        table[k]["samples_per_s_at_vmax"] = round(n / (np.percentile(us, 50) * 1e-6), 1)
+    kmax = max(range(len(vs)), key=lambda i: table["sinc_kaiser_h64"]["rel_l2"][i])
+    out = {"metric": "Doppler methods vs velocity (Fig. 5 setup): relative L2 error of the Kaiser H=64 sinc "
+                     "resampler against the analytic dilated LFM, worst velocity",
+           "value": table["sinc_kaiser_h64"]["rel_l2"][kmax], "unit": "rel_l2", "n_gpus": 1, "steps": len(vs),
+           "warmup": 0, "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"LFM {f0 / 1e6:.0f}-{(f0 + B) / 1e6:.0f} MHz, {T * 1e6:.0f} us, sampled at RF at "
+                                  f"{fs / 1e9:.0f} GHz ({n} samples); v = 0..{c['v_max'] / 1e3:.0f} km/s",
+                      "samples": n},
+           "velocities_mps": [float(v) for v in vs], "pq_lengths": [rc.pq_length(n, alpha_exact(v)) for v in vs],
+           "methods": table, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def run_long(args, torch, rc):
     """64 pulses of 2^24 samples at H = 128: Doppler then the 2^24-point ionospheric FFT."""
     c = wf.LONG_DWELL
@@ -598,13 +725,16 @@ def main():
                          "HBM traffic counters)")
     ap.add_argument("--engine", choices=["auto", "valu", "direct"], default="auto",
                     help="resampling engine (auto: matrix cores where eligible)")
-    ap.add_argument("--workload", choices=["batch", "bank", "long", "serving", "single", "compress", "paper_sinc"],
+    ap.add_argument("--workload", choices=["batch", "bank", "long", "serving", "single", "compress", "paper_sinc",
+                                           "ablation", "methods"],
                     default="batch",
                     help="batch: 1024 x 65536 pulses (the headline); bank: one 2^20-sample pulse x 256 "
                          "Doppler hypotheses; long: 64 x 2^24-sample pulses at H = 128; serving: Poisson "
                          "arrivals at 2000 pulses/s, lengths 2^12..2^22, through the server; single: one "
                          "4096-sample LFM, full sinc then ionosphere; compress: pulse compression with the "
-                         "correction, 2^19 samples; paper_sinc: one 2^19-sample resample, 25-sample window")
+                         "correction, 2^19 samples; paper_sinc: one 2^19-sample resample, 25-sample window; "
+                         "ablation: the paper's App. C sinc kernels on that setup; methods: error against "
+                         "velocity of every Doppler method (Fig. 5 setup)")
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -628,6 +758,10 @@ def main():
         return run_compress(args, torch, rc)
     if args.workload == "paper_sinc":
         return run_paper_sinc(args, torch, rc)
+    if args.workload == "ablation":
+        return run_ablation(args, torch, rc)
+    if args.workload == "methods":
+        return run_methods(args, torch, rc)
     if args.workload == "serving":
         return run_serving(args, torch, rc)
     dev = torch.device("cuda:0")

@@ -299,6 +299,67 @@ rc_status rc_set_mem_budget(rc_context ctx, int64_t bytes);
 rc_status rc_profile_enable(rc_context ctx, int enable);
 rc_status rc_profile_read(rc_context ctx, const char *kernel, double *total_ms, int64_t *launches);
 
+/* ---------------------------------------------------------------------------------------
+ * The paper's other Doppler resampling methods, as baselines beside correct_doppler.
+ * Same conventions: device pointers, asynchronous on `stream`, x and y must not overlap
+ * (except correct_doppler_tone, which may work in place), alpha finite and > 0, fs_hz > 0.
+ * ------------------------------------------------------------------------------------- */
+
+/* Variants of the paper's own GPU sinc kernel (App. C). */
+enum {
+    RC_PAPER_DIRECT = 0, /* Alg. 1: one thread per output, sinc computed per tap */
+    RC_PAPER_TILED = 1,  /* Alg. 3: each block stages its inputs in LDS first ("tiling") */
+    RC_PAPER_LUT = 2     /* Alg. 2: sinc from an LDS table of its positive half */
+};
+
+/* The paper's windowed Whittaker-Shannon kernel (App. C, Fig. 10): output m sums the
+ * n_window (odd, >= 1) inputs centred on the nearest input c = floor(alpha m + 1/2),
+ * y[m] = sum_{|n - c| <= (n_window-1)/2} x[n] sinc(alpha m - n), untapered, in the structure
+ * of the paper's kernels: a grid-stride loop over outputs with `blocks` blocks of 256 threads
+ * (0: one output per thread; the paper's H100 runs used 32).  RC_PAPER_DIRECT and
+ * RC_PAPER_TILED compute the same sum (bit-identical) and equal correct_doppler with
+ * RC_WIN_PAPER to float32 rounding.  RC_PAPER_LUT takes sinc from a table of lut_size
+ * (2 .. 16384) values sinc(i dx), i = 0 .. lut_size-1, dx = (h + 1/2) / (lut_size - 1),
+ * h = (n_window-1)/2: a tap at distance u = |alpha m - n| takes entry floor(u / dx + 1/2)
+ * (the nearest); lut_size = 100 (h + 1/2) + 1 gives the dx = 1/100 of Sec. III-A, Fig. 5.
+ * RC_PAPER_TILED needs (ceil(255 alpha) + n_window + 2) * 8 bytes of LDS, at most 64 KiB
+ * (RC_ERR_UNSUPPORTED above). */
+rc_status correct_doppler_paper(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 *y,
+                                int64_t n_out, double fs_hz, double alpha, int32_t n_window,
+                                int32_t variant, int32_t lut_size, int32_t blocks, void *stream);
+
+/* Linear interpolation (Sec. I, Table I): y[m] = (1 - mu) x[f] + mu x[f + 1] at
+ * t = alpha m, f = floor(t), mu = t - f; x = 0 outside [0, n_in). */
+rc_status correct_doppler_linear(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 *y,
+                                 int64_t n_out, double fs_hz, double alpha, void *stream);
+
+/* Frequency conversion (Sec. I, Table I): the dilation replaced by the frequency shift it
+ * causes at one reference frequency f_ref_hz (on the samples' own frequency axis):
+ * y[m] = x[m] exp(2 pi i (alpha - 1) f_ref_hz m / fs_hz).  Exact for a tone at f_ref_hz only.
+ * y may equal x. */
+rc_status correct_doppler_tone(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n,
+                               double fs_hz, double alpha, double f_ref_hz, void *stream);
+
+/* Length of the FFT P/Q resampled record for a dilation alpha (Sec. III-A): the n_in / alpha
+ * samples the dilated record spans, rounded so that an even number of samples is removed or
+ * added: n_in - 2 round((n_in - n_in / alpha) / 2) (halves away from zero).  0 if alpha is not
+ * finite and > 0 or n_in < 1. */
+int64_t rc_pq_length(int64_t n_in, double alpha);
+
+/* Doppler correction by FFT P/Q resampling (Sec. I, Sec. III-A): the DFT of x has bins removed
+ * or zero bins added to reach n_i = rc_pq_length(n_in, alpha) bins, then the inverse DFT:
+ *   y[m] = (1/n_in) sum_j Y_j exp(2 pi i j m / n_i),  m < min(n_i, n_out),  0 beyond,
+ * the trigonometric interpolant of x at t = m n_in / n_i (exact dilation by n_in / n_i).
+ * With K = min(n_in, n_i), signed bins |k| <= (K-1)/2 are copied; for even K the bin K/2 is
+ * the sum of input bins +K/2 and -K/2 when removing, and half the input Nyquist bin at +K/2
+ * and at -K/2 when adding.  With with_tone != 0 the remaining dilation alpha / alpha_eff
+ * (alpha_eff = n_in / n_i) follows as frequency conversion at alpha_eff f_ref_hz ("P/Q with
+ * frequency conversion").  n_i == n_in transforms nothing.  2 <= n_in, n_i <= 2^23; the
+ * transforms run Bluestein's chirp convolution (workspace from the context). */
+rc_status correct_doppler_fft_pq(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 *y,
+                                 int64_t n_out, double fs_hz, double alpha, double f_ref_hz,
+                                 int32_t with_tone, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,9 +29,13 @@ SYMBOLS = (
     "rc_server_stats", "rc_server_reset_stats", "rc_server_destroy",
     "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine", "rc_set_bank_engine", "rc_set_mem_budget",
     "replica_spectrum", "compress_pulse",
+    "correct_doppler_paper", "correct_doppler_linear", "correct_doppler_tone", "rc_pq_length",
+    "correct_doppler_fft_pq",
 )
 KERNELS = ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono",
-           "k_fft_strided_inv", "k_mf_tile_list", "k_bluestein", "k_farrow_z", "k_farrow_bank")
+           "k_fft_strided_inv", "k_mf_tile_list", "k_bluestein", "k_farrow_z", "k_farrow_bank",
+           "k_paper_sinc", "k_linear", "k_tone", "k_pq")
+PAPER_VARIANTS = {"direct": 0, "tiled": 1, "lut": 2}
 BANK_PRECISIONS = {"fp16x3": 0, "bf16x3": 1, "fp32": 2}
 BANK_ENGINES = {"auto": 0, "farrow": 1, "per_hypothesis": 2}
 SINC_ENGINES = {"auto": 0, "valu": 1, "direct": 2}
@@ -116,6 +120,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.correct_ionosphere.restype = c_i32
         lib.correct_ionosphere_noalloc.argtypes = [p, p, p, c_i64, c_d, c_d, c_d, c_i32, p]
         lib.correct_ionosphere_noalloc.restype = c_i32
+        lib.correct_doppler_paper.argtypes = [p, p, c_i64, p, c_i64, c_d, c_d, c_i32, c_i32, c_i32, c_i32, p]
+        lib.correct_doppler_paper.restype = c_i32
+        lib.correct_doppler_linear.argtypes = [p, p, c_i64, p, c_i64, c_d, c_d, p]
+        lib.correct_doppler_linear.restype = c_i32
+        lib.correct_doppler_tone.argtypes = [p, p, p, c_i64, c_d, c_d, c_d, p]
+        lib.correct_doppler_tone.restype = c_i32
+        lib.rc_pq_length.argtypes = [c_i64, c_d]
+        lib.rc_pq_length.restype = c_i64
+        lib.correct_doppler_fft_pq.argtypes = [p, p, c_i64, p, c_i64, c_d, c_d, c_d, c_i32, p]
+        lib.correct_doppler_fft_pq.restype = c_i32
         lib.replica_spectrum.argtypes = [p, p, c_i64, c_i64, p, p]
         lib.replica_spectrum.restype = c_i32
         lib.compress_pulse.argtypes = [p, p, p, c_i64, p, c_d, c_d, c_d, c_i32, p]
@@ -160,6 +174,11 @@ def _alpha_or_vr(alpha, v_r) -> float:
         if alpha != alpha:  # NaN: |v_r| >= c
             raise ValueError("|v_r| must be below the speed of light")
     return float(alpha)
+
+
+def pq_length(n_in: int, alpha: float) -> int:
+    """Length of the FFT P/Q resampled record (an even number of samples removed or added)."""
+    return int(load_library().rc_pq_length(int(n_in), float(alpha)))
 
 
 def k2_per_tec() -> float:
@@ -337,6 +356,70 @@ class Context:
                                                   self._stream(stream))
         if st != RC_OK:
             self._raise(st, "correct_ionosphere_noalloc")
+        return out
+
+    def _out_for(self, x, n_out, out):
+        torch = _torch()
+        _check_samples(x, "x")
+        n_out = x.numel() if n_out is None else int(n_out)
+        if out is None:
+            out = torch.empty(n_out, dtype=torch.complex64, device=x.device)
+        _check_samples(out, "out")
+        if out.numel() < n_out:
+            raise ValueError("out is shorter than n_out")
+        return n_out, out
+
+    def correct_doppler_paper(self, x, alpha: float | None = None, n_window: int = 25, variant: str = "direct",
+                              lut_size: int = 3000, blocks: int = 0, n_out: int | None = None, fs: float = 1.0,
+                              out=None, stream=None, *, v_r: float | None = None):
+        """The paper's sinc kernel (App. C): n_window inputs centred on the nearest, untapered, in
+        the variant "direct" (Alg. 1), "tiled" (Alg. 3) or "lut" (Alg. 2, lut_size entries)."""
+        alpha = _alpha_or_vr(alpha, v_r)
+        if variant not in PAPER_VARIANTS:
+            raise ValueError(f"variant must be one of {list(PAPER_VARIANTS)}")
+        n_out, out = self._out_for(x, n_out, out)
+        st = self._lib.correct_doppler_paper(self._h, x.data_ptr(), x.numel(), out.data_ptr(), n_out, float(fs),
+                                             float(alpha), int(n_window), PAPER_VARIANTS[variant], int(lut_size),
+                                             int(blocks), self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "correct_doppler_paper")
+        return out
+
+    def correct_doppler_linear(self, x, alpha: float | None = None, n_out: int | None = None, fs: float = 1.0,
+                               out=None, stream=None, *, v_r: float | None = None):
+        """Linear interpolation at t = alpha m (Sec. I, Table I)."""
+        alpha = _alpha_or_vr(alpha, v_r)
+        n_out, out = self._out_for(x, n_out, out)
+        st = self._lib.correct_doppler_linear(self._h, x.data_ptr(), x.numel(), out.data_ptr(), n_out, float(fs),
+                                              float(alpha), self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "correct_doppler_linear")
+        return out
+
+    def correct_doppler_tone(self, x, fs: float, alpha: float | None = None, f_ref: float = 0.0, out=None,
+                             stream=None, *, v_r: float | None = None):
+        """Frequency conversion: x[m] exp(2 pi i (alpha - 1) f_ref m / fs).  out may be x."""
+        alpha = _alpha_or_vr(alpha, v_r)
+        _, out = self._out_for(x, None, out)
+        if out.numel() != x.numel():
+            raise ValueError("out must have as many samples as x")
+        st = self._lib.correct_doppler_tone(self._h, x.data_ptr(), out.data_ptr(), x.numel(), float(fs),
+                                            float(alpha), float(f_ref), self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "correct_doppler_tone")
+        return out
+
+    def correct_doppler_fft_pq(self, x, fs: float, alpha: float | None = None, f_ref: float = 0.0,
+                               tone: bool = False, n_out: int | None = None, out=None, stream=None, *,
+                               v_r: float | None = None):
+        """FFT P/Q resampling to pq_length(n, alpha) samples, then (tone=True) frequency conversion
+        of the remaining dilation at the moved reference frequency (Sec. III-A)."""
+        alpha = _alpha_or_vr(alpha, v_r)
+        n_out, out = self._out_for(x, n_out, out)
+        st = self._lib.correct_doppler_fft_pq(self._h, x.data_ptr(), x.numel(), out.data_ptr(), n_out, float(fs),
+                                              float(alpha), float(f_ref), int(bool(tone)), self._stream(stream))
+        if st != RC_OK:
+            self._raise(st, "correct_doppler_fft_pq")
         return out
 
     def replica_spectrum(self, replica, n: int, out=None, stream=None):

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librc.so")
-SOURCES = ["rc_api.hip", "sinc.hip", "sinc_mfma.hip", "fft.hip", "bank.hip"]
+SOURCES = ["rc_api.hip", "sinc.hip", "sinc_mfma.hip", "fft.hip", "bank.hip", "methods.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for every device compile.

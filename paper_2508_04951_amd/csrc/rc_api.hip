@@ -629,6 +629,170 @@ rc_status correct_ionosphere_noalloc(rc_context ctx, const rc_c64 *x, rc_c64 *y,
     return RC_OK;
 }
 
+// --- the paper's other resampling methods ---------------------------------------------------
+
+// Checks shared by the baseline resamplers: pointers, lengths, fs and alpha.
+rc_status check_resample_args(rc_context ctx, const rc_c64 *x, int64_t n_in, const rc_c64 *y, int64_t n_out,
+                              double fs_hz, double alpha)
+{
+    if (!x || !y)
+        return fail(ctx, RC_ERR_INVALID_ARG, "NULL sample pointer");
+    if (n_in <= 0 || n_out <= 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "n_in and n_out must be > 0");
+    if (!(std::isfinite(fs_hz) && fs_hz > 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "fs_hz must be finite and > 0");
+    if (!(std::isfinite(alpha) && alpha > 0.0))
+        return fail(ctx, RC_ERR_INVALID_ARG, "alpha must be finite and > 0");
+    return RC_OK;
+}
+
+rc_status correct_doppler_paper(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 *y, int64_t n_out,
+                                double fs_hz, double alpha, int32_t n_window, int32_t variant, int32_t lut_size,
+                                int32_t blocks, void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    rc_status st = check_resample_args(ctx, x, n_in, y, n_out, fs_hz, alpha);
+    if (st != RC_OK)
+        return st;
+    if (overlaps(x, n_in * 8, y, n_out * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "x and y overlap");
+    if (n_window < 1 || (n_window & 1) == 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "n_window must be odd and >= 1");
+    if (variant != RC_PAPER_DIRECT && variant != RC_PAPER_TILED && variant != RC_PAPER_LUT)
+        return fail(ctx, RC_ERR_INVALID_ARG, "unknown variant");
+    if (variant == RC_PAPER_LUT && (lut_size < 2 || lut_size > 16384))
+        return fail(ctx, RC_ERR_INVALID_ARG, "lut_size must be in [2, 16384]");
+    if (blocks < 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "blocks must be >= 0");
+    const int h = (n_window - 1) / 2;
+    if (variant == RC_PAPER_TILED && (alpha > 1e6 || rc::paper_tiled_lds_bytes(alpha, h) > 65536))
+        return fail(ctx, RC_ERR_UNSUPPORTED, "the tiled kernel's input span exceeds 64 KiB of LDS");
+    DeviceGuard g(ctx->device);
+    rc::PaperArgs a{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y), n_in, n_out, alpha, h,
+                    lut_size, 0.0, 0.0};
+    if (variant == RC_PAPER_LUT) {
+        const double u_max = (double)h + 0.5;
+        a.dx = u_max / (double)(lut_size - 1);
+        a.inv_dx = (double)(lut_size - 1) / u_max;
+    }
+    const hipError_t e = rc::launch_paper_sinc(a, variant, blocks, static_cast<hipStream_t>(stream), prof_of(ctx));
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "correct_doppler_paper launch");
+    return RC_OK;
+}
+
+rc_status correct_doppler_linear(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 *y, int64_t n_out,
+                                 double fs_hz, double alpha, void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    rc_status st = check_resample_args(ctx, x, n_in, y, n_out, fs_hz, alpha);
+    if (st != RC_OK)
+        return st;
+    if (overlaps(x, n_in * 8, y, n_out * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "x and y overlap");
+    DeviceGuard g(ctx->device);
+    const hipError_t e = rc::launch_linear(reinterpret_cast<const float2 *>(x), n_in, reinterpret_cast<float2 *>(y),
+                                           n_out, alpha, static_cast<hipStream_t>(stream), prof_of(ctx));
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "correct_doppler_linear launch");
+    return RC_OK;
+}
+
+rc_status correct_doppler_tone(rc_context ctx, const rc_c64 *x, rc_c64 *y, int64_t n, double fs_hz, double alpha,
+                               double f_ref_hz, void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    rc_status st = check_resample_args(ctx, x, n, y, n, fs_hz, alpha);
+    if (st != RC_OK)
+        return st;
+    if (!std::isfinite(f_ref_hz))
+        return fail(ctx, RC_ERR_INVALID_ARG, "f_ref_hz must be finite");
+    if (x != y && overlaps(x, n * 8, y, n * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "x and y partially overlap");
+    DeviceGuard g(ctx->device);
+    const double nu = (alpha - 1.0) * f_ref_hz / fs_hz;
+    const hipError_t e = rc::launch_tone(reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y), n, nu,
+                                         static_cast<hipStream_t>(stream), prof_of(ctx));
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "correct_doppler_tone launch");
+    return RC_OK;
+}
+
+int64_t rc_pq_length(int64_t n_in, double alpha)
+{
+    if (n_in < 1 || !(std::isfinite(alpha) && alpha > 0.0))
+        return 0;
+    const double d = ((double)n_in - (double)n_in / alpha) / 2.0;
+    return n_in - 2 * (int64_t)std::llround(d);
+}
+
+rc_status correct_doppler_fft_pq(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 *y, int64_t n_out,
+                                 double fs_hz, double alpha, double f_ref_hz, int32_t with_tone, void *stream)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    rc_status st = check_resample_args(ctx, x, n_in, y, n_out, fs_hz, alpha);
+    if (st != RC_OK)
+        return st;
+    if (!std::isfinite(f_ref_hz))
+        return fail(ctx, RC_ERR_INVALID_ARG, "f_ref_hz must be finite");
+    if (overlaps(x, n_in * 8, y, n_out * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "x and y overlap");
+    const int64_t ni = rc_pq_length(n_in, alpha);
+    const int64_t kMaxPq = int64_t(1) << 23;
+    if (n_in < 2 || ni < 2 || n_in > kMaxPq || ni > kMaxPq)
+        return fail(ctx, RC_ERR_UNSUPPORTED, "FFT P/Q needs 2 <= n_in and the resampled length <= 2^23");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc::PqArgs a{reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(y), n_in, ni, n_out,
+                 nullptr, nullptr, nullptr, with_tone != 0, 0.0};
+    if (with_tone) {
+        const double a_eff = (double)n_in / (double)ni;
+        a.nu = (alpha / a_eff - 1.0) * (a_eff * f_ref_hz) / fs_hz;
+    }
+    const FftPlan *plan_in = nullptr, *plan_out = nullptr;
+    hipError_t e;
+    if (ni == n_in) {
+        e = rc::launch_pq(a, FftPlan{}, FftPlan{}, ctx->tw4096, s, prof_of(ctx));
+    } else {
+        st = get_plan(ctx, rc::bluestein_m(n_in), &plan_in);
+        if (st == RC_OK)
+            st = get_plan(ctx, rc::bluestein_m(ni), &plan_out);
+        if (st != RC_OK)
+            return st;
+        // workspace: X, then Y, then the larger Bluestein buffer, each 256-byte aligned
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t bx = al((size_t)n_in * 8), by = al((size_t)ni * 8);
+        const size_t bw = std::max(rc::bluestein_work_bytes(n_in), rc::bluestein_work_bytes(ni));
+        const void *dev = nullptr;
+        st = stage_descriptors(ctx, nullptr, 0, bx + by + bw, s, &dev);
+        if (st != RC_OK)
+            return st;
+        char *w = static_cast<char *>(const_cast<void *>(dev));
+        a.X = reinterpret_cast<float2 *>(w);
+        a.Y = reinterpret_cast<float2 *>(w + bx);
+        a.work = reinterpret_cast<float2 *>(w + bx + by);
+        e = rc::launch_pq(a, *plan_in, *plan_out, ctx->tw4096, s, prof_of(ctx));
+        st = mark_descriptors_used(ctx, s);
+        if (e == hipSuccess && st != RC_OK)
+            return st;
+    }
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "correct_doppler_fft_pq launch");
+    return RC_OK;
+}
+
 rc_status replica_spectrum(rc_context ctx, const rc_c64 *replica, int64_t n_rep, int64_t n, rc_c64 *spec,
                            void *stream)
 {
@@ -1560,7 +1724,8 @@ namespace rc {
 
 const char *const kKernelNames[kKGroups] = {"k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd",
                                             "k_fft_rows_iono", "k_fft_strided_inv", "k_sinc_mfma",
-                                            "k_mf_tile_list", "k_bluestein", "k_farrow_z", "k_farrow_bank"};
+                                            "k_mf_tile_list", "k_bluestein", "k_farrow_z", "k_farrow_bank",
+                                            "k_paper_sinc", "k_linear", "k_tone", "k_pq"};
 
 hipEvent_t Profiler::take()
 {

@@ -25,6 +25,10 @@ enum KernelGroup {
     kKBluestein,
     kKFarrowZ,
     kKFarrowBank,
+    kKPaperSinc,
+    kKLinear,
+    kKTone,
+    kKPq,
     kKGroups
 };
 extern const char *const kKernelNames[kKGroups];
@@ -280,6 +284,42 @@ hipError_t launch_iono_bluestein(const FftPlan &mplan, const float2 *tw4096, con
 // bin order, unnormalised (phase and corr unused).  y may equal x.
 hipError_t launch_bluestein_forward(const FftPlan &mplan, const float2 *tw4096, const BluesteinJob &inl,
                                     hipStream_t s, Profiler *prof);
+
+// ---------------------------------------------------------------------------------------
+// The paper's other resampling methods (methods.hip)
+// ---------------------------------------------------------------------------------------
+
+// One call of the paper's sinc kernels (App. C): 2h + 1 taps centred on the nearest input.
+struct PaperArgs {
+    const float2 *x;
+    float2 *y;
+    int64_t n_in, n_out;
+    double alpha;
+    int64_t h;
+    int lut_size;        // Alg. 2 table entries
+    double dx, inv_dx;   // Alg. 2 table spacing (h + 1/2) / (lut_size - 1) and its inverse
+};
+// Dynamic LDS of the tiled kernel (Alg. 3): the inputs of 256 consecutive outputs.
+size_t paper_tiled_lds_bytes(double alpha, int h);
+// variant: RC_PAPER_DIRECT / RC_PAPER_TILED / RC_PAPER_LUT; blocks 0: one output per thread.
+hipError_t launch_paper_sinc(const PaperArgs &a, int variant, int blocks, hipStream_t s, Profiler *prof);
+hipError_t launch_linear(const float2 *x, int64_t n_in, float2 *y, int64_t n_out, double alpha, hipStream_t s,
+                         Profiler *prof);
+// y[m] = x[m] exp(2 pi i nu m), nu in cycles per sample; y may equal x.
+hipError_t launch_tone(const float2 *x, float2 *y, int64_t n, double nu, hipStream_t s, Profiler *prof);
+// FFT P/Q resampling of x (n_in samples) to ni samples, written to y[0, n_out) (zeros past ni),
+// optionally turned by exp(2 pi i nu m).  Workspace: X (n_in complex), Y (ni complex) and `work`
+// (bluestein_work_bytes of the larger length).  ni == n_in: no transform, y is x (turned).
+struct PqArgs {
+    const float2 *x;
+    float2 *y;
+    int64_t n_in, ni, n_out;
+    float2 *X, *Y, *work;
+    int tone;
+    double nu;
+};
+hipError_t launch_pq(const PqArgs &a, const FftPlan &plan_in, const FftPlan &plan_out, const float2 *tw4096,
+                     hipStream_t s, Profiler *prof);
 
 }  // namespace rc
 

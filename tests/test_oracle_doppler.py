@@ -355,7 +355,8 @@ def _mutant_doppler(tmp_path, old, new):
 
 
 @pytest.mark.parametrize("old,new", [
-    ("(int64_t)floor(t + 0.5)", "(int64_t)floor(t)"),          # paper-mode centre at floor(t)
+    ("(int64_t)floor(t + 0.5); /* nearest input sample */",
+     "(int64_t)floor(t); /* nearest input sample */"),          # paper-mode centre at floor(t)
     ("lo = c - half_width;", "lo = c - half_width + 1;"),       # paper mode one tap short
     ("lo = (int64_t)f - half_width + 1;", "lo = (int64_t)f - half_width;"),  # 2H+1 taps
     ("hi = (int64_t)f + half_width;", "hi = (int64_t)f + half_width - 1;"),  # 2H-1 taps

@@ -125,6 +125,12 @@ COMPRESS = dict(name="pulse_compression_2^19", n=1 << 19, fs=2.048e9, f0=413e6, 
 # the Fig. 2 LFM band (413-431 MHz) over the whole record, sampled at 2.048 GHz, at v_r = 1 km/s.
 PAPER_SINC = dict(name="paper_sinc_2^19", n=1 << 19, fs=2.048e9, f0=413e6, bandwidth=18e6,
                   half_width=12, window="paper", v_r=1000.0)
+# The comparison of Doppler methods against velocity (Sec. III-A, Fig. 5): an LFM from 411 MHz
+# over 18 MHz lasting 500 us.  Read here as complex samples taken at RF (carrier 0) at the
+# original 2 GHz rate, so that resampling the record is the whole Doppler operator and frequency
+# conversion shifts at the band centre; velocities 0 .. 5 km/s as in Fig. 4.
+METHODS = dict(name="doppler_methods_fig5", fs=2e9, f0=411e6, bandwidth=18e6, pulse_s=500e-6,
+               f_ref=420e6, v_max=5000.0, points=21, n_window=25, lut_size=1251)
 
 
 def batch_pulse(p: int, n: int | None = None) -> np.ndarray:
