@@ -609,12 +609,11 @@ def device_noise(torch, n: int, count: int, seed: int, passband: float = 0.8):
     return out
 
 
-def run_serving(args, torch, rc):
+def serving_legs(torch, rc, nreq: int, saturation: bool = True):
     """Poisson arrivals at 2000 pulses/s, lengths floor(2^U), U ~ U[12, 22], each Doppler then
-    ionosphere, through the continuous-batching server; the same sequence through the plain
-    one-pulse-at-a-time path; and the server at saturation (all requests at once)."""
+    ionosphere: through the continuous-batching server at the offered rate, the same sequence
+    through the plain one-pulse-at-a-time path, and (saturation) every request at once."""
     c = wf.SERVING
-    nreq = args.requests
     rng = wf.rng_for(c["seed"], 0)
     arrivals = wf.poisson_arrivals(c["rate_hz"], nreq, rng)
     lens = wf.loguniform_lengths(nreq, rng, c["lo_exp"], c["hi_exp"])
@@ -629,7 +628,6 @@ def run_serving(args, torch, rc):
     ys = torch.empty((nbuf, nmax), dtype=torch.complex64, device="cuda")
     ctx = rc.Context(0)
     sinc = rc.Sinc(c["half_width"], "kaiser", c["beta"])
-    samples = int(lens.sum())
 
     def request(i):
         n = int(lens[i])
@@ -652,7 +650,6 @@ def run_serving(args, torch, rc):
                 pass
             submit_one(i)
 
-    # 1) the server at the offered rate
     slot_ticket = {}
 
     def submit_server(i):
@@ -662,18 +659,21 @@ def run_serving(args, torch, rc):
         x, y = request(i)
         slot_ticket[b] = srv.submit(x, y, alpha=alphas[i], tec=e[i], carrier=c["carrier"], fs=c["fs"])
 
+    # 1) the server at the offered rate
     paced(submit_server)
     srv.wait()
     st_rate = srv.stats()
     srv.reset_stats()
     slot_ticket.clear()
     # 2) the server at saturation: every request submitted at once
-    t0 = time.perf_counter()
-    for i in range(nreq):
-        submit_server(i)
-    srv.wait()
-    sat_s = time.perf_counter() - t0
-    st_sat = srv.stats()
+    sat_s, st_sat = None, None
+    if saturation:
+        t0 = time.perf_counter()
+        for i in range(nreq):
+            submit_server(i)
+        srv.wait()
+        sat_s = time.perf_counter() - t0
+        st_sat = srv.stats()
     srv.close()
     # 3) the plain path at the offered rate: correct_doppler then correct_ionosphere, one pulse at
     #    a time, each waited for
@@ -687,6 +687,29 @@ def run_serving(args, torch, rc):
         ctx.correct_ionosphere(tmp, c["fs"], c["carrier"], e[i], "correct", out=y)
         torch.cuda.synchronize()
         lat[i] = (time.perf_counter() - t0 - arrivals[i]) * 1e3
+    return dict(lens=lens, samples=int(lens.sum()), st_rate=st_rate, plain_lat=lat, sat_s=sat_s, st_sat=st_sat)
+
+
+def latency_summary(r):
+    """Served against plain end-to-end latency (submit to completion) at the offered rate."""
+    c = wf.SERVING
+    lat = r["plain_lat"]
+    return {"workload": f"{len(lat)} requests, Poisson at {c['rate_hz']:.0f}/s, lengths floor(2^U) "
+                        f"U~U[{c['lo_exp']:.0f},{c['hi_exp']:.0f}], Doppler then iono",
+            "served_ms_p50": round(r["st_rate"]["latency_ms_p50"], 4),
+            "served_ms_p99": round(r["st_rate"]["latency_ms_p99"], 4),
+            "plain_ms_p50": round(float(np.percentile(lat, 50)), 4),
+            "plain_ms_p99": round(float(np.percentile(lat, 99)), 4),
+            "mean_batch": round(r["st_rate"]["mean_batch"], 2)}
+
+
+def run_serving(args, torch, rc):
+    """The serving workload: the server at 2000 pulses/s and at saturation, beside the plain path."""
+    c = wf.SERVING
+    nreq = args.requests
+    r = serving_legs(torch, rc, nreq)
+    lens, samples, sat_s, st_rate, st_sat, lat = r["lens"], r["samples"], r["sat_s"], r["st_rate"], r["st_sat"], \
+        r["plain_lat"]
     out = {"metric": "served corrected samples/s at saturation; p50/p99 end-to-end latency at 2000 pulses/s",
            "value": round(samples / sat_s, 1), "unit": "samples/s", "n_gpus": 1, "steps": nreq, "warmup": nreq,
            "ms_per_step": round(sat_s * 1e3 / nreq, 4), "higher_is_better": True, "scaling": "weak",
@@ -720,6 +743,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="batch: skip the graph-replay timing")
+    ap.add_argument("--settle", type=float, default=1.0,
+                    help="batch: seconds of untimed steps before the warmup steps (clocks settle)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of the same buffers (reference for "
                          "HBM traffic counters)")
@@ -736,6 +762,9 @@ def main():
                          "ablation: the paper's App. C sinc kernels on that setup; methods: error against "
                          "velocity of every Doppler method (Fig. 5 setup)")
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
+    ap.add_argument("--serving-requests", type=int, default=400,
+                    help="batch: requests of the short serving leg whose served and plain p50/p99 latency "
+                         "the line reports (0: none)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -790,7 +819,17 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 3 x {xd.numel() * 8 / 2**20:.0f} MiB read + written")
 
-    log(f"[bench] warmup {args.warmup}")
+    # A fresh process runs its first few dozen steps ~10% slower while the GPU's clocks settle:
+    # untimed steps for `--settle` seconds come before the W warmup steps (reported below).
+    settle_steps, t_settle = 0, time.perf_counter()
+    while time.perf_counter() - t_settle < args.settle and settle_steps < 5000:
+        step()
+        settle_steps += 1
+        if settle_steps % 50 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    settle_s = time.perf_counter() - t_settle
+    log(f"[bench] settled {settle_steps} steps in {settle_s:.2f} s; warmup {args.warmup}")
     ms_per_step, kt, kernels = timed(torch, ctx, step, args.steps, args.warmup)
     value = samples / (ms_per_step * 1e-3)
     log(f"[bench] {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GS/s; kernels {kernels}")
@@ -825,6 +864,41 @@ def main():
         step()  # restore the batch result in yd
         torch.cuda.synchronize()
 
+    # the same batch captured once in a HIP graph (rc_batch_plan) and replayed
+    graph = None
+    if not args.no_graph:
+        plan = ctx.batch_plan(xd, yd, table, sinc)
+        for _ in range(5):
+            plan.launch()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record()
+        for _ in range(args.steps):
+            plan.launch()
+        g1.record()
+        torch.cuda.synchronize()
+        gms = g0.elapsed_time(g1) / args.steps
+        # host time to enqueue one step: the plain call (validation, grouping, descriptor upload)
+        # against one graph launch
+        def host_us(f, reps=20):
+            torch.cuda.synchronize()
+            h0 = time.perf_counter()
+            for _ in range(reps):
+                f()
+            h1 = time.perf_counter()
+            torch.cuda.synchronize()
+            return (h1 - h0) / reps * 1e6
+        call_us, launch_us = host_us(step), host_us(plan.launch)
+        plan.close()
+        graph = {"ms_per_step": round(gms, 4), "samples_per_s": round(samples / (gms * 1e-3), 1),
+                 "host_us_per_call": round(call_us, 1), "host_us_per_graph_launch": round(launch_us, 1)}
+        log(f"[bench] graph replay {gms:.3f} ms/step")
+
+    latency = None
+    if args.serving_requests > 0:
+        log("[bench] serving leg")
+        latency = latency_summary(serving_legs(torch, rc, args.serving_requests, saturation=False))
+
     cpu, rel_err = None, None
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline")
@@ -853,8 +927,11 @@ def main():
         "rel_err_max_sampled": rel_err,
         "hbm_frac_of_step": round(BYTES_PER_SAMPLE_PASS * value / (HBM_PEAK_GBS * 1e9), 4),
         "kernels": kernels,
+        "settle": {"seconds": round(settle_s, 3), "steps": settle_steps},
         "batch_latency_ms": round(ms_per_step, 4),
         "plain_path": plain,
+        "graph_replay": graph,
+        "latency": latency,
     }
     print(json.dumps(out), flush=True)
 

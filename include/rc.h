@@ -186,6 +186,32 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
                               rc_c64 *y_packed, int64_t y_len, const rc_pulse *pulses,
                               int32_t count, const rc_sinc *k, void *stream);
 
+/* Batch plans: one correct_pulse_batch call captured once in a HIP graph and replayed.  For a
+ * caller that runs the same batch shape again and again (a pulse train, a fixed bank of channels):
+ * the host work of a call (validation, grouping, descriptor upload, the matrix-core tile list) is
+ * done at creation, and a launch is one hipGraphLaunch of the recorded kernels.
+ *
+ * rc_batch_plan_create takes correct_pulse_batch's arguments (count >= 1) and fixes them; the plan
+ * owns device memory for the descriptors and workspace (not counted against rc_set_mem_budget).
+ * rc_batch_plan_launch(plan, stream) then enqueues exactly the work of that correct_pulse_batch
+ * call on `stream`, with bit-identical results.  rc_batch_plan_update(plan, pulses, count, stream)
+ * replaces the pulses (same buffers) for later launches; it enqueues the new descriptors and tile
+ * list on `stream`, so a launch on that stream after it sees them and one before it does not.
+ * The new pulses must need the same launches: the same count, lengths and flags, the same
+ * resampling engine per pulse (alpha within the same eligibility range), and pulses with neither
+ * step at the same offsets; otherwise RC_ERR_UNSUPPORTED and the plan is unchanged.
+ * rc_batch_plan_destroy synchronises the device and frees the plan; destroy every plan before its
+ * context.  Launches of one plan share its buffers: launches on different streams that overlap
+ * in time race on the outputs as two correct_pulse_batch calls would. */
+typedef struct rc_batch_plan_s *rc_batch_plan;
+rc_status rc_batch_plan_create(rc_context ctx, const rc_c64 *x_packed, int64_t x_len,
+                               rc_c64 *y_packed, int64_t y_len, const rc_pulse *pulses,
+                               int32_t count, const rc_sinc *k, rc_batch_plan *out);
+rc_status rc_batch_plan_launch(rc_batch_plan plan, void *stream);
+rc_status rc_batch_plan_update(rc_batch_plan plan, const rc_pulse *pulses, int32_t count,
+                               void *stream);
+rc_status rc_batch_plan_destroy(rc_batch_plan plan);
+
 /* A bank of Doppler hypotheses on one pulse (many alpha on the same input):
  *   y[h * n_out + m] = sum_n x[n] h(alphas[h] m - n),  h < n_hyp, m < n_out,
  * each row the correct_doppler result for its alpha (the same Eq (17) sum; the exact-integer
@@ -233,9 +259,13 @@ rc_status rc_set_bank_engine(rc_context ctx, int32_t engine);
  * that arrives at an idle server starts at once, and under load the queue fills while the
  * device works, so one launch sequence serves many requests (ionospheric lengths that are not
  * powers of two share theirs by convolution length).  A completer thread times each batch's
- * completion.  Admission is by bytes: a request holds
- * 8 (n_in + n_out) bytes, plus 32 n_out for an ionospheric length that is not a power of two,
- * until it completes; rc_server_submit returns RC_ERR_BUSY when the budget is full and
+ * completion.  Admission is by bytes: a request holds, until it completes,
+ * 8 (n_in + n_out) + 1024 bytes, plus the Bluestein workspace of an ionospheric length that is
+ * not a power of two (2 M complex values, M the power of two >= 2 n_out - 1), plus, for a
+ * Doppler pulse on the matrix cores, its tile list (17 bytes per 2048 outputs and 516 bytes per
+ * 256 tiles).  Those bound the context workspace of every batch in flight: with the context's
+ * rc_set_mem_budget at the server's budget the workspace never exceeds it.
+ * rc_server_submit returns RC_ERR_BUSY when the budget is full and
  * RC_ERR_UNSUPPORTED for a request that could never fit.  Every pulse uses the kernel *k
  * given at creation.  Output of a request does not depend on what it was batched with. */
 typedef struct rc_server_s *rc_server;
@@ -246,6 +276,9 @@ typedef struct {
     double fs_hz, alpha, tec_el_per_m2, carrier_hz;
     uint32_t flags;         /* RC_DO_DOPPLER | RC_DO_IONO */
     int32_t direction;      /* RC_CORRECT | RC_DISTORT */
+    void *stream;           /* hipStream_t: the work enqueued on it before rc_server_submit (such
+                               as what fills x) completes before the request reads x; NULL is the
+                               null stream */
 } rc_request;
 typedef struct {
     int64_t submitted, completed, rejected;   /* since creation or the last reset */
@@ -257,6 +290,9 @@ typedef struct {
 rc_status rc_server_create(rc_context ctx, const rc_sinc *k, int64_t mem_budget_bytes,
                            int32_t max_batch, rc_server *out);
 rc_status rc_server_submit(rc_server srv, const rc_request *req, int64_t *ticket);
+/* The bytes rc_server_submit would charge this request against the budget (see above), or -1
+ * for a NULL argument.  The request is not validated. */
+int64_t rc_server_request_bytes(rc_server srv, const rc_request *req);
 /* done = 1 once the request is complete; a completed ticket is then released (poll again:
  * RC_ERR_INVALID_ARG).  Returns the request's status when it reports done. */
 rc_status rc_server_poll(rc_server srv, int64_t ticket, int32_t *done);
@@ -266,6 +302,27 @@ rc_status rc_server_stats(rc_server srv, rc_server_stats_t *out);
 rc_status rc_server_reset_stats(rc_server srv);
 /* Launch what is queued, wait for everything, free the server. */
 rc_status rc_server_destroy(rc_server srv);
+
+/* Tuning.  These set launch shapes that change speed: the grid and chunk settings give
+ * bit-identical results; another FFT split changes the float32 rounding order only (results
+ * within the same parity bar against the float64 definition).
+ *   rc_set_fft_levels     the split of the n-point transform (n a power of two, 4096 < n <= 2^24)
+ *                         into `count` (1..3) strided levels, each a power of two in [2, 256], run
+ *                         before the 4096-point contiguous level; their product times 4096 is n.
+ *                         count 0 restores the default split (levels of 256, then the rest);
+ *   rc_set_sinc_grid      workgroups per CU of the matrix-core resampler's persistent grid at
+ *                         half_width 64 or 128 (0: as many as fit, the default);
+ *   rc_set_bluestein_chunk  workspace cap of one Bluestein launch sequence in a batch (0: 256 MiB).
+ * rc_load_tuning applies a JSON file written by the autotuner (paper_2508_04951_amd/tune.py):
+ *   {"fft_levels": {"<n>": [L0, ...], ...}, "sinc_grid": {"64": w, "128": w},
+ *    "bluestein_chunk_bytes": b, ...}   (other keys are ignored).
+ * rc_create loads the file named by the environment variable RC_TUNE_FILE when it is set and
+ * fails with RC_ERR_INVALID_ARG if that file cannot be read or applied.  All three settings
+ * are per context and apply to later calls. */
+rc_status rc_set_fft_levels(rc_context ctx, int64_t n, const int32_t *levels, int32_t count);
+rc_status rc_set_sinc_grid(rc_context ctx, int32_t half_width, int32_t wg_per_cu);
+rc_status rc_set_bluestein_chunk(rc_context ctx, int64_t bytes);
+rc_status rc_load_tuning(rc_context ctx, const char *path);
 
 /* Resampling engine (rc_set_sinc_engine).  Every engine computes the same sum of Eq (17):
  *   RC_SINC_AUTO   matrix cores for the Kaiser taper at H = 64 or 128 and |alpha - 1| <= 6e-5,

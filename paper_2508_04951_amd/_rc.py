@@ -26,16 +26,19 @@ SYMBOLS = (
     "rc_k2_per_tec", "rc_sync", "correct_doppler", "correct_ionosphere", "correct_ionosphere_noalloc",
     "correct_pulse_batch",
     "correct_doppler_bank", "rc_server_create", "rc_server_submit", "rc_server_poll", "rc_server_wait",
-    "rc_server_stats", "rc_server_reset_stats", "rc_server_destroy",
+    "rc_server_stats", "rc_server_reset_stats", "rc_server_destroy", "rc_server_request_bytes",
     "rc_profile_enable", "rc_profile_read", "rc_set_sinc_engine", "rc_set_bank_engine", "rc_set_mem_budget",
     "replica_spectrum", "compress_pulse",
     "correct_doppler_paper", "correct_doppler_linear", "correct_doppler_tone", "rc_pq_length",
-    "correct_doppler_fft_pq",
+    "correct_doppler_fft_pq", "rc_batch_plan_create", "rc_batch_plan_launch", "rc_batch_plan_update",
+    "rc_batch_plan_destroy", "rc_set_fft_levels", "rc_set_sinc_grid", "rc_set_bluestein_chunk", "rc_load_tuning",
 )
 KERNELS = ("k_sinc_mfma", "k_sinc_fast", "k_sinc_direct", "k_fft_strided_fwd", "k_fft_rows_iono",
            "k_fft_strided_inv", "k_mf_tile_list", "k_bluestein", "k_farrow_z", "k_farrow_bank",
            "k_paper_sinc", "k_linear", "k_tone", "k_pq")
 PAPER_VARIANTS = {"direct": 0, "tiled": 1, "lut": 2}
+# the autotuner's table for gfx950 (paper_2508_04951_amd/tune.py writes it)
+TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 BANK_PRECISIONS = {"fp16x3": 0, "bf16x3": 1, "fp32": 2}
 BANK_ENGINES = {"auto": 0, "farrow": 1, "per_hypothesis": 2}
 SINC_ENGINES = {"auto": 0, "valu": 1, "direct": 2}
@@ -59,6 +62,7 @@ class RcRequest(ctypes.Structure):
         ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n_in", ctypes.c_int64), ("n_out", ctypes.c_int64),
         ("fs_hz", ctypes.c_double), ("alpha", ctypes.c_double), ("tec_el_per_m2", ctypes.c_double),
         ("carrier_hz", ctypes.c_double), ("flags", ctypes.c_uint32), ("direction", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -137,6 +141,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.correct_pulse_batch.argtypes = [p, p, c_i64, p, c_i64, ctypes.POINTER(RcPulse), c_i32,
                                             ctypes.POINTER(RcSinc), p]
         lib.correct_pulse_batch.restype = c_i32
+        lib.rc_batch_plan_create.argtypes = [p, p, c_i64, p, c_i64, ctypes.POINTER(RcPulse), c_i32,
+                                             ctypes.POINTER(RcSinc), ctypes.POINTER(p)]
+        lib.rc_batch_plan_create.restype = c_i32
+        lib.rc_batch_plan_launch.argtypes = [p, p]
+        lib.rc_batch_plan_launch.restype = c_i32
+        lib.rc_batch_plan_update.argtypes = [p, ctypes.POINTER(RcPulse), c_i32, p]
+        lib.rc_batch_plan_update.restype = c_i32
+        lib.rc_batch_plan_destroy.argtypes = [p]
+        lib.rc_batch_plan_destroy.restype = c_i32
         lib.rc_profile_enable.argtypes = [p, ctypes.c_int]
         lib.rc_profile_enable.restype = c_i32
         lib.rc_profile_read.argtypes = [p, ctypes.c_char_p, ctypes.POINTER(c_d), ctypes.POINTER(c_i64)]
@@ -145,10 +158,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.rc_set_sinc_engine.restype = c_i32
         lib.rc_set_bank_engine.argtypes = [p, c_i32]
         lib.rc_set_bank_engine.restype = c_i32
+        lib.rc_set_fft_levels.argtypes = [p, c_i64, ctypes.POINTER(c_i32), c_i32]
+        lib.rc_set_fft_levels.restype = c_i32
+        lib.rc_set_sinc_grid.argtypes = [p, c_i32, c_i32]
+        lib.rc_set_sinc_grid.restype = c_i32
+        lib.rc_set_bluestein_chunk.argtypes = [p, c_i64]
+        lib.rc_set_bluestein_chunk.restype = c_i32
+        lib.rc_load_tuning.argtypes = [p, ctypes.c_char_p]
+        lib.rc_load_tuning.restype = c_i32
         lib.rc_set_mem_budget.argtypes = [p, ctypes.c_int64]
         lib.rc_set_mem_budget.restype = c_i32
         lib.rc_server_create.argtypes = [p, ctypes.POINTER(RcSinc), c_i64, c_i32, ctypes.POINTER(p)]
         lib.rc_server_submit.argtypes = [p, ctypes.POINTER(RcRequest), ctypes.POINTER(c_i64)]
+        lib.rc_server_request_bytes.argtypes = [p, ctypes.POINTER(RcRequest)]
+        lib.rc_server_request_bytes.restype = c_i64
         lib.rc_server_poll.argtypes = [p, c_i64, ctypes.POINTER(c_i32)]
         lib.rc_server_wait.argtypes = [p, c_i64]
         lib.rc_server_stats.argtypes = [p, ctypes.POINTER(RcServerStats)]
@@ -220,7 +243,10 @@ def _check_samples(t, name: str):
 class Context:
     """An rc_context on one HIP device."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tuning: str | None = "default"):
+        """tuning: "default" applies the autotuner's table shipped with the package (tuning.json
+        beside this file) unless RC_TUNE_FILE names one, which rc_create then loads itself; a
+        path applies that file; None applies nothing beyond RC_TUNE_FILE."""
         self._lib = load_library()
         self.device = int(device)
         h = ctypes.c_void_p()
@@ -228,6 +254,10 @@ class Context:
         if st != RC_OK:
             raise RcError(st, f"rc_create({device}) failed: {self._lib.rc_status_string(st).decode()}")
         self._h = h
+        if tuning == "default":
+            tuning = None if os.environ.get("RC_TUNE_FILE") else (TUNING_PATH if os.path.exists(TUNING_PATH) else None)
+        if tuning:
+            self.load_tuning(tuning)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -266,6 +296,30 @@ class Context:
         st = self._lib.rc_set_mem_budget(self._h, int(nbytes))
         if st != RC_OK:
             self._raise(st, "rc_set_mem_budget")
+
+    def set_fft_levels(self, n: int, levels=()):
+        """Strided levels of the n-point transform before its 4096-point level (() = default)."""
+        arr = (ctypes.c_int32 * max(1, len(levels)))(*[int(v) for v in levels])
+        st = self._lib.rc_set_fft_levels(self._h, int(n), arr, len(levels))
+        if st != RC_OK:
+            self._raise(st, "rc_set_fft_levels")
+
+    def set_sinc_grid(self, half_width: int, wg_per_cu: int = 0):
+        """Workgroups per CU of the matrix-core resampler at half_width 64 or 128 (0 = all that fit)."""
+        st = self._lib.rc_set_sinc_grid(self._h, int(half_width), int(wg_per_cu))
+        if st != RC_OK:
+            self._raise(st, "rc_set_sinc_grid")
+
+    def set_bluestein_chunk(self, nbytes: int = 0):
+        st = self._lib.rc_set_bluestein_chunk(self._h, int(nbytes))
+        if st != RC_OK:
+            self._raise(st, "rc_set_bluestein_chunk")
+
+    def load_tuning(self, path: str):
+        """Apply an autotuner table (JSON; see rc_load_tuning)."""
+        st = self._lib.rc_load_tuning(self._h, os.fsencode(path))
+        if st != RC_OK:
+            self._raise(st, "rc_load_tuning")
 
     def set_sinc_engine(self, engine: str = "auto"):
         """Resampling engine for later calls: "auto" (matrix cores where eligible), "valu" or
@@ -477,6 +531,11 @@ class Context:
             self._raise(st, "correct_pulse_batch")
         return y_packed
 
+    def batch_plan(self, x_packed, y_packed, pulses, sinc: Sinc | None = None) -> "BatchPlan":
+        """correct_pulse_batch(x_packed, y_packed, pulses, sinc) captured once in a HIP graph:
+        BatchPlan.launch() replays it (see rc_batch_plan_create)."""
+        return BatchPlan(self, x_packed, y_packed, pulses, sinc)
+
     def correct_doppler_bank(self, x, alphas=None, sinc: Sinc | None = None, n_out: int | None = None,
                              precision: str = "fp16x3", fs: float = 1.0, out=None, stream=None, *, v_r=None):
         """Row h of the (len(alphas), n_out) result is correct_doppler(x, alphas[h]).  Give the
@@ -505,6 +564,51 @@ class Context:
         return out
 
 
+class BatchPlan:
+    """A batch captured in a HIP graph (rc_batch_plan_*).  It keeps its buffers alive."""
+
+    def __init__(self, ctx: "Context", x_packed, y_packed, pulses, sinc: Sinc | None = None):
+        _check_samples(x_packed, "x_packed")
+        _check_samples(y_packed, "y_packed")
+        self._ctx, self._lib = ctx, ctx._lib
+        self._x, self._y = x_packed, y_packed
+        arr = pulse_array(pulses)
+        ptr = arr if isinstance(arr, ctypes.Array) else arr.ctypes.data_as(ctypes.POINTER(RcPulse))
+        self._k = (sinc or Sinc()).c()
+        h = ctypes.c_void_p()
+        st = self._lib.rc_batch_plan_create(ctx._h, x_packed.data_ptr(), x_packed.numel(), y_packed.data_ptr(),
+                                            y_packed.numel(), ptr, len(arr), ctypes.byref(self._k), ctypes.byref(h))
+        if st != RC_OK:
+            ctx._raise(st, "rc_batch_plan_create")
+        self._h = h
+        self.count = len(arr)
+
+    def launch(self, stream=None):
+        st = self._lib.rc_batch_plan_launch(self._h, self._ctx._stream(stream))
+        if st != RC_OK:
+            self._ctx._raise(st, "rc_batch_plan_launch")
+        return self._y
+
+    def update(self, pulses, stream=None):
+        """New pulses (same lengths, flags and engines) for the following launches."""
+        arr = pulse_array(pulses)
+        ptr = arr if isinstance(arr, ctypes.Array) else arr.ctypes.data_as(ctypes.POINTER(RcPulse))
+        st = self._lib.rc_batch_plan_update(self._h, ptr, len(arr), self._ctx._stream(stream))
+        if st != RC_OK:
+            self._ctx._raise(st, "rc_batch_plan_update")
+
+    def close(self):
+        if self._h:
+            self._lib.rc_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Server:
     """A continuous-batching server (rc_server) on a Context: submit single-pulse requests on
     device buffers, wait for tickets, read latency statistics."""
@@ -523,8 +627,12 @@ class Server:
         self._held = {}  # ticket -> (x, y): the buffers stay referenced until the ticket is released
 
     def submit(self, x, y, alpha: float = 1.0, tec: float = 0.0, carrier: float = 0.0, fs: float = 1.0,
-               flags: int | None = None, direction: str = "correct", n_out: int | None = None) -> int:
-        """Queue one pulse: x (device complex64) -> y (device complex64, n_out samples)."""
+               flags: int | None = None, direction: str = "correct", n_out: int | None = None,
+               stream=None, charge_only: bool = False) -> int:
+        """Queue one pulse: x (device complex64) -> y (device complex64, n_out samples).  The
+        request reads x after the work already enqueued on `stream` (default: torch's current
+        stream), so x may still be in flight there.  charge_only: return the bytes the request
+        would hold against the budget instead of submitting it."""
         _check_samples(x, "x")
         _check_samples(y, "y")
         n_out = y.numel() if n_out is None else int(n_out)
@@ -532,8 +640,11 @@ class Server:
             raise ValueError("y is shorter than n_out")
         fl = (DO_DOPPLER | DO_IONO) if flags is None else int(flags)
         req = RcRequest(x.data_ptr(), y.data_ptr(), x.numel(), n_out, float(fs), float(alpha), float(tec),
-                        float(carrier), fl, DIRECTIONS[direction] if isinstance(direction, str) else int(direction))
+                        float(carrier), fl, DIRECTIONS[direction] if isinstance(direction, str) else int(direction),
+                        self._ctx._stream(stream))
         t = ctypes.c_int64()
+        if charge_only:
+            return int(self._lib.rc_server_request_bytes(self._h, ctypes.byref(req)))
         st = self._lib.rc_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
         if st != RC_OK:
             self._ctx._raise(st, "rc_server_submit")

@@ -413,17 +413,18 @@ struct RowArgs {
     float scale;              // 1/n when this is the only pass, else 1
 };
 
-// (cos pi w / 2, sin pi w / 2) for |w| <= 1/2 quarter turn: an even and an odd polynomial in w,
-// fitted to minimax on that interval (fit error below 3e-9; float32 evaluation stays within
-// 1.5 ulp of the true values).
+// (cos pi w / 2, sin pi w / 2) for |w| <= 1/2 quarter turn: with u = w^2, w S(u) and 1 + u C(u),
+// S and C cubics fitted (weighted Remez exchange on u in [0, 1/4], the coefficients rounded to
+// float32 one at a time with the rest refitted; fit_cis_quarter.py) to an absolute error below
+// 5.1e-9 (sin) and 4.1e-10 (cos); float32 evaluation stays within 7e-8 and 2 ulp of the true values.
 __device__ __forceinline__ float2 cis_quarter(float w)
 {
     const float u = w * w;
-    float ps = fmaf(u, -0x1.2d9bb8p-8f, 0x1.465ec6p-4f);
-    ps = fmaf(u, ps, -0x1.4abbbap-1f);
-    ps = fmaf(u, ps, 0x1.921fb6p+0f);
-    float pc = fmaf(u, 0x1.d9f7bcp-11f, -0x1.55c664p-6f);
-    pc = fmaf(u, pc, 0x1.03c1dep-2f);
+    float ps = fmaf(u, -0x1.2a7638p-8f, 0x1.46496cp-4f);
+    ps = fmaf(u, ps, -0x1.4abb68p-1f);
+    ps = fmaf(u, ps, 0x1.921fb4p+0f);
+    float pc = fmaf(u, 0x1.d47d46p-11f, -0x1.55b146p-6f);
+    pc = fmaf(u, pc, 0x1.03c1aep-2f);
     pc = fmaf(u, pc, -0x1.3bd3ccp+0f);
     return make_float2(fmaf(u, pc, 1.0f), w * ps);
 }
@@ -792,6 +793,31 @@ hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs)
         plan.len[d++] = kFftTile;
         plan.levels = d;
     }
+    for (int i = 0; i < plan.levels; ++i)
+        plan.log2len[i] = ilog2(plan.len[i]);
+    return hipSuccess;
+}
+
+hipError_t build_fft_plan_levels(int64_t n, const std::vector<int> &strided, FftPlan &plan)
+{
+    plan = FftPlan{};
+    plan.n = n;
+    if (ilog2(n) > 24 || (int64_t(1) << ilog2(n)) != n || n <= kFftTile || strided.empty() ||
+        (int)strided.size() + 1 > kFftMaxLevels)
+        return hipErrorInvalidValue;
+    int64_t prod = kFftTile;
+    for (int L : strided) {
+        if (L < 2 || L > 256 || (L & (L - 1)) != 0)
+            return hipErrorInvalidValue;
+        prod *= L;
+    }
+    if (prod != n)
+        return hipErrorInvalidValue;
+    int d = 0;
+    for (int L : strided)
+        plan.len[d++] = L;
+    plan.len[d++] = kFftTile;
+    plan.levels = d;
     for (int i = 0; i < plan.levels; ++i)
         plan.log2len[i] = ilog2(plan.len[i]);
     return hipSuccess;

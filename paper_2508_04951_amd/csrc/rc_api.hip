@@ -5,6 +5,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <new>
@@ -123,18 +124,36 @@ rc_status reserve_descriptors(rc_context ctx, size_t bytes, size_t extra, void *
     if (dev_bytes > slot.dev_cap) {
         size_t cap = grow(dev_bytes);
         if (ctx->mem_budget > 0) {
-            // the other slots keep their workspace; this one is replaced
-            size_t others = 0;
-            for (int i = 0; i < rc_context_s::kDescSlots; ++i)
-                if (i != ctx->desc_next)
-                    others += ctx->desc[i].dev_cap;
+            // Under a budget every slot holds exactly what its last call needed, and the slots
+            // whose work has completed give their workspace back when the total would exceed the
+            // budget; the slots still in use keep theirs.  This one is replaced.
+            cap = dev_bytes;
             const size_t budget = (size_t)ctx->mem_budget;
-            if (others + cap > budget)
-                cap = dev_bytes;  // no rounding up when the budget is tight
-            if (others + cap > budget)
+            auto others = [&] {
+                size_t o = 0;
+                for (int i = 0; i < rc_context_s::kDescSlots; ++i)
+                    if (i != ctx->desc_next)
+                        o += ctx->desc[i].dev_cap;
+                return o;
+            };
+            if (others() + cap > budget) {
+                for (int i = 0; i < rc_context_s::kDescSlots; ++i) {
+                    auto &o = ctx->desc[i];
+                    if (i == ctx->desc_next || !o.dev)
+                        continue;
+                    if (o.pending && hipEventQuery(o.done) != hipSuccess)
+                        continue;  // still in use (or failed: kept until its event is waited for)
+                    (void)hipFree(o.dev);
+                    o.dev = nullptr;
+                    o.dev_cap = 0;
+                    o.pending = false;
+                }
+            }
+            if (others() + cap > budget)
                 return fail(ctx, RC_ERR_OUT_OF_MEMORY,
-                            "workspace of " + std::to_string(others + cap) + " bytes would exceed the memory budget of " +
-                                std::to_string(budget) + " (rc_set_mem_budget)");
+                            "workspace of " + std::to_string(others() + cap) +
+                                " bytes would exceed the memory budget of " + std::to_string(budget) +
+                                " (rc_set_mem_budget)");
         }
         if (slot.dev)
             (void)hipFree(slot.dev);
@@ -206,7 +225,9 @@ rc_status get_plan(rc_context ctx, int64_t n, const FftPlan **out)
     auto it = ctx->plans.find(n);
     if (it == ctx->plans.end()) {
         FftPlan plan;
-        hipError_t e = rc::build_fft_plan(n, plan, ctx->allocs);
+        const auto tuned = ctx->fft_levels.find(n);
+        hipError_t e = tuned != ctx->fft_levels.end() ? rc::build_fft_plan_levels(n, tuned->second, plan)
+                                                       : rc::build_fft_plan(n, plan, ctx->allocs);
         if (e == hipErrorInvalidValue)
             return fail(ctx, RC_ERR_UNSUPPORTED, "transform length " + std::to_string(n) + " not supported");
         if (e != hipSuccess)
@@ -275,6 +296,186 @@ PhaseNum phase_numerator(double tec, int32_t direction, double fs, double carrie
 }
 
 rc::Profiler *prof_of(rc_context ctx) { return ctx->prof.on ? &ctx->prof : nullptr; }
+
+// A JSON value, for the tuning file: objects keep their keys in order.
+struct Json {
+    enum Kind { Null, Bool, Number, String, Array, Object } kind = Null;
+    double num = 0.0;
+    std::string str;
+    std::vector<Json> arr;
+    std::vector<std::pair<std::string, Json>> obj;
+};
+
+// Recursive-descent JSON reader (RFC 8259 grammar; \u escapes kept only for ASCII).
+struct JsonReader {
+    const std::string &t;
+    size_t i = 0;
+    std::string err;
+    explicit JsonReader(const std::string &text) : t(text) {}
+    void ws()
+    {
+        while (i < t.size() && (t[i] == ' ' || t[i] == '\t' || t[i] == '\n' || t[i] == '\r'))
+            ++i;
+    }
+    bool fail_at(const char *what)
+    {
+        if (err.empty())
+            err = std::string(what) + " at byte " + std::to_string(i);
+        return false;
+    }
+    bool lit(const char *w)
+    {
+        const size_t n = std::strlen(w);
+        if (t.compare(i, n, w) != 0)
+            return fail_at("unexpected token");
+        i += n;
+        return true;
+    }
+    bool str(std::string &out)
+    {
+        if (i >= t.size() || t[i] != '"')
+            return fail_at("expected a string");
+        ++i;
+        out.clear();
+        while (i < t.size() && t[i] != '"') {
+            char c = t[i++];
+            if (c == '\\') {
+                if (i >= t.size())
+                    return fail_at("bad escape");
+                const char e = t[i++];
+                switch (e) {
+                case 'n': c = '\n'; break;
+                case 't': c = '\t'; break;
+                case 'r': c = '\r'; break;
+                case 'b': c = '\b'; break;
+                case 'f': c = '\f'; break;
+                case 'u': {
+                    if (i + 4 > t.size())
+                        return fail_at("bad escape");
+                    c = (char)std::strtol(t.substr(i, 4).c_str(), nullptr, 16);
+                    i += 4;
+                    break;
+                }
+                default: c = e;
+                }
+            }
+            out.push_back(c);
+        }
+        if (i >= t.size())
+            return fail_at("unterminated string");
+        ++i;
+        return true;
+    }
+    bool value(Json &v, int depth)
+    {
+        if (depth > 64)
+            return fail_at("nesting too deep");
+        ws();
+        if (i >= t.size())
+            return fail_at("unexpected end");
+        const char c = t[i];
+        if (c == '{') {
+            v.kind = Json::Object;
+            ++i;
+            ws();
+            if (i < t.size() && t[i] == '}') {
+                ++i;
+                return true;
+            }
+            for (;;) {
+                ws();
+                std::string key;
+                if (!str(key))
+                    return false;
+                ws();
+                if (i >= t.size() || t[i] != ':')
+                    return fail_at("expected ':'");
+                ++i;
+                Json item;
+                if (!value(item, depth + 1))
+                    return false;
+                v.obj.emplace_back(std::move(key), std::move(item));
+                ws();
+                if (i < t.size() && t[i] == ',') {
+                    ++i;
+                    continue;
+                }
+                if (i < t.size() && t[i] == '}') {
+                    ++i;
+                    return true;
+                }
+                return fail_at("expected ',' or '}'");
+            }
+        }
+        if (c == '[') {
+            v.kind = Json::Array;
+            ++i;
+            ws();
+            if (i < t.size() && t[i] == ']') {
+                ++i;
+                return true;
+            }
+            for (;;) {
+                Json item;
+                if (!value(item, depth + 1))
+                    return false;
+                v.arr.push_back(std::move(item));
+                ws();
+                if (i < t.size() && t[i] == ',') {
+                    ++i;
+                    continue;
+                }
+                if (i < t.size() && t[i] == ']') {
+                    ++i;
+                    return true;
+                }
+                return fail_at("expected ',' or ']'");
+            }
+        }
+        if (c == '"') {
+            v.kind = Json::String;
+            return str(v.str);
+        }
+        if (c == 't') {
+            v.kind = Json::Bool;
+            v.num = 1.0;
+            return lit("true");
+        }
+        if (c == 'f') {
+            v.kind = Json::Bool;
+            return lit("false");
+        }
+        if (c == 'n') {
+            v.kind = Json::Null;
+            return lit("null");
+        }
+        char *end = nullptr;
+        v.num = std::strtod(t.c_str() + i, &end);
+        if (end == t.c_str() + i)
+            return fail_at("expected a value");
+        v.kind = Json::Number;
+        i = (size_t)(end - t.c_str());
+        return true;
+    }
+};
+
+bool parse_json(const std::string &text, Json &out, std::string &err)
+{
+    JsonReader r(text);
+    if (!r.value(out, 0)) {
+        err = r.err;
+        return false;
+    }
+    r.ws();
+    if (r.i != text.size()) {
+        err = "trailing characters at byte " + std::to_string(r.i);
+        return false;
+    }
+    return true;
+}
+
+// Workgroups per CU of the matrix-core resampler's persistent grid (0: occupancy maximum).
+int sinc_grid(rc_context ctx, int half_width) { return ctx->sinc_wg_per_cu[half_width == 128 ? 1 : 0]; }
 
 // Workspace of correct_ionosphere_noalloc: Bluestein's convolution buffer and chirp spectrum,
 // 2 M complex values for a length n that is not a power of two (M the power of two >= 2n - 1),
@@ -410,6 +611,15 @@ rc_status rc_create(int hip_device, rc_context *out)
         e = hipEventCreateWithFlags(&ctx->tiles_done, hipEventDisableTiming);
     if (e == hipSuccess)
         e = scratch_on_device(hip_device, &ctx->static_scratch);
+    if (e == hipSuccess) {
+        // tuning chosen by the autotuner, when the environment names a file
+        const char *tune = std::getenv("RC_TUNE_FILE");
+        if (tune && *tune && rc_load_tuning(ctx, tune) != RC_OK) {
+            std::fprintf(stderr, "rc_create: %s\n", ctx->last_error.c_str());
+            (void)rc_destroy(ctx);
+            return RC_ERR_INVALID_ARG;
+        }
+    }
     if (e != hipSuccess) {
         if (ctx->tiles_done)
             (void)hipEventDestroy(ctx->tiles_done);
@@ -517,9 +727,10 @@ rc_status correct_doppler(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 
         if (ts != RC_OK)
             return ts;
         const int64_t ntiles = (n_out + rc::kSincMfmaTile - 1) / rc::kSincMfmaTile;
-        if (!rc::sinc_mfma_uses_list(k->half_width, ntiles)) {
+        const int wpc = sinc_grid(ctx, k->half_width);
+        if (!rc::sinc_mfma_uses_list(k->half_width, ntiles, wpc)) {
             e = rc::launch_sinc_mfma(nullptr, &job, 1, n_out, ntiles, nullptr, k->half_width, table, s,
-                                     prof_of(ctx));
+                                     prof_of(ctx), nullptr, rc::TileListMode::BuildAndRun, wpc);
             break;
         }
         // a long pulse: the job descriptor and the tile list go to a staging slot
@@ -530,7 +741,7 @@ rc_status correct_doppler(rc_context ctx, const rc_c64 *x, int64_t n_in, rc_c64 
         char *devc = static_cast<char *>(const_cast<void *>(dev));
         const rc::TileStream tls = tile_stream_of(ctx);
         e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc), nullptr, 1, n_out, ntiles, devc + 256,
-                                 k->half_width, table, s, prof_of(ctx), &tls);
+                                 k->half_width, table, s, prof_of(ctx), &tls, rc::TileListMode::BuildAndRun, wpc);
         ts = mark_descriptors_used(ctx, s);
         if (e == hipSuccess && ts != RC_OK)
             return ts;
@@ -610,11 +821,14 @@ rc_status correct_ionosphere_noalloc(rc_context ctx, const rc_c64 *x, rc_c64 *y,
     const PhaseNum phase = phase_numerator(tec_el_per_m2, direction, fs_hz, carrier_hz, n);
     const float2 *xf = reinterpret_cast<const float2 *>(x);
     float2 *yf = reinterpret_cast<float2 *>(y);
-    // the plan is rebuilt here rather than taken from (and inserted into) the context's cache;
-    // building one only fills the struct
+    // the plan is rebuilt here rather than taken from (and inserted into) the context's cache,
+    // with the context's tuned split if it has one; building one only fills the struct
     FftPlan plan;
     std::vector<void *> no_allocs;
-    hipError_t e = rc::build_fft_plan(iono_plan_length(n), plan, no_allocs);
+    const int64_t pn = iono_plan_length(n);
+    const auto tuned = ctx->fft_levels.find(pn);
+    hipError_t e = tuned != ctx->fft_levels.end() ? rc::build_fft_plan_levels(pn, tuned->second, plan)
+                                                   : rc::build_fft_plan(pn, plan, no_allocs);
     if (e != hipSuccess)
         return fail(ctx, RC_ERR_UNSUPPORTED, "transform length not supported");
     if (pow2) {
@@ -932,6 +1146,8 @@ rc_status validate_pulse(rc_context ctx, const PulseWork &p, const std::string &
 }
 
 rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, const rc_sinc *k, hipStream_t s);
+rc_status batch_work(rc_context ctx, const rc_c64 *x_packed, int64_t x_len, rc_c64 *y_packed, int64_t y_len,
+                     const rc_pulse *pulses, int32_t count, std::vector<PulseWork> &work);
 
 // correct_pulse_batch with the context lock held (also the per-hypothesis Doppler bank)
 rc_status pulse_batch_locked(rc_context ctx, const rc_c64 *x_packed, int64_t x_len, rc_c64 *y_packed,
@@ -948,11 +1164,23 @@ rc_status pulse_batch_locked(rc_context ctx, const rc_c64 *x_packed, int64_t x_l
         return fail(ctx, RC_ERR_INVALID_ARG, "buffer lengths must be > 0");
     if (overlaps(x_packed, x_len * 8, y_packed, y_len * 8))
         return fail(ctx, RC_ERR_INVALID_ARG, "input and output buffers overlap");
-    // validate every pulse; output ranges must be pairwise disjoint
+    std::vector<PulseWork> work;
+    st = batch_work(ctx, x_packed, x_len, y_packed, y_len, pulses, count, work);
+    if (st != RC_OK)
+        return st;
+    return run_pulses_locked(ctx, work, k, static_cast<hipStream_t>(stream));
+}
+
+// Validate a packed batch (every pulse inside its buffer, output ranges pairwise disjoint) into
+// its list of pulses with device pointers.
+rc_status batch_work(rc_context ctx, const rc_c64 *x_packed, int64_t x_len, rc_c64 *y_packed, int64_t y_len,
+                     const rc_pulse *pulses, int32_t count, std::vector<PulseWork> &work)
+{
+    rc_status st = RC_OK;
     const float2 *xb = reinterpret_cast<const float2 *>(x_packed);
     float2 *yb = reinterpret_cast<float2 *>(y_packed);
     std::vector<std::pair<int64_t, int64_t>> outs;
-    std::vector<PulseWork> work;
+    work.clear();
     outs.reserve((size_t)count);
     work.reserve((size_t)count);
     for (int32_t i = 0; i < count; ++i) {
@@ -973,56 +1201,71 @@ rc_status pulse_batch_locked(rc_context ctx, const rc_c64 *x_packed, int64_t x_l
     for (size_t i = 1; i < outs.size(); ++i)
         if (outs[i].first < outs[i - 1].second)
             return fail(ctx, RC_ERR_INVALID_ARG, "output ranges overlap");
-    return run_pulses_locked(ctx, work, k, static_cast<hipStream_t>(stream));
+    return RC_OK;
 }
 
-// Launch a validated list of pulses on `s`: Doppler jobs grouped by engine, ionospheric jobs
-// grouped by transform length, plain copies for pulses with neither step.
-rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, const rc_sinc *k, hipStream_t s)
+// A validated list of pulses grouped for launching: Doppler jobs by engine, ionospheric jobs by
+// transform length (Bluestein ones in chunks by convolution length), plain copies for pulses with
+// neither step; and the descriptor blob the launches read, uploaded as one piece.
+struct BlueChunk {
+    int64_t m, max_n;
+    size_t first, count, off_jobs, off_ffts;
+};
+struct BatchPrep {
+    std::vector<SincJob> mfma, fast, direct;
+    int64_t mfma_max = 0, fast_max = 0, direct_max = 0, direct_taps = 0;
+    std::map<int64_t, std::vector<IonoJob>> iono;           // power-of-two lengths, by length
+    std::map<int64_t, std::vector<rc::BluesteinJob>> blue;  // other lengths, by convolution length
+    std::vector<BlueChunk> chunks;
+    std::vector<int32_t> copies;
+    const void *mfma_table = nullptr;
+    int64_t mfma_tiles = 0;
+    size_t mfma_work = 0, bs_work = 0;
+    std::vector<char> blob;  // [mfma | fast | direct | iono groups | Bluestein chunks]
+    size_t off_mfma = 0, off_fast = 0, off_direct = 0;
+    std::vector<size_t> off_iono;
+    // device bytes after the descriptors: [tile list][Bluestein], each region 256-byte aligned
+    static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
+    size_t extra() const { return mfma_work || bs_work ? al(mfma_work) + bs_work : 0; }
+    size_t device_bytes() const { return extra() ? al(blob.size()) + extra() : blob.size(); }
+};
+
+rc_status prepare_batch(rc_context ctx, const std::vector<PulseWork> &work, const rc_sinc *k, BatchPrep &bp)
 {
     rc_status st = RC_OK;
     const int32_t count = (int32_t)work.size();
-    DeviceGuard g(ctx->device);
-
-    // Group the work: fast-path Doppler jobs, generic Doppler jobs, plain copies, and the
-    // ionospheric jobs by transform length (one launch sequence per length).
-    std::vector<SincJob> mfma, fast, direct;
-    int64_t mfma_max = 0, fast_max = 0, direct_max = 0, direct_taps = 0;
-    std::map<int64_t, std::vector<IonoJob>> iono;              // power-of-two lengths, by length
-    std::map<int64_t, std::vector<rc::BluesteinJob>> blue;     // other lengths, by convolution length
-    std::vector<int32_t> copies;
     for (int32_t i = 0; i < count; ++i) {
         const PulseWork &p = work[(size_t)i];
         if (p.flags & RC_DO_DOPPLER) {
             const SincJob j{p.x, p.y, p.n_in, p.n_out, p.alpha, 0};
             const SincPath path = sinc_path(ctx, p.alpha, *k);
             if (path == SincPath::Mfma) {
-                mfma.push_back(j);
-                mfma_max = std::max(mfma_max, p.n_out);
+                bp.mfma.push_back(j);
+                bp.mfma_max = std::max(bp.mfma_max, p.n_out);
             } else if (path == SincPath::Fast) {
-                fast.push_back(j);
-                fast_max = std::max(fast_max, p.n_out);
+                bp.fast.push_back(j);
+                bp.fast_max = std::max(bp.fast_max, p.n_out);
             } else {
-                direct.push_back(j);
-                direct_max = std::max(direct_max, p.n_out);
-                direct_taps = std::max(direct_taps, taps_per_output(*k, p.n_in));
+                bp.direct.push_back(j);
+                bp.direct_max = std::max(bp.direct_max, p.n_out);
+                bp.direct_taps = std::max(bp.direct_taps, taps_per_output(*k, p.n_in));
             }
         } else if (!(p.flags & RC_DO_IONO)) {
-            copies.push_back(i);
+            bp.copies.push_back(i);
         }
         if (p.flags & RC_DO_IONO) {
             const float2 *src = (p.flags & RC_DO_DOPPLER) ? p.y : p.x;
             const PhaseNum ph = phase_numerator(p.tec, p.direction, p.fs_hz, p.carrier, p.n_out);
             if (is_pow2(p.n_out))
-                iono[p.n_out].push_back(IonoJob{src, p.y, ph, p.carrier, p.fs_hz, nullptr});
+                bp.iono[p.n_out].push_back(IonoJob{src, p.y, ph, p.carrier, p.fs_hz, nullptr});
             else
-                blue[rc::bluestein_m(p.n_out)].push_back(
+                bp.blue[rc::bluestein_m(p.n_out)].push_back(
                     rc::BluesteinJob{src, p.y, nullptr, p.n_out, ph, p.carrier, p.fs_hz, nullptr});
         }
     }
-    if (mfma.size() > 65535 || fast.size() > 65535 || direct.size() > 65535)
+    if (bp.mfma.size() > 65535 || bp.fast.size() > 65535 || bp.direct.size() > 65535)
         return fail(ctx, RC_ERR_UNSUPPORTED, "more than 65535 pulses of one kind in a batch");
-    for (auto &kv : iono) {
+    for (auto &kv : bp.iono) {
         const FftPlan *plan = nullptr;
         st = get_plan(ctx, kv.first, &plan);
         if (st != RC_OK)
@@ -1031,97 +1274,160 @@ rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, 
     // Bluestein pulses of one convolution length run in chunks of one launch sequence each; a
     // chunk's pulses have workspaces side by side in one region (at most kBluesteinChunkBytes,
     // or one pulse), reused by the next chunk in stream order.
-    struct BlueChunk {
-        int64_t m, max_n;
-        size_t first, count, off_jobs, off_ffts;
-    };
-    std::vector<BlueChunk> chunks;
-    size_t bs_work = 0;
-    for (auto &kv : blue) {
+    for (auto &kv : bp.blue) {
         const FftPlan *plan = nullptr;
         st = get_plan(ctx, kv.first, &plan);
         if (st != RC_OK)
             return st;
         const size_t per = rc::bluestein_work_bytes(kv.second[0].n);  // 2 m complex values
-        const size_t cap = std::max<size_t>(1, std::min<size_t>(65535, kBluesteinChunkBytes / per));
+        const size_t chunk = ctx->bluestein_chunk > 0 ? (size_t)ctx->bluestein_chunk : kBluesteinChunkBytes;
+        const size_t cap = std::max<size_t>(1, std::min<size_t>(65535, chunk / per));
         for (size_t b = 0; b < kv.second.size(); b += cap) {
             const size_t cnt = std::min(cap, kv.second.size() - b);
             int64_t mx = 0;
             for (size_t i = b; i < b + cnt; ++i)
                 mx = std::max(mx, kv.second[i].n);
-            chunks.push_back(BlueChunk{kv.first, mx, b, cnt, 0, 0});
-            bs_work = std::max(bs_work, cnt * per);
+            bp.chunks.push_back(BlueChunk{kv.first, mx, b, cnt, 0, 0});
+            bp.bs_work = std::max(bp.bs_work, cnt * per);
         }
     }
-    const void *mfma_table = nullptr;
-    int64_t mfma_tiles = 0;
-    size_t mfma_work = 0;
-    if (!mfma.empty()) {
-        st = get_mfma_table(ctx, *k, &mfma_table);
+    if (!bp.mfma.empty()) {
+        st = get_mfma_table(ctx, *k, &bp.mfma_table);
         if (st != RC_OK)
             return st;
-        for (SincJob &j : mfma) {
-            j.tile0 = mfma_tiles;
-            mfma_tiles += (j.n_out + rc::kSincMfmaTile - 1) / rc::kSincMfmaTile;
+        for (SincJob &j : bp.mfma) {
+            j.tile0 = bp.mfma_tiles;
+            bp.mfma_tiles += (j.n_out + rc::kSincMfmaTile - 1) / rc::kSincMfmaTile;
         }
-        if (mfma_tiles > 0x7fffffff)
+        if (bp.mfma_tiles > 0x7fffffff)
             return fail(ctx, RC_ERR_UNSUPPORTED, "more than 2^31 - 1 matrix-core tiles in a batch");
-        if (rc::sinc_mfma_uses_list(k->half_width, mfma_tiles))
-            mfma_work = rc::sinc_mfma_work_bytes(mfma_tiles);
+        if (rc::sinc_mfma_uses_list(k->half_width, bp.mfma_tiles, sinc_grid(ctx, k->half_width)))
+            bp.mfma_work = rc::sinc_mfma_work_bytes(bp.mfma_tiles);
     }
-
-    // one descriptor upload: [mfma | fast | direct | iono groups...], then the tile-list workspace
-    std::vector<char> blob;
     auto append = [&](const void *p, size_t bytes) {
-        const size_t off = (blob.size() + 15) & ~(size_t)15;
-        blob.resize(off + bytes);
-        std::memcpy(blob.data() + off, p, bytes);
+        const size_t off = (bp.blob.size() + 15) & ~(size_t)15;
+        bp.blob.resize(off + bytes);
+        std::memcpy(bp.blob.data() + off, p, bytes);
         return off;
     };
-    const size_t off_mfma = mfma.empty() ? 0 : append(mfma.data(), mfma.size() * sizeof(SincJob));
-    const size_t off_fast = fast.empty() ? 0 : append(fast.data(), fast.size() * sizeof(SincJob));
-    const size_t off_direct = direct.empty() ? 0 : append(direct.data(), direct.size() * sizeof(SincJob));
-    std::vector<size_t> off_iono;
-    for (auto &kv : iono)
-        off_iono.push_back(append(kv.second.data(), kv.second.size() * sizeof(IonoJob)));
+    bp.off_mfma = bp.mfma.empty() ? 0 : append(bp.mfma.data(), bp.mfma.size() * sizeof(SincJob));
+    bp.off_fast = bp.fast.empty() ? 0 : append(bp.fast.data(), bp.fast.size() * sizeof(SincJob));
+    bp.off_direct = bp.direct.empty() ? 0 : append(bp.direct.data(), bp.direct.size() * sizeof(SincJob));
+    for (auto &kv : bp.iono)
+        bp.off_iono.push_back(append(kv.second.data(), kv.second.size() * sizeof(IonoJob)));
     // per Bluestein chunk: its jobs, then 2 x count FFT jobs (chirp transforms, convolutions);
-    // their workspace pointers are filled in once the slot's device address is known
-    for (BlueChunk &c : chunks) {
-        c.off_jobs = append(blue[c.m].data() + c.first, c.count * sizeof(rc::BluesteinJob));
+    // their workspace pointers are filled in once the device address is known
+    for (BlueChunk &c : bp.chunks) {
+        c.off_jobs = append(bp.blue[c.m].data() + c.first, c.count * sizeof(rc::BluesteinJob));
         const std::vector<IonoJob> blank(2 * c.count);
         c.off_ffts = append(blank.data(), blank.size() * sizeof(IonoJob));
     }
-    // device workspace after the descriptors: [tile list][Bluestein]
-    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    const size_t extra = mfma_work || bs_work ? al(mfma_work) + bs_work : 0;
-    char *devc = nullptr;
-    if (!blob.empty() || extra) {
-        void *host = nullptr;
-        st = reserve_descriptors(ctx, blob.size(), extra, &host, &devc);
+    return RC_OK;
+}
+
+// The Bluestein workspace pointers of the blob, for a device copy of it at devc.
+void point_bluestein_work(BatchPrep &bp, char *devc)
+{
+    float2 *bw = reinterpret_cast<float2 *>(devc + BatchPrep::al(bp.blob.size()) + BatchPrep::al(bp.mfma_work));
+    for (const BlueChunk &c : bp.chunks) {
+        auto *jobs = reinterpret_cast<rc::BluesteinJob *>(bp.blob.data() + c.off_jobs);
+        auto *ffts = reinterpret_cast<IonoJob *>(bp.blob.data() + c.off_ffts);
+        for (size_t q = 0; q < c.count; ++q) {
+            float2 *a = bw + (size_t)q * 2 * c.m, *b = a + c.m;
+            jobs[q].a = a;
+            ffts[q] = IonoJob{b, b, PhaseNum{}, 0.0, 0.0, nullptr};
+            ffts[c.count + q] = IonoJob{a, a, PhaseNum{}, 0.0, 0.0, b};
+        }
+    }
+}
+
+// Enqueue the batch's work on s, its descriptors (and workspace) at devc on the device.
+rc_status enqueue_batch(rc_context ctx, const BatchPrep &bp, const std::vector<PulseWork> &work, const rc_sinc *k,
+                        char *devc, hipStream_t s, rc::Profiler *prof, const rc::TileStream *tls,
+                        rc::TileListMode mode)
+{
+    char *wbase = bp.extra() ? devc + BatchPrep::al(bp.blob.size()) : nullptr;
+    void *tile_work = bp.mfma_work ? wbase : nullptr;
+    hipError_t e = hipSuccess;
+    if (mode == rc::TileListMode::BuildOnly) {
+        if (!bp.mfma.empty())
+            e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc + bp.off_mfma), nullptr,
+                                     (int)bp.mfma.size(), bp.mfma_max, bp.mfma_tiles, tile_work, k->half_width,
+                                     bp.mfma_table, s, nullptr, nullptr, mode, sinc_grid(ctx, k->half_width));
+        return e == hipSuccess ? RC_OK : device_fail(ctx, e, "batch tile list");
+    }
+    for (int32_t i : bp.copies) {
+        const PulseWork &p = work[(size_t)i];
+        e = hipMemcpyAsync(p.y, p.x, (size_t)p.n_in * 8, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return device_fail(ctx, e, "copy");
+    }
+    const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
+    if (!bp.mfma.empty())
+        e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc + bp.off_mfma), nullptr, (int)bp.mfma.size(),
+                                 bp.mfma_max, bp.mfma_tiles, tile_work, k->half_width, bp.mfma_table, s, prof, tls,
+                                 mode, sinc_grid(ctx, k->half_width));
+    if (e == hipSuccess && !bp.fast.empty())
+        e = rc::launch_sinc_fast(reinterpret_cast<const SincJob *>(devc + bp.off_fast), nullptr, (int)bp.fast.size(),
+                                 bp.fast_max, k->half_width, kp, s, prof);
+    if (e == hipSuccess && !bp.direct.empty())
+        e = rc::launch_sinc_direct(reinterpret_cast<const SincJob *>(devc + bp.off_direct), nullptr,
+                                   (int)bp.direct.size(), bp.direct_max, *k, kp, bp.direct_taps, s, prof);
+    if (e != hipSuccess)
+        return device_fail(ctx, e, "batch Doppler launch");
+    for (const BlueChunk &c : bp.chunks) {
+        const FftPlan *plan = nullptr;
+        rc_status st = get_plan(ctx, c.m, &plan);
         if (st != RC_OK)
             return st;
-        float2 *bw = reinterpret_cast<float2 *>(devc + al(blob.size()) + al(mfma_work));
-        for (const BlueChunk &c : chunks) {
-            auto *jobs = reinterpret_cast<rc::BluesteinJob *>(blob.data() + c.off_jobs);
-            auto *ffts = reinterpret_cast<IonoJob *>(blob.data() + c.off_ffts);
-            for (size_t q = 0; q < c.count; ++q) {
-                float2 *a = bw + (size_t)q * 2 * c.m, *b = a + c.m;
-                jobs[q].a = a;
-                ffts[q] = IonoJob{b, b, PhaseNum{}, 0.0, 0.0, nullptr};
-                ffts[c.count + q] = IonoJob{a, a, PhaseNum{}, 0.0, 0.0, b};
-            }
+        e = rc::launch_iono_bluestein(*plan, ctx->tw4096, reinterpret_cast<const rc::BluesteinJob *>(devc + c.off_jobs),
+                                      reinterpret_cast<const IonoJob *>(devc + c.off_ffts), rc::BluesteinJob{},
+                                      (int)c.count, c.max_n, s, prof);
+        if (e != hipSuccess)
+            return device_fail(ctx, e, "batch ionosphere launch");
+    }
+    size_t gi = 0;
+    for (auto &kv : bp.iono) {
+        const FftPlan *plan = nullptr;
+        rc_status st = get_plan(ctx, kv.first, &plan);
+        if (st != RC_OK)
+            return st;
+        const IonoJob *jd = reinterpret_cast<const IonoJob *>(devc + bp.off_iono[gi++]);
+        // at most 65535 pulses per launch keeps every grid dimension in range
+        for (size_t b = 0; b < kv.second.size(); b += 65535) {
+            const int nj = (int)std::min<size_t>(65535, kv.second.size() - b);
+            e = rc::launch_iono(*plan, ctx->tw4096, jd + b, nullptr, nj, s, prof);
+            if (e != hipSuccess)
+                return device_fail(ctx, e, "batch ionosphere launch");
         }
-        if (!blob.empty())
-            std::memcpy(host, blob.data(), blob.size());
-        st = upload_descriptors(ctx, blob.size(), s);
+    }
+    return RC_OK;
+}
+
+// Launch a validated list of pulses on `s`, its descriptors staged through the context's ring.
+rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, const rc_sinc *k, hipStream_t s)
+{
+    DeviceGuard g(ctx->device);
+    BatchPrep bp;
+    rc_status st = prepare_batch(ctx, work, k, bp);
+    if (st != RC_OK)
+        return st;
+    const size_t extra = bp.extra();
+    char *devc = nullptr;
+    if (!bp.blob.empty() || extra) {
+        void *host = nullptr;
+        st = reserve_descriptors(ctx, bp.blob.size(), extra, &host, &devc);
+        if (st != RC_OK)
+            return st;
+        point_bluestein_work(bp, devc);
+        if (!bp.blob.empty())
+            std::memcpy(host, bp.blob.data(), bp.blob.size());
+        st = upload_descriptors(ctx, bp.blob.size(), s);
         if (st != RC_OK) {
             (void)mark_descriptors_used(ctx, s);
             return st;
         }
     }
-    const void *dev = devc;
-    char *wbase = extra ? devc + al(blob.size()) : nullptr;
-    void *tile_work = mfma_work ? wbase : nullptr;
     // from here on the slot is in use: mark it whatever happens
     struct SlotMark {
         rc_context ctx;
@@ -1132,55 +1438,15 @@ rc_status run_pulses_locked(rc_context ctx, const std::vector<PulseWork> &work, 
             if (armed)
                 (void)mark_descriptors_used(ctx, s);
         }
-    } slot_mark{ctx, s, dev != nullptr};
-    hipError_t e = hipSuccess;
-    for (int32_t i : copies) {
-        const PulseWork &p = work[(size_t)i];
-        e = hipMemcpyAsync(p.y, p.x, (size_t)p.n_in * 8, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess)
-            return device_fail(ctx, e, "copy");
-    }
-    const rc::KaiserPoly kp = rc::make_kaiser_poly(k->window == RC_WIN_KAISER ? k->kaiser_beta : 0.0);
-    if (!mfma.empty()) {
-        const rc::TileStream tls = tile_stream_of(ctx);
-        e = rc::launch_sinc_mfma(reinterpret_cast<const SincJob *>(devc + off_mfma), nullptr, (int)mfma.size(),
-                                 mfma_max, mfma_tiles, tile_work, k->half_width, mfma_table, s, prof_of(ctx), &tls);
-    }
-    if (e == hipSuccess && !fast.empty())
-        e = rc::launch_sinc_fast(reinterpret_cast<const SincJob *>(devc + off_fast), nullptr, (int)fast.size(),
-                                 fast_max, k->half_width, kp, s, prof_of(ctx));
-    if (e == hipSuccess && !direct.empty())
-        e = rc::launch_sinc_direct(reinterpret_cast<const SincJob *>(devc + off_direct), nullptr,
-                                   (int)direct.size(), direct_max, *k, kp, direct_taps, s, prof_of(ctx));
-    if (e != hipSuccess)
-        return device_fail(ctx, e, "batch Doppler launch");
-    size_t gi = 0;
-    for (const BlueChunk &c : chunks) {
-        const FftPlan *plan = nullptr;
-        st = get_plan(ctx, c.m, &plan);
-        if (st != RC_OK)
-            return st;
-        e = rc::launch_iono_bluestein(*plan, ctx->tw4096, reinterpret_cast<const rc::BluesteinJob *>(devc + c.off_jobs),
-                                      reinterpret_cast<const IonoJob *>(devc + c.off_ffts), rc::BluesteinJob{},
-                                      (int)c.count, c.max_n, s, prof_of(ctx));
-        if (e != hipSuccess)
-            return device_fail(ctx, e, "batch ionosphere launch");
-    }
-    for (auto &kv : iono) {
-        const FftPlan *plan = nullptr;
-        st = get_plan(ctx, kv.first, &plan);
-        if (st != RC_OK)
-            return st;
-        const IonoJob *jd = reinterpret_cast<const IonoJob *>(devc + off_iono[gi++]);
-        // at most 65535 pulses per launch keeps every grid dimension in range
-        for (size_t b = 0; b < kv.second.size(); b += 65535) {
-            const int nj = (int)std::min<size_t>(65535, kv.second.size() - b);
-            e = rc::launch_iono(*plan, ctx->tw4096, jd + b, nullptr, nj, s, prof_of(ctx));
-            if (e != hipSuccess)
-                return device_fail(ctx, e, "batch ionosphere launch");
-        }
-    }
-    if (dev) {
+    } slot_mark{ctx, s, devc != nullptr};
+    rc::TileStream tls{};
+    if (!bp.mfma.empty())
+        tls = tile_stream_of(ctx);
+    st = enqueue_batch(ctx, bp, work, k, devc, s, prof_of(ctx), bp.mfma.empty() ? nullptr : &tls,
+                       rc::TileListMode::BuildAndRun);
+    if (st != RC_OK)
+        return st;
+    if (devc) {
         slot_mark.armed = false;
         return mark_descriptors_used(ctx, s);
     }
@@ -1214,6 +1480,249 @@ rc_status correct_pulse_batch(rc_context ctx, const rc_c64 *x_packed, int64_t x_
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->last_error.clear();
     return pulse_batch_locked(ctx, x_packed, x_len, y_packed, y_len, pulses, count, k, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Batch plans: one batch's launch sequence captured once in a HIP graph and replayed.
+
+struct rc_batch_plan_s {
+    rc_context ctx = nullptr;
+    rc_sinc k{};
+    const rc_c64 *x = nullptr;
+    rc_c64 *y = nullptr;
+    int64_t x_len = 0, y_len = 0;
+    std::vector<PulseWork> work;
+    BatchPrep bp;
+    char *dev = nullptr;            // descriptors, then the tile list and Bluestein workspace
+    void *host = nullptr;           // pinned staging of descriptor updates
+    hipEvent_t uploaded = nullptr;  // the last update's upload (the staging buffer is free after it)
+    hipStream_t stream = nullptr;   // set-up and capture
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::mutex mu;
+};
+
+namespace {
+
+// Two preparations launch the same graph: the same groups in the same order with the same
+// lengths, tile counts, Bluestein chunks and descriptor layout, and the same plain copies.
+bool same_launches(const BatchPrep &a, const BatchPrep &b, const std::vector<PulseWork> &wa,
+                   const std::vector<PulseWork> &wb)
+{
+    auto same_jobs = [](const std::vector<SincJob> &u, const std::vector<SincJob> &v) {
+        if (u.size() != v.size())
+            return false;
+        for (size_t i = 0; i < u.size(); ++i)
+            if (u[i].n_in != v[i].n_in || u[i].n_out != v[i].n_out || u[i].tile0 != v[i].tile0)
+                return false;
+        return true;
+    };
+    if (!same_jobs(a.mfma, b.mfma) || !same_jobs(a.fast, b.fast) || !same_jobs(a.direct, b.direct))
+        return false;
+    if (a.mfma_max != b.mfma_max || a.fast_max != b.fast_max || a.direct_max != b.direct_max ||
+        a.direct_taps != b.direct_taps || a.mfma_tiles != b.mfma_tiles || a.mfma_work != b.mfma_work ||
+        a.bs_work != b.bs_work || a.mfma_table != b.mfma_table || a.blob.size() != b.blob.size())
+        return false;
+    if (a.iono.size() != b.iono.size() || a.chunks.size() != b.chunks.size() || a.copies != b.copies)
+        return false;
+    for (auto ia = a.iono.begin(), ib = b.iono.begin(); ia != a.iono.end(); ++ia, ++ib)
+        if (ia->first != ib->first || ia->second.size() != ib->second.size())
+            return false;
+    for (size_t i = 0; i < a.chunks.size(); ++i) {
+        const BlueChunk &p = a.chunks[i], &q = b.chunks[i];
+        if (p.m != q.m || p.max_n != q.max_n || p.first != q.first || p.count != q.count ||
+            p.off_jobs != q.off_jobs || p.off_ffts != q.off_ffts)
+            return false;
+    }
+    for (int32_t i : a.copies)  // the graph's copy nodes hold their pointers
+        if (wa[(size_t)i].x != wb[(size_t)i].x || wa[(size_t)i].y != wb[(size_t)i].y)
+            return false;
+    return true;
+}
+
+void free_plan(rc_batch_plan p)
+{
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    if (p->uploaded)
+        (void)hipEventDestroy(p->uploaded);
+    if (p->stream)
+        (void)hipStreamDestroy(p->stream);
+    if (p->host)
+        (void)hipHostFree(p->host);
+    if (p->dev)
+        (void)hipFree(p->dev);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+rc_status rc_batch_plan_create(rc_context ctx, const rc_c64 *x_packed, int64_t x_len, rc_c64 *y_packed,
+                               int64_t y_len, const rc_pulse *pulses, int32_t count, const rc_sinc *k,
+                               rc_batch_plan *out)
+{
+    if (!ctx || !out)
+        return RC_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    rc_status st = check_sinc(ctx, k);
+    if (st != RC_OK)
+        return st;
+    if (count <= 0 || !pulses || !x_packed || !y_packed)
+        return fail(ctx, RC_ERR_INVALID_ARG, "a plan needs count >= 1 and non-NULL pointers");
+    if (x_len <= 0 || y_len <= 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "buffer lengths must be > 0");
+    if (overlaps(x_packed, x_len * 8, y_packed, y_len * 8))
+        return fail(ctx, RC_ERR_INVALID_ARG, "input and output buffers overlap");
+    rc_batch_plan p = new (std::nothrow) rc_batch_plan_s();
+    if (!p)
+        return RC_ERR_OUT_OF_MEMORY;
+    p->ctx = ctx;
+    p->k = *k;
+    p->x = x_packed;
+    p->y = y_packed;
+    p->x_len = x_len;
+    p->y_len = y_len;
+    st = batch_work(ctx, x_packed, x_len, y_packed, y_len, pulses, count, p->work);
+    if (st == RC_OK)
+        st = prepare_batch(ctx, p->work, k, p->bp);
+    if (st != RC_OK) {
+        delete p;
+        return st;
+    }
+    DeviceGuard g(ctx->device);
+    auto bail = [&](hipError_t e, const char *where) {
+        free_plan(p);
+        return e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation
+                   ? fail(ctx, RC_ERR_OUT_OF_MEMORY, std::string(where) + ": out of device memory")
+                   : device_fail(ctx, e, where);
+    };
+    const size_t bytes = p->bp.device_bytes();
+    hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming);
+    if (e != hipSuccess)
+        return bail(e, "batch plan stream");
+    if (bytes) {
+        e = hipMalloc(reinterpret_cast<void **>(&p->dev), bytes);
+        if (e == hipSuccess && !p->bp.blob.empty())
+            e = hipHostMalloc(&p->host, p->bp.blob.size(), hipHostMallocDefault);
+        if (e != hipSuccess)
+            return bail(e, "batch plan workspace");
+        point_bluestein_work(p->bp, p->dev);
+        if (!p->bp.blob.empty()) {
+            std::memcpy(p->host, p->bp.blob.data(), p->bp.blob.size());
+            e = hipMemcpyAsync(p->dev, p->host, p->bp.blob.size(), hipMemcpyHostToDevice, p->stream);
+            if (e == hipSuccess)
+                e = hipEventRecord(p->uploaded, p->stream);
+            if (e != hipSuccess)
+                return bail(e, "batch plan descriptors");
+        }
+    }
+    // the tile list depends on the descriptors only: built once here (and on updates)
+    st = enqueue_batch(ctx, p->bp, p->work, &p->k, p->dev, p->stream, nullptr, nullptr, rc::TileListMode::BuildOnly);
+    if (st != RC_OK) {
+        free_plan(p);
+        return st;
+    }
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess)
+        return bail(e, "batch plan set-up");
+    e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return bail(e, "batch plan capture");
+    st = enqueue_batch(ctx, p->bp, p->work, &p->k, p->dev, p->stream, nullptr, nullptr, rc::TileListMode::RunOnly);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(p->stream, &graph);
+    p->graph = graph;
+    if (st != RC_OK) {
+        free_plan(p);
+        return st;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess)
+        return bail(e, "batch plan graph");
+    *out = p;
+    return RC_OK;
+}
+
+rc_status rc_batch_plan_launch(rc_batch_plan plan, void *stream)
+{
+    if (!plan)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(plan->mu);
+    DeviceGuard g(plan->ctx->device);
+    const hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> lc(plan->ctx->mu);
+        return device_fail(plan->ctx, e, "rc_batch_plan_launch");
+    }
+    return RC_OK;
+}
+
+rc_status rc_batch_plan_update(rc_batch_plan plan, const rc_pulse *pulses, int32_t count, void *stream)
+{
+    if (!plan)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lp(plan->mu);
+    rc_context ctx = plan->ctx;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    if (count != (int32_t)plan->work.size() || !pulses)
+        return fail(ctx, RC_ERR_INVALID_ARG, "an update must give the plan's number of pulses");
+    std::vector<PulseWork> work;
+    rc_status st = batch_work(ctx, plan->x, plan->x_len, plan->y, plan->y_len, pulses, count, work);
+    if (st != RC_OK)
+        return st;
+    BatchPrep bp;
+    st = prepare_batch(ctx, work, &plan->k, bp);
+    if (st != RC_OK)
+        return st;
+    if (!same_launches(plan->bp, bp, plan->work, work))
+        return fail(ctx, RC_ERR_UNSUPPORTED,
+                    "these pulses need other launches than the plan's (lengths, flags, resampling engines, "
+                    "Bluestein groups or copies differ): create a new plan");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (!bp.blob.empty()) {
+        point_bluestein_work(bp, plan->dev);
+        e = hipEventSynchronize(plan->uploaded);  // the staging buffer's last upload has been read
+        if (e == hipSuccess) {
+            std::memcpy(plan->host, bp.blob.data(), bp.blob.size());
+            e = hipMemcpyAsync(plan->dev, plan->host, bp.blob.size(), hipMemcpyHostToDevice, s);
+        }
+        if (e == hipSuccess)
+            e = hipEventRecord(plan->uploaded, s);
+        if (e != hipSuccess)
+            return device_fail(ctx, e, "rc_batch_plan_update");
+    }
+    st = enqueue_batch(ctx, bp, work, &plan->k, plan->dev, s, nullptr, nullptr, rc::TileListMode::BuildOnly);
+    if (st != RC_OK)
+        return st;
+    plan->work = std::move(work);
+    plan->bp = std::move(bp);
+    return RC_OK;
+}
+
+rc_status rc_batch_plan_destroy(rc_batch_plan plan)
+{
+    if (!plan)
+        return RC_ERR_INVALID_ARG;
+    {
+        DeviceGuard g(plan->ctx->device);
+        (void)hipDeviceSynchronize();  // no launch of the plan may still read its buffers
+    }
+    free_plan(plan);
+    return RC_OK;
 }
 
 rc_status correct_doppler_bank(rc_context ctx, const rc_c64 *x, int64_t n, rc_c64 *y, int64_t n_out, double fs_hz,
@@ -1300,6 +1809,7 @@ struct rc_server_s {
         PulseWork work;
         int64_t bytes;
         clock::time_point submitted;
+        hipEvent_t ready;  // recorded on the request's stream at submission
     };
     struct Flight {
         hipEvent_t done;
@@ -1321,6 +1831,7 @@ struct rc_server_s {
     std::deque<Flight> flights;                  // launched, not complete (stream order)
     std::unordered_map<int64_t, Ticket> tickets; // admitted, not yet waited for
     std::vector<hipEvent_t> event_pool;
+    std::vector<hipEvent_t> ready_pool;          // request-ready events no request holds
     int64_t in_flight_bytes = 0;                 // admitted and not complete
     int64_t next_ticket = 1;
     bool stop = false, launcher_done = false;
@@ -1375,7 +1886,12 @@ void server_launcher(rc_server srv)
             std::lock_guard<std::mutex> lk(srv->ctx->mu);
             srv->ctx->last_error.clear();
             DeviceGuard g(srv->ctx->device);
-            st = run_pulses_locked(srv->ctx, work, &srv->k, srv->stream);
+            st = RC_OK;
+            for (const auto &r : take)
+                if (hipStreamWaitEvent(srv->stream, r.ready, 0) != hipSuccess)
+                    st = RC_ERR_DEVICE;
+            if (st == RC_OK)
+                st = run_pulses_locked(srv->ctx, work, &srv->k, srv->stream);
             if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
                 ev = nullptr;
             if (ev && hipEventRecord(ev, srv->stream) != hipSuccess)
@@ -1421,6 +1937,7 @@ void server_completer(rc_server srv)
                     it->second.status = st;
                 }
                 srv->in_flight_bytes -= r.bytes;
+                srv->ready_pool.push_back(r.ready);
                 srv->completed += 1;
                 srv->samples += r.work.n_out;
                 srv->latency_ms.push_back(std::chrono::duration<double, std::milli>(now - r.submitted).count());
@@ -1432,6 +1949,21 @@ void server_completer(rc_server srv)
         srv->cv_done.notify_all();
         srv->cv_queue.notify_all();  // a flight slot is free
     }
+}
+
+// Bytes a request holds while admitted: its input and output, and an upper bound of its share
+// of a batch's device workspace, so that the workspace of the batches in flight never exceeds
+// the server's budget: the Bluestein buffers of a length that is not a power of two
+// (bluestein_work_bytes), the matrix-core tile list of a Doppler pulse on that path, and 1 KiB
+// for its descriptors and the workspace regions' alignment.
+int64_t request_bytes(rc_context ctx, const PulseWork &w, const rc_sinc &k)
+{
+    int64_t b = 8 * (w.n_in + w.n_out) + 1024;
+    if ((w.flags & RC_DO_IONO) && !is_pow2(w.n_out))
+        b += (int64_t)rc::bluestein_work_bytes(w.n_out);
+    if ((w.flags & RC_DO_DOPPLER) && sinc_path(ctx, w.alpha, k) == SincPath::Mfma)
+        b += (int64_t)rc::sinc_mfma_work_bytes((w.n_out + rc::kSincMfmaTile - 1) / rc::kSincMfmaTile);
+    return b;
 }
 
 double percentile(std::vector<double> v, double q)
@@ -1518,18 +2050,44 @@ rc_status rc_server_submit(rc_server srv, const rc_request *req, int64_t *ticket
         if (!(w.flags & RC_DO_DOPPLER) && req->x != req->y && overlaps(req->x, w.n_in * 8, req->y, w.n_out * 8))
             return fail(srv->ctx, RC_ERR_INVALID_ARG, "request: x and y partially overlap");
     }
-    // bytes a request holds while admitted: its input and output, and a transform workspace
-    // of up to 16 B per sample for lengths that are not powers of two
-    const int64_t bytes = 8 * (w.n_in + w.n_out) + ((w.flags & RC_DO_IONO) && !is_pow2(w.n_out) ? 32 * w.n_out : 0);
+    const int64_t bytes = request_bytes(srv->ctx, w, srv->k);
+    // the request reads x only after the work enqueued on req->stream so far
+    hipEvent_t ready = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (!srv->ready_pool.empty()) {
+            ready = srv->ready_pool.back();
+            srv->ready_pool.pop_back();
+        }
+    }
+    {
+        DeviceGuard g(srv->ctx->device);
+        hipError_t e = ready ? hipSuccess : hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventRecord(ready, static_cast<hipStream_t>(req->stream));
+        if (e != hipSuccess) {
+            if (ready) {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                srv->ready_pool.push_back(ready);
+            }
+            std::lock_guard<std::mutex> lk(srv->ctx->mu);
+            return device_fail(srv->ctx, e, "request: recording its stream");
+        }
+    }
     std::lock_guard<std::mutex> lk(srv->mu);
-    if (srv->stop)
+    auto give_back = [&] { srv->ready_pool.push_back(ready); };
+    if (srv->stop) {
+        give_back();
         return RC_ERR_INVALID_ARG;
+    }
     if (bytes > srv->budget) {
         srv->rejected += 1;
+        give_back();
         return RC_ERR_UNSUPPORTED;  // can never be admitted under this budget
     }
     if (srv->in_flight_bytes + bytes > srv->budget) {
         srv->rejected += 1;
+        give_back();
         return RC_ERR_BUSY;
     }
     const auto now = rc_server_s::clock::now();
@@ -1541,10 +2099,21 @@ rc_status rc_server_submit(rc_server srv, const rc_request *req, int64_t *ticket
     srv->in_flight_bytes += bytes;
     srv->submitted += 1;
     srv->tickets.emplace(t, rc_server_s::Ticket{});
-    srv->queue.push_back({t, w, bytes, now});
+    srv->queue.push_back({t, w, bytes, now, ready});
     srv->cv_queue.notify_one();
     *ticket = t;
     return RC_OK;
+}
+
+int64_t rc_server_request_bytes(rc_server srv, const rc_request *req)
+{
+    if (!srv || !req)
+        return -1;
+    const PulseWork w{reinterpret_cast<const float2 *>(req->x), reinterpret_cast<float2 *>(req->y), req->n_in,
+                      req->n_out, req->fs_hz, req->alpha, req->tec_el_per_m2, req->carrier_hz, req->flags,
+                      req->direction};
+    std::lock_guard<std::mutex> lk(srv->ctx->mu);
+    return request_bytes(srv->ctx, w, srv->k);
 }
 
 rc_status rc_server_poll(rc_server srv, int64_t ticket, int32_t *done)
@@ -1648,6 +2217,8 @@ rc_status rc_server_destroy(rc_server srv)
         DeviceGuard g(srv->ctx->device);
         for (hipEvent_t e : srv->event_pool)
             (void)hipEventDestroy(e);
+        for (hipEvent_t e : srv->ready_pool)
+            (void)hipEventDestroy(e);
         (void)hipStreamDestroy(srv->stream);
     }
     delete srv;
@@ -1673,6 +2244,130 @@ rc_status rc_set_bank_engine(rc_context ctx, int32_t engine)
     if (engine != RC_BANK_ENGINE_AUTO && engine != RC_BANK_ENGINE_FARROW && engine != RC_BANK_ENGINE_PER_HYPOTHESIS)
         return fail(ctx, RC_ERR_INVALID_ARG, "unknown bank engine");
     ctx->bank_engine = engine;
+    return RC_OK;
+}
+
+rc_status rc_set_fft_levels(rc_context ctx, int64_t n, const int32_t *levels, int32_t count)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    if (count < 0 || (count > 0 && !levels))
+        return fail(ctx, RC_ERR_INVALID_ARG, "NULL levels or negative count");
+    if (count == 0) {
+        ctx->fft_levels.erase(n);
+    } else {
+        std::vector<int> lv(levels, levels + count);
+        FftPlan probe;
+        if (rc::build_fft_plan_levels(n, lv, probe) != hipSuccess)
+            return fail(ctx, RC_ERR_INVALID_ARG,
+                        "levels must be powers of two in [2, 256], at most 3, with 4096 times their product = n");
+        ctx->fft_levels[n] = lv;
+    }
+    ctx->plans.erase(n);  // rebuilt with the new split on its next use
+    return RC_OK;
+}
+
+rc_status rc_set_sinc_grid(rc_context ctx, int32_t half_width, int32_t wg_per_cu)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    if ((half_width != 64 && half_width != 128) || wg_per_cu < 0 || wg_per_cu > 64)
+        return fail(ctx, RC_ERR_INVALID_ARG, "half_width must be 64 or 128 and wg_per_cu in [0, 64]");
+    ctx->sinc_wg_per_cu[half_width == 128 ? 1 : 0] = wg_per_cu;
+    return RC_OK;
+}
+
+rc_status rc_set_bluestein_chunk(rc_context ctx, int64_t bytes)
+{
+    if (!ctx)
+        return RC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last_error.clear();
+    if (bytes < 0)
+        return fail(ctx, RC_ERR_INVALID_ARG, "bytes must be >= 0");
+    ctx->bluestein_chunk = bytes;
+    return RC_OK;
+}
+
+rc_status rc_load_tuning(rc_context ctx, const char *path)
+{
+    if (!ctx || !path)
+        return RC_ERR_INVALID_ARG;
+    std::string text, err;
+    {
+        std::FILE *f = std::fopen(path, "rb");
+        if (!f) {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            return fail(ctx, RC_ERR_INVALID_ARG, std::string("cannot open the tuning file ") + path);
+        }
+        char buf[4096];
+        size_t got;
+        while ((got = std::fread(buf, 1, sizeof buf, f)) > 0)
+            text.append(buf, got);
+        std::fclose(f);
+    }
+    Json root;
+    if (!parse_json(text, root, err) || root.kind != Json::Object) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        return fail(ctx, RC_ERR_INVALID_ARG, std::string("tuning file ") + path + ": " + (err.empty() ? "not an object" : err));
+    }
+    auto bad = [&](const std::string &why) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        return fail(ctx, RC_ERR_INVALID_ARG, std::string("tuning file ") + path + ": " + why);
+    };
+    // validate everything first, then apply
+    std::vector<std::pair<int64_t, std::vector<int32_t>>> lv;
+    std::vector<std::pair<int32_t, int32_t>> grid;
+    int64_t chunk = -1;
+    for (const auto &kv : root.obj) {
+        if (kv.first == "fft_levels") {
+            if (kv.second.kind != Json::Object)
+                return bad("fft_levels must be an object");
+            for (const auto &e : kv.second.obj) {
+                if (e.second.kind != Json::Array)
+                    return bad("fft_levels entries must be arrays");
+                std::vector<int32_t> v;
+                for (const auto &q : e.second.arr) {
+                    if (q.kind != Json::Number)
+                        return bad("fft_levels values must be numbers");
+                    v.push_back((int32_t)q.num);
+                }
+                char *end = nullptr;
+                const long long n = std::strtoll(e.first.c_str(), &end, 10);
+                if (!end || *end)
+                    return bad("fft_levels keys must be transform lengths");
+                lv.emplace_back((int64_t)n, v);
+            }
+        } else if (kv.first == "sinc_grid") {
+            if (kv.second.kind != Json::Object)
+                return bad("sinc_grid must be an object");
+            for (const auto &e : kv.second.obj) {
+                if (e.second.kind != Json::Number)
+                    return bad("sinc_grid values must be numbers");
+                grid.emplace_back((int32_t)std::atoi(e.first.c_str()), (int32_t)e.second.num);
+            }
+        } else if (kv.first == "bluestein_chunk_bytes") {
+            if (kv.second.kind != Json::Number)
+                return bad("bluestein_chunk_bytes must be a number");
+            chunk = (int64_t)kv.second.num;
+        }  // other keys (the measurements behind the choices) are ignored
+    }
+    for (const auto &e : lv) {
+        const rc_status st = rc_set_fft_levels(ctx, e.first, e.second.data(), (int32_t)e.second.size());
+        if (st != RC_OK)
+            return st;
+    }
+    for (const auto &e : grid) {
+        const rc_status st = rc_set_sinc_grid(ctx, e.first, e.second);
+        if (st != RC_OK)
+            return st;
+    }
+    if (chunk >= 0)
+        return rc_set_bluestein_chunk(ctx, chunk);
     return RC_OK;
 }
 

@@ -67,6 +67,8 @@ constexpr double kPi = 3.14159265358979323846;
 struct KaiserPoly {
     int n;          // number of terms
     double c[56];   // c[j] = (beta^2/4)^j / (j!)^2 / I0(beta)
+    int nf;         // terms a float32 evaluation needs: the rest sum to below 2^-27 of K(0) = 1
+    float cf[56];   // c[j] rounded to float32
 };
 
 // Global-memory view of a device pointer.  Kernels read their pointers from job descriptors,
@@ -134,7 +136,7 @@ bool sinc_mfma_eligible(double alpha, const rc_sinc &k);
 hipError_t build_sinc_mfma_table(int half_width, double beta, void **dev, std::vector<void *> &allocs);
 // Batches of more tiles than the resident workgroups run persistent workgroups over a tile list
 // sorted by phase; the list needs `sinc_mfma_work_bytes(ntiles)` of device workspace.
-bool sinc_mfma_uses_list(int half_width, int64_t ntiles);
+bool sinc_mfma_uses_list(int half_width, int64_t ntiles, int wg_per_cu = 0);
 size_t sinc_mfma_work_bytes(int64_t ntiles);
 // Where the tile-list kernels may run: on `stream` once `after` (the descriptor upload) has
 // completed, signalling `done`, which the compute stream waits for before the resampling kernel.
@@ -145,11 +147,16 @@ struct TileStream {
     hipEvent_t after;  // may be null
     hipEvent_t done;
 };
+// What launch_sinc_mfma enqueues when it uses a tile list: the list and then the resampling
+// kernel; the list alone (it depends only on the job descriptors); or the resampling kernel over
+// a list built earlier in the same workspace (a captured graph replaying a fixed batch).
+enum class TileListMode { BuildAndRun, BuildOnly, RunOnly };
 // jobs_dev (device array, tile0 set) or job_inline (one job, tile0 = 0); `work` is the workspace
 // when sinc_mfma_uses_list(), else unused.  With ts null the tile list is built on s.
 hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, int njobs,
                             int64_t max_out, int64_t ntiles, void *work, int half_width,
-                            const void *table, hipStream_t s, Profiler *prof, const TileStream *ts = nullptr);
+                            const void *table, hipStream_t s, Profiler *prof, const TileStream *ts = nullptr,
+                            TileListMode mode = TileListMode::BuildAndRun, int wg_per_cu = 0);
 KaiserPoly make_kaiser_poly(double beta);
 size_t sinc_fast_lds_bytes(int half_width);
 
@@ -235,6 +242,10 @@ struct FftPlan {
 };
 
 hipError_t build_fft_plan(int64_t n, FftPlan &plan, std::vector<void *> &allocs);
+// The plan of a power-of-two n > 4096 with the given strided levels (each a power of two in
+// [2, 256], at most kFftMaxLevels - 1 of them) before the 4096-point contiguous level; their
+// product times 4096 must be n.  hipErrorInvalidValue otherwise.
+hipError_t build_fft_plan_levels(int64_t n, const std::vector<int> &strided, FftPlan &plan);
 hipError_t make_base_twiddles(float2 **dev);  // exp(-2 pi i q / 4096), q < 4096
 
 // What the contiguous FFT pass multiplies each bin by: the dispersive phase (the ionospheric
@@ -357,6 +368,10 @@ struct rc_context_s {
     int sinc_engine = 0;  // RC_SINC_AUTO / RC_SINC_VALU / RC_SINC_DIRECT
     int bank_engine = 0;  // RC_BANK_ENGINE_AUTO / _FARROW / _PER_HYPOTHESIS
     int64_t mem_budget = 0;  // cap on the slots' device workspace in bytes (rc_set_mem_budget); 0: none
+    // tuning (rc_set_fft_levels, rc_set_sinc_grid, rc_set_bluestein_chunk, rc_load_tuning)
+    std::map<int64_t, std::vector<int>> fft_levels;  // strided levels by transform length
+    int sinc_wg_per_cu[2] = {0, 0};                   // matrix-core grid at H = 64, 128 (0: occupancy)
+    int64_t bluestein_chunk = 0;                      // Bluestein chunk workspace cap (0: default)
     // device address of this device's copy of the library's static workspace (the
     // no-allocation entry point's Bluestein buffers), looked up once per device at rc_create
     float2 *static_scratch = nullptr;

@@ -663,13 +663,15 @@ hipError_t mf_device(MfDevice **out)
     return hipSuccess;
 }
 
+// Resident workgroups of the persistent grid: wg_per_cu per CU (0: as many as fit), at most
+// what the kernel's resources allow.
 template <int H>
-hipError_t resident_wgs(int64_t *n)
+hipError_t resident_wgs(int64_t *n, int wg_per_cu)
 {
     MfDevice *d = nullptr;
     hipError_t e = mf_device<H>(&d);
     if (e == hipSuccess)
-        *n = (int64_t)d->per_cu * d->cus;
+        *n = (int64_t)(wg_per_cu > 0 ? std::min(wg_per_cu, d->per_cu) : d->per_cu) * d->cus;
     return e;
 }
 
@@ -681,15 +683,21 @@ size_t work_phase_off(int64_t n) { return work_counts_off(n) + (size_t)sort_chun
 
 template <int H>
 hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int64_t max_out, int64_t ntiles,
-                    void *work, const unsigned char *table, hipStream_t s, Profiler *prof, const TileStream *ts)
+                    void *work, const unsigned char *table, hipStream_t s, Profiler *prof, const TileStream *ts,
+                    TileListMode mode, int wg_per_cu)
 {
     MfDevice *d = nullptr;
     hipError_t e = mf_device<H>(&d);
     if (e != hipSuccess)
         return e;
     const size_t lds = MfGeom<H>::bytes;
-    const int64_t resident = (int64_t)d->per_cu * d->cus;
+    int64_t resident = 0;
+    e = resident_wgs<H>(&resident, wg_per_cu);
+    if (e != hipSuccess)
+        return e;
     if (ntiles <= resident || !work) {
+        if (mode == TileListMode::BuildOnly)
+            return hipSuccess;  // no list on this path
         const int64_t nblk = (max_out + kMfOut - 1) / kMfOut;
         if (prof)
             prof->begin(kKSincMfma, s);
@@ -706,6 +714,9 @@ hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int6
     uint2 *list = reinterpret_cast<uint2 *>(w + work_list_off(ntiles));
     unsigned char *phase = w + work_phase_off(ntiles);
     const int64_t tblk = (max_out + (int64_t)kMfOut * 256 - 1) / ((int64_t)kMfOut * 256);
+    if (mode == TileListMode::RunOnly)
+        goto run;
+    {
     hipStream_t ls = s;
     if (ts) {
         ls = ts->stream;
@@ -735,8 +746,10 @@ hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int6
         if (e == hipSuccess)
             e = hipStreamWaitEvent(s, ts->done, 0);
     }
-    if (e != hipSuccess)
+    if (e != hipSuccess || mode == TileListMode::BuildOnly)
         return e;
+    }
+run:
     int64_t grid = resident;
     if (grid >= kXcds)
         grid -= grid % kXcds;
@@ -758,10 +771,11 @@ bool sinc_mfma_eligible(double alpha, const rc_sinc &k)
            std::fabs(alpha - 1.0) <= kSincMfmaMaxEps && make_kaiser_poly(k.kaiser_beta).n <= kMfKaiserTerms;
 }
 
-bool sinc_mfma_uses_list(int half_width, int64_t ntiles)
+bool sinc_mfma_uses_list(int half_width, int64_t ntiles, int wg_per_cu)
 {
     int64_t resident = 0;
-    const hipError_t e = half_width == 64 ? resident_wgs<64>(&resident) : resident_wgs<128>(&resident);
+    const hipError_t e =
+        half_width == 64 ? resident_wgs<64>(&resident, wg_per_cu) : resident_wgs<128>(&resident, wg_per_cu);
     return e == hipSuccess && ntiles > resident;
 }
 
@@ -781,7 +795,7 @@ hipError_t build_sinc_mfma_table(int half_width, double beta, void **dev, std::v
 
 hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, int njobs, int64_t max_out,
                             int64_t ntiles, void *work, int half_width, const void *table, hipStream_t s,
-                            Profiler *prof, const TileStream *ts)
+                            Profiler *prof, const TileStream *ts, TileListMode mode, int wg_per_cu)
 {
     if (njobs <= 0 || max_out <= 0)
         return hipSuccess;
@@ -793,8 +807,9 @@ hipError_t launch_sinc_mfma(const SincJob *jobs_dev, const SincJob *job_inline, 
         return hipErrorInvalidValue;  // the list kernels read the job array
     const SincJob inl = job_inline ? *job_inline : SincJob{};
     const unsigned char *t = static_cast<const unsigned char *>(table);
-    return half_width == 64 ? launch_h<64>(jobs_dev, inl, njobs, max_out, ntiles, work, t, s, prof, ts)
-                            : launch_h<128>(jobs_dev, inl, njobs, max_out, ntiles, work, t, s, prof, ts);
+    return half_width == 64
+               ? launch_h<64>(jobs_dev, inl, njobs, max_out, ntiles, work, t, s, prof, ts, mode, wg_per_cu)
+               : launch_h<128>(jobs_dev, inl, njobs, max_out, ntiles, work, t, s, prof, ts, mode, wg_per_cu);
 }
 
 }  // namespace rc

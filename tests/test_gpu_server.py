@@ -137,8 +137,13 @@ def test_server_admission_poll_and_errors(torch, ctx):
     n = 1 << 24  # ~0.6 ms of device work per request: far longer than the next submit call
     x = dev(torch, wf.bandlimited_noise(n, wf.rng_for(302, 0)))
     ys = [torch.empty(n, dtype=torch.complex64, device="cuda") for _ in range(4)]
-    # a budget of three requests (16 B per sample each)
-    srv = rc.Server(ctx, rc.Sinc(64), mem_budget_bytes=3 * 16 * n, max_batch=16)
+    # a budget of three requests: their samples (16 B each), descriptors and tile lists
+    probe = rc.Server(ctx, rc.Sinc(64), mem_budget_bytes=1 << 40, max_batch=16)
+    charge = max(probe.submit(x, ys[0], alpha=alpha_exact(1000.0 * i), tec=20 * wf.TECU, carrier=450e6, fs=10e6,
+                              charge_only=True) for i in range(4))
+    probe.close()
+    assert 16 * n < charge < 16 * n + (1 << 20)
+    srv = rc.Server(ctx, rc.Sinc(64), mem_budget_bytes=3 * charge + 1000, max_batch=16)
     t = [srv.submit(x, ys[i], alpha=alpha_exact(1000.0 * i), tec=20 * wf.TECU, carrier=450e6, fs=10e6)
          for i in range(3)]
     with pytest.raises(rc.RcError) as ei:  # the fourth does not fit while three are in flight
@@ -165,3 +170,69 @@ def test_server_admission_poll_and_errors(torch, ctx):
     srv.reset_stats()
     assert srv.stats()["completed"] == 0
     srv.close()
+
+
+def test_server_budget_bounds_the_context_workspace(torch):
+    """With the context's workspace capped at the server's budget, a stream of Bluestein-length
+    and matrix-core requests (each charged its own workspace) never needs more: every request
+    completes and equals its single-pulse calls on an unbounded context."""
+    import paper_2508_04951_amd as rc
+
+    budget = 96 << 20
+    c = rc.Context(0)
+    c.set_mem_budget(budget)
+    ref_ctx = rc.Context(0)
+    k = rc.Sinc(64, "kaiser", 8.0)
+    srv = rc.Server(c, k, mem_budget_bytes=budget, max_batch=8)
+    rng = wf.rng_for(305, 0)
+    lens = [300001, 70001, 1 << 20, 12345, 500000, 1 << 18, 262143, 99999, 700001, 4097] * 2
+    done = []
+    pending = []
+    for i, n in enumerate(lens):
+        r = dict(n=n, n_out=n, alpha=alpha_exact(rng.uniform(-8000, 8000)), tec=rng.uniform(5, 100) * wf.TECU,
+                 flags=rc.DO_DOPPLER | rc.DO_IONO, direction="correct")
+        x = dev(torch, wf.bandlimited_noise(n, wf.rng_for(305, i + 1)))
+        y = torch.empty_like(x)
+        while True:
+            try:
+                t = srv.submit(x, y, alpha=r["alpha"], tec=r["tec"], carrier=450e6, fs=10e6, flags=r["flags"])
+                break
+            except rc.RcError as e:
+                assert e.status == 5, e  # only RC_ERR_BUSY: wait for the oldest and retry
+                srv.wait(pending.pop(0)[0])
+        pending.append((t, r, x, y))
+        done.append((r, x, y))
+    srv.wait()
+    srv.close()
+    for r, x, y in done:
+        assert np.array_equal(y.cpu().numpy(), alone(torch, ref_ctx, x, r, k)), r["n"]
+
+
+def test_server_reads_x_after_the_submitting_stream(torch, ctx):
+    """x is produced on a side stream and submitted without a host synchronisation: the request
+    waits for that stream's work, so it sees the finished x."""
+    import paper_2508_04951_amd as rc
+
+    n = 1 << 20
+    xh = wf.bandlimited_noise(n, wf.rng_for(306, 0))
+    src = dev(torch, xh)
+    k = rc.Sinc(64, "kaiser", 8.0)
+    srv = rc.Server(ctx, k, mem_budget_bytes=1 << 32, max_batch=4)
+    side = torch.cuda.Stream()
+    outs = []
+    for i in range(4):
+        x = torch.zeros(n, dtype=torch.complex64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            for _ in range(20):  # a queue of work ahead of the copy that fills x
+                torch.mul(src, 1.0, out=y)
+            x.copy_(src)
+            t = srv.submit(x, y, alpha=alpha_exact(1500.0 * i), tec=30 * wf.TECU, carrier=450e6, fs=10e6)
+        outs.append((t, i, x, y))
+    srv.wait()
+    srv.close()
+    r = dict(n_out=n, flags=rc.DO_DOPPLER | rc.DO_IONO, direction="correct", tec=30 * wf.TECU)
+    for t, i, x, y in outs:
+        rr = dict(r, alpha=alpha_exact(1500.0 * i))
+        assert np.array_equal(y.cpu().numpy(), alone(torch, ctx, src, rr, k)), i
