@@ -502,6 +502,28 @@ __device__ __forceinline__ float2 phase_at(const PhaseK &P, int64_t kk)
     return (quad & 2) ? make_float2(-c, -sn) : make_float2(c, sn);
 }
 
+// phase_at without xprec, in fewer instructions and with the same result: |n4| < 2^26 there,
+// so n4 converts to int exactly and its two low bits are n4 mod 4; the quarter turns are applied
+// by swapping (bit 0) and by flipping both signs (bit 1); f == 0 is selected, not branched to.
+__device__ __forceinline__ float2 phase_fast(const PhaseK &P, int kk)
+{
+    const double f = fma(P.fs_n, (double)kk, P.carrier);
+    double rf = __builtin_amdgcn_rcp(f);
+    rf = fma(rf, fma(-f, rf, 1.0), rf);
+    double t4 = P.c4 * rf;
+    t4 = fma(fma(-t4, f, P.c4), rf, t4);
+    const double n4 = rint(t4);
+    const float2 w = cis_quarter((float)(t4 - n4));
+    const int quad = (int)n4;
+    const bool odd = quad & 1;
+    const unsigned flip = ((unsigned)quad & 2u) << 30;  // sign bit when quad & 2
+    float c = odd ? -w.y : w.x;
+    float sn = odd ? w.x : w.y;
+    c = __uint_as_float(__float_as_uint(c) ^ flip);
+    sn = __uint_as_float(__float_as_uint(sn) ^ flip);
+    return f == 0.0 ? make_float2(1.f, 0.f) : make_float2(c, sn);
+}
+
 __device__ __forceinline__ float2 iono_phase(const IonoJob &jb, int64_t k, int64_t n)
 {
     const int64_t kk = (k < (n + 1) / 2) ? k : k - n;
@@ -596,11 +618,17 @@ __device__ __forceinline__ float2 row_phase(const PhaseK &pk, int kout, int mult
     return phase_at(pk, k < (n + 1) / 2 ? k : k - n);
 }
 
+__device__ __forceinline__ float2 row_phase_fast(const PhaseK &pk, int kout, int mult, int l, int n)
+{
+    const int k = kout + mult * l;
+    return phase_fast(pk, k < (n + 1) / 2 ? k : k - n);
+}
+
 // Contiguous level of 4096 points, one row per block: forward DFT, the per-bin factor, inverse
 // DFT.  F selects the factor (see RowFactor).  The correlation variant holds the table across the
 // forward transform and evaluates the phases after it: it needs more than 128 registers, so it
-// runs at three blocks per CU instead of four.
-template <int F>
+// runs at three blocks per CU instead of four.  Scaled: the outputs take a.scale (not 1).
+template <int F, bool Scaled>
 __global__ void __launch_bounds__(kFftThreads, F == kRowTablePhase ? 3 : 4) k_fft_row4096_iono(RowArgs a)
 {
     __shared__ float2 lds[kLdsSlots];
@@ -637,9 +665,15 @@ __global__ void __launch_bounds__(kFftThreads, F == kRowTablePhase ? 3 : 4) k_ff
             int kout, mult;
             row_bin_origin(a, r, kout, mult);
             const PhaseK pk = phase_consts(jb, a.n);
+            if (pk.xprec) {  // uniform over the workgroup
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-                ph[q] = row_phase(pk, kout, mult, j + 256 * q, (int)a.n);
+                for (int q = 0; q < 16; ++q)
+                    ph[q] = row_phase(pk, kout, mult, j + 256 * q, (int)a.n);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    ph[q] = row_phase_fast(pk, kout, mult, j + 256 * q, (int)a.n);
+            }
         }
     }
     row4096<-1>(v, lds, j, b2, b3);
@@ -647,7 +681,7 @@ __global__ void __launch_bounds__(kFftThreads, F == kRowTablePhase ? 3 : 4) k_ff
         const auto dst = gmem(jb.y) + (r << 12);
 #pragma unroll
         for (int q = 0; q < 16; ++q)
-            dst[j + 256 * q] = make_float2(v[q].x * a.scale, v[q].y * a.scale);
+            dst[j + 256 * q] = Scaled ? make_float2(v[q].x * a.scale, v[q].y * a.scale) : v[q];
         return;  // uniform over the workgroup
     }
     if constexpr (F == kRowTablePhase) {
@@ -676,7 +710,7 @@ __global__ void __launch_bounds__(kFftThreads, F == kRowTablePhase ? 3 : 4) k_ff
     row4096<+1>(v, lds, j, b2, b3);
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-        store_nt(jb.y + (r << 12) + j + 256 * q, make_float2(v[q].x * a.scale, v[q].y * a.scale));
+        store_nt(jb.y + (r << 12) + j + 256 * q, Scaled ? make_float2(v[q].x * a.scale, v[q].y * a.scale) : v[q]);
 }
 
 // Single-level transform of n = L < 4096 points: the tile holds C = 4096/L whole pulses.
@@ -917,12 +951,16 @@ hipError_t launch_fft_impl(const FftPlan &plan, const float2 *tw4096, const Iono
             const int64_t blocks = (int64_t)njobs << a.log2rpp;
             if (blocks > 0x7fffffff)
                 return hipErrorInvalidValue;
-            if (factor == kRowTablePhase)
-                hipLaunchKernelGGL(k_fft_row4096_iono<kRowTablePhase>, dim3((unsigned)blocks), dim3(kFftThreads), 0,
-                                   s, a);
+            const dim3 grid((unsigned)blocks);
+            const bool scaled = a.scale != 1.0f;
+            if (factor == kRowTablePhase && scaled)
+                hipLaunchKernelGGL((k_fft_row4096_iono<kRowTablePhase, true>), grid, dim3(kFftThreads), 0, s, a);
+            else if (factor == kRowTablePhase)
+                hipLaunchKernelGGL((k_fft_row4096_iono<kRowTablePhase, false>), grid, dim3(kFftThreads), 0, s, a);
+            else if (scaled)
+                hipLaunchKernelGGL((k_fft_row4096_iono<kRowPhaseOrTable, true>), grid, dim3(kFftThreads), 0, s, a);
             else
-                hipLaunchKernelGGL(k_fft_row4096_iono<kRowPhaseOrTable>, dim3((unsigned)blocks), dim3(kFftThreads), 0,
-                                   s, a);
+                hipLaunchKernelGGL((k_fft_row4096_iono<kRowPhaseOrTable, false>), grid, dim3(kFftThreads), 0, s, a);
         } else {
             const int64_t blocks = ((int64_t)njobs + (1 << a.log2C) - 1) >> a.log2C;
             hipLaunchKernelGGL(k_fft_rows_iono, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, a);

@@ -45,6 +45,7 @@ __device__ __forceinline__ half2v pkrtz(float a, float b)
 }
 
 constexpr int kMfOut = kSincMfmaTile;  // outputs per tile (one phase-grid point)
+constexpr int kSubTile = 256;          // outputs of one 16 x 16 matrix-core product
 constexpr int kMfOrders = 5;           // quartic in the drift
 constexpr int kMfLo = 2;               // orders that also take the hi*lo and lo*hi products
 constexpr int kMfBlk = kMfOrders + kMfLo;  // 1 KiB B fragments per 32-tap step
@@ -60,18 +61,23 @@ struct MfGeom {
     static constexpr int ntap = 2 * H + 1;
     static constexpr int kext = ((2 * H + 16) + 31) / 32 * 32;
     static constexpr int ksteps = kext / 32;
-    static constexpr int span = kMfOut + kext;                 // staged samples
-    static constexpr int spp = (span + 511) / 512;            // staged sample pairs per thread
+    static constexpr int wout = 2 * kSubTile;                  // outputs per wave and tile
+    static constexpr int wspan = wout + kext;                  // samples staged per wave
+    static constexpr int wpp = (wspan + 127) / 128;            // staged sample pairs per lane
     static constexpr int rowlen = kext + 32;                   // padded coefficient row (halves)
     static constexpr int node_iters = (ntap + 47) / 48;       // 12 taps x 5 nodes per wave
     static constexpr int bbytes = ksteps * kMfBlk * 1024;  // B fragments of one phase
-    // main kernel LDS: B block, then 4 fp16 arrays of `span`, then 4 floats (wave maxima)
+    // main kernel LDS: B block, then per wave 4 fp16 arrays of `wspan` (re hi, re lo, im hi,
+    // im lo; 64-byte multiples, so every region stays 16-byte aligned)
     static constexpr int a_off = bbytes;
-    static constexpr int m_off = a_off + ((4 * span * 2) + 15) / 16 * 16;
-    static constexpr int bytes = m_off + 16;
+    static constexpr int a_wave = 4 * wspan;                   // halves per wave region
+    static constexpr int bytes = a_off + 4 * a_wave * 2;
     // table kernel LDS: coefficient rows [order][part][rowlen]
     static constexpr int rows_bytes = kMfOrders * 2 * rowlen * 2;
 };
+
+static_assert(4 * 2 * kSubTile == kMfOut, "four waves of two sub-tiles cover a tile");
+static_assert(MfGeom<64>::wspan % 32 == 0 && MfGeom<128>::wspan % 32 == 0, "wave regions stay aligned");
 
 // The Kaiser series with a fixed number of terms NT >= kp.n (terms past kp.n are zero).
 constexpr int kMfKaiserTerms = 32;
@@ -251,6 +257,10 @@ k_mf_tile_scatter(const uint2 *__restrict__ ref, const unsigned char *__restrict
 // The resampling GEMM.  Without a list, workgroup (x, y) computes tile x of job y.  With a list,
 // the grid is persistent: workgroup b takes the run c(b) of the sorted list, where c deals
 // consecutive b to different XCDs so that an XCD holds a contiguous range of phases.
+//
+// Wave w of a group of four owns outputs 512 w .. 512 w + 511 of the group's tile (sub-tiles 2w
+// and 2w + 1) and stages the input they read, wspan = 512 + kext samples, into an LDS region of
+// its own with a scale of its own: the waves share only the phase's B block.
 // A tile of the persistent loop: its job, first output and position in the input.
 struct MfCur {
     SincJob jb;
@@ -258,59 +268,112 @@ struct MfCur {
     MfTile tp;
 };
 
-template <int H>
-__global__ void __launch_bounds__(256, 2)
-k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restrict__ list, int64_t ntiles,
-            const unsigned char *__restrict__ table)
+// Largest of a non-negative float over the wave, uniform: the bit patterns of non-negative
+// floats order like their values, so the maximum is taken on them, within each row of 16 lanes
+// by DPP moves (quad permutations, then rotations by 4 and 8), then over the rows' first lanes.
+__device__ __forceinline__ float wave_max_nonneg(float v)
+{
+    int u = __float_as_int(v);
+    u = max(u, __builtin_amdgcn_update_dpp(0, u, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    u = max(u, __builtin_amdgcn_update_dpp(0, u, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    u = max(u, __builtin_amdgcn_update_dpp(0, u, 0x124, 0xF, 0xF, false));  // row_ror:4
+    u = max(u, __builtin_amdgcn_update_dpp(0, u, 0x128, 0xF, 0xF, false));  // row_ror:8
+    const int a = max(__builtin_amdgcn_readlane(u, 0), __builtin_amdgcn_readlane(u, 16));
+    const int b = max(__builtin_amdgcn_readlane(u, 32), __builtin_amdgcn_readlane(u, 48));
+    return __int_as_float(max(a, b));
+}
+
+// A wave-uniform 64-bit integer held in scalar registers (the value of the first active lane).
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Orders memory operations of one wave on LDS: what its lanes stored before is what its lanes
+// load after.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Tile i of the sorted list.
+__device__ __forceinline__ MfCur mf_list_tile(const SincJob *__restrict__ jobs, const uint2 *__restrict__ list,
+                                              int64_t i)
+{
+    const uint2 e = gload(list, i);
+    MfCur t;
+    t.jb = gload(jobs, e.x);
+    t.M0 = (int64_t)e.y * kMfOut;
+    t.tp = mf_tile(t.jb.alpha, t.M0);
+    return t;
+}
+
+// Phase p's B fragments into LDS, by the whole workgroup (NT threads), four 16-byte loads in
+// flight per thread; the caller brackets it with barriers.  Indices past the block are clamped
+// to its last element, which is then copied more than once with the same value: no branches,
+// so every load is complete when the copy ends.
+template <int H, int NT>
+__device__ __forceinline__ void mf_load_b(const unsigned char *__restrict__ table, int p, unsigned char *bsm,
+                                          int tid)
 {
     using G = MfGeom<H>;
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    unsigned char *bsm = smem;
-    _Float16 *a_rh = reinterpret_cast<_Float16 *>(smem + G::a_off);
-    _Float16 *a_rl = a_rh + G::span;
-    _Float16 *a_ih = a_rl + G::span;
-    _Float16 *a_il = a_ih + G::span;
-    float *wmax = reinterpret_cast<float *>(smem + G::m_off);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-
-    int64_t i0 = 0, i1 = 1;
-    if (list) {
-        const int64_t g = gridDim.x, b = blockIdx.x;
-        const int64_t c = g % kXcds == 0 ? (b % kXcds) * (g / kXcds) + b / kXcds : b;
-        i0 = c * ntiles / g;
-        i1 = (c + 1) * ntiles / g;
-        if (i0 >= i1)
-            return;  // uniform over the workgroup
+    const auto src = gmem(reinterpret_cast<const uint4 *>(table + (size_t)(p + kPhases / 2) * G::bbytes));
+    uint4 *dst = reinterpret_cast<uint4 *>(bsm);
+    constexpr int n16 = G::bbytes / 16;
+#pragma unroll 1
+    for (int k = tid; k < n16; k += 4 * NT) {
+        const int k1 = k + NT < n16 ? k + NT : n16 - 1;
+        const int k2 = k + 2 * NT < n16 ? k + 2 * NT : n16 - 1;
+        const int k3 = k + 3 * NT < n16 ? k + 3 * NT : n16 - 1;
+        const uint4 v0 = src[k], v1 = src[k1], v2 = src[k2], v3 = src[k3];
+        dst[k] = v0;
+        dst[k1] = v1;
+        dst[k2] = v2;
+        dst[k3] = v3;
     }
-    auto tile_at = [&](int64_t i) {
-        MfCur t;
-        if (list) {
-            const uint2 e = gload(list, i);
-            t.jb = gload(jobs, e.x);
-            t.M0 = (int64_t)e.y * kMfOut;
-        } else {
-            t.jb = jobs ? gload(jobs, blockIdx.y) : inl;
-            t.M0 = (int64_t)blockIdx.x * kMfOut;
-        }
-        t.tp = mf_tile(t.jb.alpha, t.M0);
-        return t;
-    };
+}
 
-    // The input span of a tile, samples lo .. lo + span - 1, is fetched into registers (two
-    // per thread and step) one tile ahead.
-    float2 xv[G::spp][2];
-    auto fetch = [&](const MfCur &t) {
-        const int64_t lo = t.M0 + (int64_t)t.tp.Sd - H;
-        if (lo >= 0 && lo + G::span <= t.jb.n_in) {
+// One wave's part of a tile: the fetch of its input span into registers, the staging into its
+// LDS region, the matrix products and the stores.
+template <int H>
+struct MfWave {
+    using G = MfGeom<H>;
+    const unsigned char *bsm;        // the phase's B block
+    _Float16 *a_rh, *a_rl, *a_ih, *a_il;  // this wave's region: re hi, re lo, im hi, im lo
+    int lane, wbase;                 // wbase: this wave's first output in a tile
+    float2 xv[G::wpp][2];            // the fetched span, two samples per lane and step
+    floatx4 acc[2][kMfOrders][2];    // Z_r of the two sub-tiles, re and im
+
+    __device__ __forceinline__ MfWave(unsigned char *smem, int region, int lane_, int wbase_)
+        : bsm(smem), lane(lane_), wbase(wbase_)
+    {
+        a_rh = reinterpret_cast<_Float16 *>(smem + G::a_off) + region * G::a_wave;
+        a_rl = a_rh + G::wspan;
+        a_ih = a_rl + G::wspan;
+        a_il = a_ih + G::wspan;
+    }
+
+    // this wave has outputs in tile t (uniform over the wave)
+    __device__ __forceinline__ bool active(const MfCur &t) const { return t.M0 + wbase < t.jb.n_out; }
+
+    // samples lo .. lo + wspan - 1 of the input, two per lane and step
+    __device__ __forceinline__ void fetch(const MfCur &t)
+    {
+        const int64_t lo = uniform64(t.M0 + (int64_t)t.tp.Sd - H + wbase);
+        if (lo >= 0 && lo + G::wspan <= t.jb.n_in) {
             // the whole span lies inside x (the usual case; uniform): 32-bit offsets from its start
             const auto xs = gmem(t.jb.x) + lo;
 #pragma unroll
-            for (int q = 0; q < G::spp; ++q) {
+            for (int q = 0; q < G::wpp; ++q) {
 #pragma unroll
                 for (int h2 = 0; h2 < 2; ++h2) {
-                    const int e = 2 * tid + 512 * q + h2;
-                    const float2 v = xs[e < G::span ? e : G::span - 1];
-                    xv[q][h2] = e < G::span ? v : make_float2(0.f, 0.f);
+                    const int e = 2 * lane + 128 * q + h2;
+                    const float2 v = xs[e < G::wspan ? e : G::wspan - 1];
+                    xv[q][h2] = e < G::wspan ? v : make_float2(0.f, 0.f);
                 }
             }
             return;
@@ -320,83 +383,42 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
         // every lane loads an in-bounds sample (index clamped) and zeroes what lies outside x
         // or past the span: no branch between the loads
 #pragma unroll
-        for (int q = 0; q < G::spp; ++q) {
+        for (int q = 0; q < G::wpp; ++q) {
 #pragma unroll
             for (int h2 = 0; h2 < 2; ++h2) {
-                const int e = 2 * tid + 512 * q + h2;
+                const int e = 2 * lane + 128 * q + h2;
                 const int64_t g = lo + e;
-                const bool ok = e < G::span && g >= 0 && g <= last;
+                const bool ok = e < G::wspan && g >= 0 && g <= last;
                 const int64_t gc = g < 0 ? 0 : (g > last ? last : g);
                 const float2 v = xs[gc];
                 xv[q][h2] = ok ? v : make_float2(0.f, 0.f);
             }
         }
-    };
+    }
 
-    // Staging of the fetched span into LDS for phase p; returns the scale exponent.  Every wave
-    // must be done with the LDS operands of the previous tile (the barrier inside ensures it
-    // before anything is overwritten).
-    int cur_p = kPhaseRows;  // no B block in LDS yet
-    auto stage = [&](int p) {
-        // largest component of the span
+    // The fetched span into this wave's region, scaled by a power of two (largest component in
+    // [2^10, 2^11)) and split into fp16 hi/lo; returns the scale exponent.
+    __device__ __forceinline__ int stage()
+    {
         float mx = 0.f;
 #pragma unroll
-        for (int q = 0; q < G::spp; ++q)
+        for (int q = 0; q < G::wpp; ++q)
 #pragma unroll
             for (int h2 = 0; h2 < 2; ++h2)
                 mx = fmaxf(mx, fmaxf(fabsf(xv[q][h2].x), fabsf(xv[q][h2].y)));
-        for (int o = 32; o > 0; o >>= 1)
-            mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-        if (lane == 0)
-            wmax[wave] = mx;
-        __syncthreads();
-        // this phase's B fragments, unless they are in LDS already (uniform branch); the loads
-        // of a round are all issued before the first is waited for
-        if (p != cur_p) {
-            const auto src = gmem(reinterpret_cast<const uint4 *>(table + (size_t)(p + kPhases / 2) * G::bbytes));
-            uint4 *dst = reinterpret_cast<uint4 *>(bsm);
-            constexpr int n16 = G::bbytes / 16, per = 8, full = n16 / (per * 256);
-            constexpr int tail = (n16 - full * per * 256 + 255) / 256;
-#pragma unroll 1
-            for (int k0 = 0; k0 < full * per * 256; k0 += per * 256) {
-                uint4 v[per];
-#pragma unroll
-                for (int u = 0; u < per; ++u)
-                    v[u] = src[k0 + u * 256 + tid];
-#pragma unroll
-                for (int u = 0; u < per; ++u)
-                    dst[k0 + u * 256 + tid] = v[u];
-            }
-            if (tail > 0) {
-                constexpr int k0 = full * per * 256;
-                uint4 v[tail > 0 ? tail : 1];
-#pragma unroll
-                for (int u = 0; u < tail; ++u) {
-                    const int k = k0 + u * 256 + tid;
-                    v[u] = src[k < n16 ? k : n16 - 1];
-                }
-#pragma unroll
-                for (int u = 0; u < tail; ++u) {
-                    const int k = k0 + u * 256 + tid;
-                    if (k < n16)
-                        dst[k] = v[u];
-                }
-            }
-            cur_p = p;
-        }
-        // scale by a power of two (largest component in [2^10, 2^11)), split into fp16 hi/lo
-        const float wm = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        mx = wave_max_nonneg(mx);
         int xe = 0;
-        if (wm > 0.f) {
+        if (mx > 0.f) {
             int E;
-            frexpf(wm, &E);  // wm = f 2^E, f in [0.5, 1)
+            frexpf(mx, &E);  // mx = f 2^E, f in [0.5, 1)
             xe = 11 - E;
         }
         const float xs2 = ldexpf(1.0f, xe);
+        wave_lds_sync();  // this wave's loads of the previous tile's operands come first
 #pragma unroll
-        for (int q = 0; q < G::spp; ++q) {
-            const int e = 2 * tid + 512 * q;
-            if (e < G::span) {  // span is even: a pair is either wholly inside or outside
+        for (int q = 0; q < G::wpp; ++q) {
+            const int e = 2 * lane + 128 * q;
+            if (e < G::wspan) {  // wspan is even: a pair is either wholly inside or outside
                 // hi rounds toward zero (one packed conversion per pair); the residual x - hi is
                 // exact in float32 and becomes lo
                 const float r0 = xv[q][0].x * xs2, r1 = xv[q][1].x * xs2;
@@ -411,162 +433,222 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
                 *reinterpret_cast<half2v *>(a_il + e) = il;
             }
         }
+        wave_lds_sync();  // and its lanes' stores are seen by its lanes' fragment loads
         return xe;
+    }
+
+    // The matrix products of the staged span with the B block.  The wave runs its two sub-tiles
+    // together: each B fragment is read from LDS once per 32-tap step for both.  A fragments:
+    // lane (i, q) = (l % 16, l / 16) holds the 8 samples at 16 i + 8 q + 32 s of its sub-tile's
+    // span (aligned 8-sample runs of the Hankel matrix).
+    __device__ __forceinline__ void gemm()
+    {
+        const int arow = 16 * (lane & 15) + 8 * (lane >> 4);
+        // step s of the contraction; the first step starts every accumulator from zero (the
+        // matrix core's inline constant), so nothing is cleared beforehand
+        auto kstep = [&](int s, bool first) {
+            half8 xh[2][2], xl[2][2];  // [sub-tile][re/im]
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int e = arow + kSubTile * t + 32 * s;
+                xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
+                xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
+                xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
+                xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
+            }
+            const half8 *blk = reinterpret_cast<const half8 *>(bsm + s * kMfBlk * 1024);
+            half8 bh[kMfOrders], bl[kMfLo];
+#pragma unroll
+            for (int r = 0; r < kMfOrders; ++r)
+                bh[r] = blk[64 * r + lane];
+#pragma unroll
+            for (int r = 0; r < kMfLo; ++r)
+                bl[r] = blk[64 * (kMfOrders + r) + lane];
+            // hi*hi for every order, then hi*lo and lo*hi for the low orders: at least eight
+            // independent products between two that update the same accumulator
+#pragma unroll
+            for (int r = 0; r < kMfOrders; ++r)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2)
+                        acc[t][r][c2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                            xh[t][c2], bh[r], first ? floatx4{0.f, 0.f, 0.f, 0.f} : acc[t][r][c2], 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < kMfLo; ++r)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2)
+                        acc[t][r][c2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh[t][c2], bl[r], acc[t][r][c2], 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < kMfLo; ++r)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2)
+                        acc[t][r][c2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl[t][c2], bh[r], acc[t][r][c2], 0, 0, 0);
+        };
+        kstep(0, true);
+        // not unrolled: hoisting the next step's fragments would cost the second wave per SIMD
+#pragma unroll 1
+        for (int s = 1; s < G::ksteps; ++s)
+            kstep(s, false);
+    }
+
+    // Lane holds Z_r[row 4 (l/16) + j][col l % 16] of each sub-tile: output
+    // m = M0 + wbase + 256 t + 16 row + col.  z is linear in m.  Outputs next to an exact sample
+    // instant (sigma within 1e-5 of 0), where alpha m may round to an integer, are checked in
+    // float64 and, if exact, rewritten with the input sample after all stores are issued (a load
+    // between the stores would make each store wait).
+    __device__ __forceinline__ void store(const MfCur &c, int xe)
+    {
+        const double alpha = c.jb.alpha, eps = alpha - 1.0;
+        const int64_t S = (int64_t)c.tp.Sd;
+        const float unscale = ldexpf(1.0f, -(xe + kCoefExp));
+        // z_m = (sigma_m - sigma_p) / delta_max = z_c + (m - mcen) eps / delta_max
+        const float zc = (float)((c.tp.sc - (double)c.tp.p * (1.0 / kPhases)) * (1.0 / kDeltaMax));
+        const float zstep = (float)(eps * (1.0 / kDeltaMax));
+        const float sc32 = (float)c.tp.sc;
+        const float e32 = (float)eps;
+        const auto yt = gmem(c.jb.y) + c.M0;  // this tile's first output
+        const bool full = c.M0 + kMfOut <= c.jb.n_out;  // uniform
+        const int nvalid = full ? kMfOut : (int)(c.jb.n_out - c.M0);
+        // sigma runs over sc +- |eps| 1023.5 in this tile: only if that range comes within 1e-5
+        // of 0 can an output sit on an exact sample instant (uniform)
+        const bool may_hit = fabs(c.tp.sc) <= fabs(eps) * kMfHalf + 2e-5;
+        // output (t, j) of this lane is m - M0 = loff + 256 t + 16 j
+        const int loff = wbase + 64 * (lane >> 4) + (lane & 15);
+        const float dml = (float)loff - (float)kMfHalf;  // m - mcen, exact like every sum below
+        auto poly = [&](int t, int j, float z) {
+            float yr = acc[t][kMfOrders - 1][0][j], yi = acc[t][kMfOrders - 1][1][j];
+#pragma unroll
+            for (int r = kMfOrders - 2; r >= 0; --r) {
+                yr = fmaf(yr, z, acc[t][r][0][j]);
+                yi = fmaf(yi, z, acc[t][r][1][j]);
+            }
+            return make_float2(yr * unscale, yi * unscale);
+        };
+        float2 *const yl = c.jb.y + c.M0 + loff;
+        unsigned near = 0;  // bit 4 t + j: output (t, j) is next to an exact instant
+        if (full && !may_hit) {
+            // the usual tile (uniform): no output to check, constant offsets from the lane's first
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float dm = dml + (float)(kSubTile * t + 16 * j);
+                    store_nt(yl + kSubTile * t + 16 * j, poly(t, j, fmaf(dm, zstep, zc)));
+                }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (!full && loff + kSubTile * t + 16 * j >= nvalid)
+                        continue;
+                    const float dm = dml + (float)(kSubTile * t + 16 * j);
+                    if (may_hit && fabsf(fmaf(dm, e32, sc32)) < 1e-5f)
+                        near |= 1u << (4 * t + j);
+                    store_nt(yl + kSubTile * t + 16 * j, poly(t, j, fmaf(dm, zstep, zc)));
+                }
+            }
+        }
+        if (__any(near != 0)) {  // rare: uniform over the wave
+            const auto xg = gmem(c.jb.x);
+#pragma unroll 1
+            for (int b = 0; b < 8; ++b) {
+                if (!((near >> b) & 1u))
+                    continue;
+                const int t = b >> 2, j = b & 3;
+                const int off = loff + kSubTile * t + 16 * j;
+                const int64_t m = c.M0 + off;
+                const double md = (double)m;
+                if (((__dmul_rn(alpha, md) - md) - c.tp.Sd) == 0.0) {
+                    const int64_t src = m + S;
+                    float2 v = make_float2(0.f, 0.f);
+                    if (src >= 0 && src < c.jb.n_in)
+                        v = xg[src];
+                    yt[off] = v;
+                }
+            }
+        }
+    }
+};
+
+// Four waves, one tile at a time: the tiles of a list run (persistent grid, two workgroups per
+// CU), or without a list tile blockIdx.x of job blockIdx.y.  Per tile: the matrix products, then
+// the staging of the next tile's span (its loads were issued a tile ahead, before this wave's
+// previous stores) and the fetch of the one after, then this tile's stores.  The waves wait for
+// each other only when the phase changes.
+template <int H>
+__global__ void __launch_bounds__(256, 2)
+k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restrict__ list, int64_t ntiles,
+            const unsigned char *__restrict__ table)
+{
+    using G = MfGeom<H>;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    MfWave<H> W(smem, wave, lane, G::wout * wave);
+
+    int64_t i0 = 0, i1 = 1;
+    if (list) {
+        const int64_t g = gridDim.x, b = blockIdx.x;
+        const int64_t c = g % kXcds == 0 ? (b % kXcds) * (g / kXcds) + b / kXcds : b;
+        i0 = c * ntiles / g;
+        i1 = (c + 1) * ntiles / g;
+        if (i0 >= i1)
+            return;  // uniform over the workgroup
+    }
+    auto tile_at = [&](int64_t i) {
+        if (list)
+            return mf_list_tile(jobs, list, i);
+        MfCur t;
+        t.jb = jobs ? gload(jobs, blockIdx.y) : inl;
+        t.M0 = (int64_t)blockIdx.x * kMfOut;
+        t.tp = mf_tile(t.jb.alpha, t.M0);
+        return t;
     };
 
     MfCur cur = tile_at(i0);
     if (cur.M0 >= cur.jb.n_out)
         return;  // only without a list (ragged jobs); uniform over the workgroup
-    fetch(cur);
-    int xe = stage(cur.tp.p);
+    int cur_p = cur.tp.p;
+    mf_load_b<H, 256>(table, cur_p, smem, tid);
+    if (W.active(cur))
+        W.fetch(cur);
+    int xe = W.active(cur) ? W.stage() : 0;
     MfCur nxt = cur;
     if (i0 + 1 < i1) {
         nxt = tile_at(i0 + 1);
-        fetch(nxt);
+        if (W.active(nxt))
+            W.fetch(nxt);
     }
-    __syncthreads();  // the first tile's A and B are in LDS
+    __syncthreads();  // the first phase's B block is in LDS
 
-    // Per tile: the matrix products, then the next tile's staging and the fetch of the one after
-    // (its loads are issued before this tile's stores, and both are waited for only after the
-    // next tile's products), then this tile's stores.
     for (int64_t i = i0; i < i1; ++i) {
-        const bool active = cur.M0 + 256 * wave < cur.jb.n_out;  // uniform over the wave
-        floatx4 acc[2][kMfOrders][2];
-
-        // 1) the GEMM.  Wave w owns sub-tiles w and w + 4 and runs them together: each B
-        //    fragment is read from LDS once per 32-tap step for both.
-        if (active) {
-            // A fragments: lane (i, q) = (l % 16, l / 16) holds the 8 samples at
-            // 16 i + 8 q + 32 s of its sub-tile's span (aligned 8-sample runs of the Hankel matrix)
-            const int arow = 256 * wave + 16 * (lane & 15) + 8 * (lane >> 4);
-            // step s of the contraction; the first step starts every accumulator from zero (the
-            // matrix core's inline constant), so nothing is cleared beforehand
-            auto kstep = [&](int s, bool first) {
-                half8 xh[2][2], xl[2][2];  // [sub-tile][re/im]
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int e = arow + 1024 * t + 32 * s;
-                    xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
-                    xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
-                    xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
-                    xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
-                }
-                const half8 *blk = reinterpret_cast<const half8 *>(bsm + s * kMfBlk * 1024);
-                half8 bh[kMfOrders], bl[kMfLo];
-#pragma unroll
-                for (int r = 0; r < kMfOrders; ++r)
-                    bh[r] = blk[64 * r + lane];
-#pragma unroll
-                for (int r = 0; r < kMfLo; ++r)
-                    bl[r] = blk[64 * (kMfOrders + r) + lane];
-                // hi*hi for every order, then hi*lo and lo*hi for the low orders: at least eight
-                // independent products between two that update the same accumulator
-#pragma unroll
-                for (int r = 0; r < kMfOrders; ++r)
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-#pragma unroll
-                        for (int c = 0; c < 2; ++c)
-                            acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                                xh[t][c], bh[r], first ? floatx4{0.f, 0.f, 0.f, 0.f} : acc[t][r][c], 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < kMfLo; ++r)
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-#pragma unroll
-                        for (int c = 0; c < 2; ++c)
-                            acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh[t][c], bl[r], acc[t][r][c], 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < kMfLo; ++r)
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-#pragma unroll
-                        for (int c = 0; c < 2; ++c)
-                            acc[t][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl[t][c], bh[r], acc[t][r][c], 0, 0, 0);
-            };
-            kstep(0, true);
-            // not unrolled: hoisting the next step's fragments would cost the second wave per SIMD
-#pragma unroll 1
-            for (int s = 1; s < G::ksteps; ++s)
-                kstep(s, false);
+        if (cur.tp.p != cur_p) {  // uniform over the workgroup: every wave walks the same run
+            __syncthreads();      // every wave is done with the previous block
+            mf_load_b<H, 256>(table, cur.tp.p, smem, tid);
+            cur_p = cur.tp.p;
+            __syncthreads();
         }
-
-        // 2) the next tile into LDS (after every wave's products: the barrier in stage), and the
-        //    fetch of the tile after it
-        const int cxe = xe;
         const MfCur c = cur;
+        const int cxe = xe;
+        const bool active = W.active(c);
+        if (active)
+            W.gemm();
         if (i + 1 < i1) {
-            xe = stage(nxt.tp.p);
             cur = nxt;
+            xe = W.active(cur) ? W.stage() : 0;
             if (i + 2 < i1) {
                 nxt = tile_at(i + 2);
-                fetch(nxt);
+                if (W.active(nxt))
+                    W.fetch(nxt);
             }
         }
-
-        // 3) lane holds Z_r[row 4 (l/16) + j][col l % 16] of each sub-tile: output
-        //    m = M0 + 256 sub + 16 row + col.  z is linear in m.  Outputs next to an exact
-        //    sample instant (sigma within 1e-5 of 0), where alpha m may round to an integer,
-        //    are checked in float64 and, if exact, rewritten with the input sample after all
-        //    stores are issued (a load between the stores would make each store wait).
-        if (active) {
-            const double alpha = c.jb.alpha, eps = alpha - 1.0;
-            const int64_t S = (int64_t)c.tp.Sd;
-            const float unscale = ldexpf(1.0f, -(cxe + kCoefExp));
-            // z_m = (sigma_m - sigma_p) / delta_max = z_c + (m - mcen) eps / delta_max
-            const float zc = (float)((c.tp.sc - (double)c.tp.p * (1.0 / kPhases)) * (1.0 / kDeltaMax));
-            const float zstep = (float)(eps * (1.0 / kDeltaMax));
-            const float sc32 = (float)c.tp.sc;
-            const float e32 = (float)eps;
-            const auto yt = gmem(c.jb.y) + c.M0;  // this tile's first output
-            const bool full = c.M0 + kMfOut <= c.jb.n_out;  // uniform
-            const int nvalid = full ? kMfOut : (int)(c.jb.n_out - c.M0);
-            // sigma runs over sc +- |eps| 1023.5 in this tile: only if that range comes within 1e-5
-            // of 0 can an output sit on an exact sample instant (uniform)
-            const bool may_hit = fabs(c.tp.sc) <= fabs(eps) * kMfHalf + 2e-5;
-            unsigned near = 0;  // bit 4 t + j: output (t, j) is next to an exact instant
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int off = 256 * (wave + 4 * t) + 16 * (4 * (lane >> 4) + j) + (lane & 15);  // m - M0
-                    if (!full && off >= nvalid)
-                        continue;
-                    const float dm = (float)off - (float)kMfHalf;
-                    const float z = fmaf(dm, zstep, zc);
-                    if (may_hit && fabsf(fmaf(dm, e32, sc32)) < 1e-5f)
-                        near |= 1u << (4 * t + j);
-                    float yr = acc[t][kMfOrders - 1][0][j], yi = acc[t][kMfOrders - 1][1][j];
-#pragma unroll
-                    for (int r = kMfOrders - 2; r >= 0; --r) {
-                        yr = fmaf(yr, z, acc[t][r][0][j]);
-                        yi = fmaf(yi, z, acc[t][r][1][j]);
-                    }
-                    store_nt(c.jb.y + c.M0 + off, make_float2(yr * unscale, yi * unscale));
-                }
-            }
-            if (__any(near != 0)) {  // rare: uniform over the wave
-                const auto xg = gmem(c.jb.x);
-#pragma unroll 1
-                for (int b = 0; b < 8; ++b) {
-                    if (!((near >> b) & 1u))
-                        continue;
-                    const int t = b >> 2, j = b & 3;
-                    const int off = 256 * (wave + 4 * t) + 16 * (4 * (lane >> 4) + j) + (lane & 15);
-                    const int64_t m = c.M0 + off;
-                    const double md = (double)m;
-                    if (((__dmul_rn(alpha, md) - md) - c.tp.Sd) == 0.0) {
-                        const int64_t src = m + S;
-                        float2 v = make_float2(0.f, 0.f);
-                        if (src >= 0 && src < c.jb.n_in)
-                            v = xg[src];
-                        yt[off] = v;
-                    }
-                }
-            }
-        }
-        if (i + 1 < i1)
-            __syncthreads();  // the next tile's A and B are in LDS
+        if (active)
+            W.store(c, cxe);
     }
 }
 
