@@ -636,8 +636,13 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
         const MfCur c = cur;
         const int cxe = xe;
         const bool active = W.active(c);
-        if (active)
+        if (active) {
+            // the products at the highest issue priority: when the other wave on this SIMD is in
+            // its vector phase, the matrix core's next instruction still issues first
+            __builtin_amdgcn_s_setprio(3);
             W.gemm();
+            __builtin_amdgcn_s_setprio(0);
+        }
         if (i + 1 < i1) {
             cur = nxt;
             xe = W.active(cur) ? W.stage() : 0;
