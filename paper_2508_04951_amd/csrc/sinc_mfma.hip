@@ -283,6 +283,17 @@ __device__ __forceinline__ float wave_max_nonneg(float v)
     return __int_as_float(max(a, b));
 }
 
+// max(m, |a|, |b|) in one instruction: v_max3_f32 with absolute-value source modifiers.  fmaxf
+// on loaded samples, which the compiler cannot prove canonical, would first quiet each of them
+// with an instruction of its own.  A quiet NaN operand is ignored either way; signalling NaNs do
+// not come out of arithmetic.
+__device__ __forceinline__ float max3_abs(float m, float a, float b)
+{
+    float r;
+    asm("v_max3_f32 %0, %1, |%2|, |%3|" : "=v"(r) : "v"(m), "v"(a), "v"(b));
+    return r;
+}
+
 // A wave-uniform 64-bit integer held in scalar registers (the value of the first active lane).
 __device__ __forceinline__ int64_t uniform64(int64_t v)
 {
@@ -405,7 +416,7 @@ struct MfWave {
         for (int q = 0; q < G::wpp; ++q)
 #pragma unroll
             for (int h2 = 0; h2 < 2; ++h2)
-                mx = fmaxf(mx, fmaxf(fabsf(xv[q][h2].x), fabsf(xv[q][h2].y)));
+                mx = max3_abs(mx, xv[q][h2].x, xv[q][h2].y);
         mx = wave_max_nonneg(mx);
         int xe = 0;
         if (mx > 0.f) {
@@ -441,59 +452,99 @@ struct MfWave {
     // together: each B fragment is read from LDS once per 32-tap step for both.  A fragments:
     // lane (i, q) = (l % 16, l / 16) holds the 8 samples at 16 i + 8 q + 32 s of its sub-tile's
     // span (aligned 8-sample runs of the Hankel matrix).
+    //
+    // A step runs three groups of products: lo*hi of the low orders (xl, bh), hi*hi of every
+    // order (xh, bh), hi*lo of the low orders (xh, bl).  Each register of the step's fragments is
+    // refilled with the next step's as soon as its last product of this step has issued: xl after
+    // the first group, bh[r] after the hi*hi products of order r, xh[t][c] after its hi*lo
+    // products, bl last.  Every fragment thus has at least eight products to hide its read behind.
+    // Scheduling barriers keep the compiler from moving the reads next to their first use.
     __device__ __forceinline__ void gemm()
     {
         const int arow = 16 * (lane & 15) + 8 * (lane >> 4);
-        // step s of the contraction; the first step starts every accumulator from zero (the
-        // matrix core's inline constant), so nothing is cleared beforehand
-        auto kstep = [&](int s, bool first) {
-            half8 xh[2][2], xl[2][2];  // [sub-tile][re/im]
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int e = arow + kSubTile * t + 32 * s;
-                xh[t][0] = *reinterpret_cast<const half8 *>(a_rh + e);
-                xl[t][0] = *reinterpret_cast<const half8 *>(a_rl + e);
-                xh[t][1] = *reinterpret_cast<const half8 *>(a_ih + e);
-                xl[t][1] = *reinterpret_cast<const half8 *>(a_il + e);
-            }
-            const half8 *blk = reinterpret_cast<const half8 *>(bsm + s * kMfBlk * 1024);
-            half8 bh[kMfOrders], bl[kMfLo];
-#pragma unroll
-            for (int r = 0; r < kMfOrders; ++r)
-                bh[r] = blk[64 * r + lane];
-#pragma unroll
-            for (int r = 0; r < kMfLo; ++r)
-                bl[r] = blk[64 * (kMfOrders + r) + lane];
-            // hi*hi for every order, then hi*lo and lo*hi for the low orders: at least eight
-            // independent products between two that update the same accumulator
-#pragma unroll
-            for (int r = 0; r < kMfOrders; ++r)
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int c2 = 0; c2 < 2; ++c2)
-                        acc[t][r][c2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                            xh[t][c2], bh[r], first ? floatx4{0.f, 0.f, 0.f, 0.f} : acc[t][r][c2], 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < kMfLo; ++r)
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int c2 = 0; c2 < 2; ++c2)
-                        acc[t][r][c2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh[t][c2], bl[r], acc[t][r][c2], 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < kMfLo; ++r)
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int c2 = 0; c2 < 2; ++c2)
-                        acc[t][r][c2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl[t][c2], bh[r], acc[t][r][c2], 0, 0, 0);
+        half8 xh[2][2], xl[2][2], bh[kMfOrders], bl[kMfLo];  // x: [sub-tile][re/im]
+        const _Float16 *const xre[2] = {a_rh, a_rl}, *const xim[2] = {a_ih, a_il};
+        auto ld_x = [&](int lo, int s, int t, int c2) {
+            const _Float16 *const base = c2 ? xim[lo] : xre[lo];
+            return *reinterpret_cast<const half8 *>(base + arow + kSubTile * t + 32 * s);
         };
-        kstep(0, true);
-        // not unrolled: hoisting the next step's fragments would cost the second wave per SIMD
+        auto ld_b = [&](int s, int j) {
+            return reinterpret_cast<const half8 *>(bsm + s * kMfBlk * 1024)[64 * j + lane];
+        };
+        auto mfma = [&](const half8 &x, const half8 &w, floatx4 &c, bool zero) {
+            c = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, w, zero ? floatx4{0.f, 0.f, 0.f, 0.f} : c, 0, 0, 0);
+        };
+        // step s; the first starts every accumulator from zero (the matrix core's inline
+        // constant), so nothing is cleared beforehand; `more`: read step s + 1's fragments
+        auto kstep = [&](int s, bool first, bool more) {
+#pragma unroll
+            for (int r = 0; r < kMfLo; ++r)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2)
+                        mfma(xl[t][c2], bh[r], acc[t][r][c2], first);
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2)
+                        xl[t][c2] = ld_x(1, s + 1, t, c2);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int r = 0; r < kMfOrders; ++r) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2)
+                        mfma(xh[t][c2], bh[r], acc[t][r][c2], first && r >= kMfLo);
+                __builtin_amdgcn_sched_barrier(0);
+                if (more)
+                    bh[r] = ld_b(s + 1, r);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int c2 = 0; c2 < 2; ++c2) {
+#pragma unroll
+                    for (int r = 0; r < kMfLo; ++r)
+                        mfma(xh[t][c2], bl[r], acc[t][r][c2], false);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (more)
+                        xh[t][c2] = ld_x(0, s + 1, t, c2);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            if (more) {
+#pragma unroll
+                for (int r = 0; r < kMfLo; ++r)
+                    bl[r] = ld_b(s + 1, kMfOrders + r);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        };
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+                xl[t][c2] = ld_x(1, 0, t, c2);
+#pragma unroll
+        for (int r = 0; r < kMfOrders; ++r)
+            bh[r] = ld_b(0, r);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+                xh[t][c2] = ld_x(0, 0, t, c2);
+#pragma unroll
+        for (int r = 0; r < kMfLo; ++r)
+            bl[r] = ld_b(0, kMfOrders + r);
+        kstep(0, true, true);
 #pragma unroll 1
-        for (int s = 1; s < G::ksteps; ++s)
-            kstep(s, false);
+        for (int s = 1; s < G::ksteps - 1; ++s)
+            kstep(s, false, true);
+        kstep(G::ksteps - 1, false, false);
     }
 
     // Lane holds Z_r[row 4 (l/16) + j][col l % 16] of each sub-tile: output
