@@ -61,7 +61,13 @@ struct MfGeom {
     static constexpr int ntap = 2 * H + 1;
     static constexpr int kext = ((2 * H + 16) + 31) / 32 * 32;
     static constexpr int ksteps = kext / 32;
-    static constexpr int wout = 2 * kSubTile;                  // outputs per wave and tile
+    // Sub-tiles per wave: two at H = 64, whose LDS fits two four-wave workgroups per CU; one at
+    // H = 128, where a four-wave workgroup would be alone on its CU with one wave per SIMD, so
+    // the tile goes to eight waves sharing one B block (two waves per SIMD).
+    static constexpr int nsub = H <= 64 ? 2 : 1;
+    static constexpr int nwaves = kSincMfmaTile / (nsub * kSubTile);
+    static constexpr int threads = 64 * nwaves;
+    static constexpr int wout = nsub * kSubTile;               // outputs per wave and tile
     static constexpr int wspan = wout + kext;                  // samples staged per wave
     static constexpr int wpp = (wspan + 127) / 128;            // staged sample pairs per lane
     static constexpr int rowlen = kext + 32;                   // padded coefficient row (halves)
@@ -71,12 +77,13 @@ struct MfGeom {
     // im lo; 64-byte multiples, so every region stays 16-byte aligned)
     static constexpr int a_off = bbytes;
     static constexpr int a_wave = 4 * wspan;                   // halves per wave region
-    static constexpr int bytes = a_off + 4 * a_wave * 2;
+    static constexpr int bytes = a_off + nwaves * a_wave * 2;
     // table kernel LDS: coefficient rows [order][part][rowlen]
     static constexpr int rows_bytes = kMfOrders * 2 * rowlen * 2;
 };
 
-static_assert(4 * 2 * kSubTile == kMfOut, "four waves of two sub-tiles cover a tile");
+static_assert(MfGeom<64>::nwaves * MfGeom<64>::wout == kMfOut && MfGeom<128>::nwaves * MfGeom<128>::wout == kMfOut,
+              "the waves' sub-tiles cover a tile");
 static_assert(MfGeom<64>::wspan % 32 == 0 && MfGeom<128>::wspan % 32 == 0, "wave regions stay aligned");
 
 // The Kaiser series with a fixed number of terms NT >= kp.n (terms past kp.n are zero).
@@ -258,9 +265,9 @@ k_mf_tile_scatter(const uint2 *__restrict__ ref, const unsigned char *__restrict
 // the grid is persistent: workgroup b takes the run c(b) of the sorted list, where c deals
 // consecutive b to different XCDs so that an XCD holds a contiguous range of phases.
 //
-// Wave w of a group of four owns outputs 512 w .. 512 w + 511 of the group's tile (sub-tiles 2w
-// and 2w + 1) and stages the input they read, wspan = 512 + kext samples, into an LDS region of
-// its own with a scale of its own: the waves share only the phase's B block.
+// Wave w owns outputs wout w .. wout (w + 1) - 1 of the workgroup's tile (its nsub sub-tiles of
+// 256) and stages the input they read, wspan = wout + kext samples, into an LDS region of its
+// own with a scale of its own: the waves share only the phase's B block.
 // A tile of the persistent loop: its job, first output and position in the input.
 struct MfCur {
     SincJob jb;
@@ -357,7 +364,7 @@ struct MfWave {
     _Float16 *a_rh, *a_rl, *a_ih, *a_il;  // this wave's region: re hi, re lo, im hi, im lo
     int lane, wbase;                 // wbase: this wave's first output in a tile
     float2 xv[G::wpp][2];            // the fetched span, two samples per lane and step
-    floatx4 acc[2][kMfOrders][2];    // Z_r of the two sub-tiles, re and im
+    floatx4 acc[G::nsub][kMfOrders][2];  // Z_r of the wave's sub-tiles, re and im
 
     __device__ __forceinline__ MfWave(unsigned char *smem, int region, int lane_, int wbase_)
         : bsm(smem), lane(lane_), wbase(wbase_)
@@ -448,8 +455,8 @@ struct MfWave {
         return xe;
     }
 
-    // The matrix products of the staged span with the B block.  The wave runs its two sub-tiles
-    // together: each B fragment is read from LDS once per 32-tap step for both.  A fragments:
+    // The matrix products of the staged span with the B block.  The wave runs its sub-tiles
+    // together: each B fragment is read from LDS once per 32-tap step for all of them.  A fragments:
     // lane (i, q) = (l % 16, l / 16) holds the 8 samples at 16 i + 8 q + 32 s of its sub-tile's
     // span (aligned 8-sample runs of the Hankel matrix).
     //
@@ -462,7 +469,7 @@ struct MfWave {
     __device__ __forceinline__ void gemm()
     {
         const int arow = 16 * (lane & 15) + 8 * (lane >> 4);
-        half8 xh[2][2], xl[2][2], bh[kMfOrders], bl[kMfLo];  // x: [sub-tile][re/im]
+        half8 xh[G::nsub][2], xl[G::nsub][2], bh[kMfOrders], bl[kMfLo];  // x: [sub-tile][re/im]
         const _Float16 *const xre[2] = {a_rh, a_rl}, *const xim[2] = {a_ih, a_il};
         auto ld_x = [&](int lo, int s, int t, int c2) {
             const _Float16 *const base = c2 ? xim[lo] : xre[lo];
@@ -480,14 +487,14 @@ struct MfWave {
 #pragma unroll
             for (int r = 0; r < kMfLo; ++r)
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int t = 0; t < G::nsub; ++t)
 #pragma unroll
                     for (int c2 = 0; c2 < 2; ++c2)
                         mfma(xl[t][c2], bh[r], acc[t][r][c2], first);
             __builtin_amdgcn_sched_barrier(0);
             if (more) {
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int t = 0; t < G::nsub; ++t)
 #pragma unroll
                     for (int c2 = 0; c2 < 2; ++c2)
                         xl[t][c2] = ld_x(1, s + 1, t, c2);
@@ -496,7 +503,7 @@ struct MfWave {
 #pragma unroll
             for (int r = 0; r < kMfOrders; ++r) {
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int t = 0; t < G::nsub; ++t)
 #pragma unroll
                     for (int c2 = 0; c2 < 2; ++c2)
                         mfma(xh[t][c2], bh[r], acc[t][r][c2], first && r >= kMfLo);
@@ -506,7 +513,7 @@ struct MfWave {
                 __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+            for (int t = 0; t < G::nsub; ++t)
 #pragma unroll
                 for (int c2 = 0; c2 < 2; ++c2) {
 #pragma unroll
@@ -525,7 +532,7 @@ struct MfWave {
             __builtin_amdgcn_sched_barrier(0);
         };
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < G::nsub; ++t)
 #pragma unroll
             for (int c2 = 0; c2 < 2; ++c2)
                 xl[t][c2] = ld_x(1, 0, t, c2);
@@ -533,7 +540,7 @@ struct MfWave {
         for (int r = 0; r < kMfOrders; ++r)
             bh[r] = ld_b(0, r);
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < G::nsub; ++t)
 #pragma unroll
             for (int c2 = 0; c2 < 2; ++c2)
                 xh[t][c2] = ld_x(0, 0, t, c2);
@@ -585,7 +592,7 @@ struct MfWave {
         if (full && !may_hit) {
             // the usual tile (uniform): no output to check, constant offsets from the lane's first
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+            for (int t = 0; t < G::nsub; ++t)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const float dm = dml + (float)(kSubTile * t + 16 * j);
@@ -593,7 +600,7 @@ struct MfWave {
                 }
         } else {
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
+            for (int t = 0; t < G::nsub; ++t) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if (!full && loff + kSubTile * t + 16 * j >= nvalid)
@@ -608,7 +615,7 @@ struct MfWave {
         if (__any(near != 0)) {  // rare: uniform over the wave
             const auto xg = gmem(c.jb.x);
 #pragma unroll 1
-            for (int b = 0; b < 8; ++b) {
+            for (int b = 0; b < 4 * G::nsub; ++b) {
                 if (!((near >> b) & 1u))
                     continue;
                 const int t = b >> 2, j = b & 3;
@@ -627,13 +634,17 @@ struct MfWave {
     }
 };
 
-// Four waves, one tile at a time: the tiles of a list run (persistent grid, two workgroups per
-// CU), or without a list tile blockIdx.x of job blockIdx.y.  Per tile: the matrix products, then
-// the staging of the next tile's span (its loads were issued a tile ahead, before this wave's
-// previous stores) and the fetch of the one after, then this tile's stores.  The waves wait for
-// each other only when the phase changes.
+// One tile at a time (four waves of two sub-tiles at H = 64, eight of one at H = 128): the tiles
+// of a list run (persistent grid), or without a list tile blockIdx.x of job blockIdx.y.  Per
+// tile: the matrix products, then the staging of the next tile's span (its loads were issued a
+// tile ahead, before this wave's previous stores) and the fetch of the one after, then this
+// tile's stores.  The waves wait for each other only when the phase changes.  Two workgroups
+// share a CU at H = 64, one at H = 128 (LDS); either way a SIMD runs two waves.
 template <int H>
-__global__ void __launch_bounds__(256, 2)
+constexpr int mf_wg_per_cu() { return 2 * MfGeom<H>::bytes <= 160 * 1024 ? 2 : 1; }
+
+template <int H>
+__global__ void __launch_bounds__(MfGeom<H>::threads, mf_wg_per_cu<H>())
 k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restrict__ list, int64_t ntiles,
             const unsigned char *__restrict__ table)
 {
@@ -665,7 +676,7 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
     if (cur.M0 >= cur.jb.n_out)
         return;  // only without a list (ragged jobs); uniform over the workgroup
     int cur_p = cur.tp.p;
-    mf_load_b<H, 256>(table, cur_p, smem, tid);
+    mf_load_b<H, G::threads>(table, cur_p, smem, tid);
     if (W.active(cur))
         W.fetch(cur);
     int xe = W.active(cur) ? W.stage() : 0;
@@ -680,7 +691,7 @@ k_sinc_mfma(const SincJob *__restrict__ jobs, SincJob inl, const uint2 *__restri
     for (int64_t i = i0; i < i1; ++i) {
         if (cur.tp.p != cur_p) {  // uniform over the workgroup: every wave walks the same run
             __syncthreads();      // every wave is done with the previous block
-            mf_load_b<H, 256>(table, cur.tp.p, smem, tid);
+            mf_load_b<H, G::threads>(table, cur.tp.p, smem, tid);
             cur_p = cur.tp.p;
             __syncthreads();
         }
@@ -788,7 +799,7 @@ hipError_t mf_device(MfDevice **out)
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sinc_mfma<H>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.per_cu, k_sinc_mfma<H>, 256, lds);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.per_cu, k_sinc_mfma<H>, MfGeom<H>::threads, lds);
         if (e == hipSuccess)
             e = hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess)
@@ -839,8 +850,8 @@ hipError_t launch_h(const SincJob *jobs_dev, const SincJob &inl, int njobs, int6
         const int64_t nblk = (max_out + kMfOut - 1) / kMfOut;
         if (prof)
             prof->begin(kKSincMfma, s);
-        hipLaunchKernelGGL(k_sinc_mfma<H>, dim3((unsigned)nblk, (unsigned)njobs), dim3(256), lds, s, jobs_dev,
-                           inl, nullptr, (int64_t)0, table);
+        hipLaunchKernelGGL(k_sinc_mfma<H>, dim3((unsigned)nblk, (unsigned)njobs), dim3(MfGeom<H>::threads), lds, s,
+                           jobs_dev, inl, nullptr, (int64_t)0, table);
         e = hipGetLastError();
         if (prof)
             prof->end(s);
@@ -893,8 +904,8 @@ run:
         grid -= grid % kXcds;
     if (prof)
         prof->begin(kKSincMfma, s);
-    hipLaunchKernelGGL(k_sinc_mfma<H>, dim3((unsigned)grid), dim3(256), lds, s, jobs_dev, SincJob{}, list, ntiles,
-                       table);
+    hipLaunchKernelGGL(k_sinc_mfma<H>, dim3((unsigned)grid), dim3(MfGeom<H>::threads), lds, s, jobs_dev, SincJob{},
+                       list, ntiles, table);
     e = hipGetLastError();
     if (prof)
         prof->end(s);
