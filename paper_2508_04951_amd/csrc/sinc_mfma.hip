@@ -460,12 +460,13 @@ struct MfWave {
     // lane (i, q) = (l % 16, l / 16) holds the 8 samples at 16 i + 8 q + 32 s of its sub-tile's
     // span (aligned 8-sample runs of the Hankel matrix).
     //
-    // A step runs three groups of products: lo*hi of the low orders (xl, bh), hi*hi of every
-    // order (xh, bh), hi*lo of the low orders (xh, bl).  Each register of the step's fragments is
-    // refilled with the next step's as soon as its last product of this step has issued: xl after
-    // the first group, bh[r] after the hi*hi products of order r, xh[t][c] after its hi*lo
-    // products, bl last.  Every fragment thus has at least eight products to hide its read behind.
-    // Scheduling barriers keep the compiler from moving the reads next to their first use.
+    // A step runs, sub-tile by sub-tile, three groups of products: lo*hi of the low orders (xl,
+    // bh), hi*hi of every order (xh, bh), hi*lo of the low orders (xh, bl).  Each register of
+    // the step's fragments is refilled with the next step's as soon as its last product of this
+    // step has issued: a sub-tile's xl after its first group and its xh[c] after its hi*lo
+    // products, bh[r] after the last sub-tile's hi*hi products of order r, bl last.  With two
+    // sub-tiles every fragment has at least twelve products to hide its read behind (four with
+    // one).  Scheduling barriers keep the compiler from moving the reads next to their first use.
     __device__ __forceinline__ void gemm()
     {
         const int arow = 16 * (lane & 15) + 8 * (lane >> 4);
@@ -485,35 +486,32 @@ struct MfWave {
         // constant), so nothing is cleared beforehand; `more`: read step s + 1's fragments
         auto kstep = [&](int s, bool first, bool more) {
 #pragma unroll
-            for (int r = 0; r < kMfLo; ++r)
+            for (int t = 0; t < G::nsub; ++t) {
+                const bool last = t == G::nsub - 1;
 #pragma unroll
-                for (int t = 0; t < G::nsub; ++t)
+                for (int r = 0; r < kMfLo; ++r)
 #pragma unroll
                     for (int c2 = 0; c2 < 2; ++c2)
                         mfma(xl[t][c2], bh[r], acc[t][r][c2], first);
-            __builtin_amdgcn_sched_barrier(0);
-            if (more) {
-#pragma unroll
-                for (int t = 0; t < G::nsub; ++t)
+                __builtin_amdgcn_sched_barrier(0);
+                if (more) {
 #pragma unroll
                     for (int c2 = 0; c2 < 2; ++c2)
                         xl[t][c2] = ld_x(1, s + 1, t, c2);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int r = 0; r < kMfOrders; ++r) {
-#pragma unroll
-                for (int t = 0; t < G::nsub; ++t)
+                for (int r = 0; r < kMfOrders; ++r) {
 #pragma unroll
                     for (int c2 = 0; c2 < 2; ++c2)
                         mfma(xh[t][c2], bh[r], acc[t][r][c2], first && r >= kMfLo);
-                __builtin_amdgcn_sched_barrier(0);
-                if (more)
-                    bh[r] = ld_b(s + 1, r);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int t = 0; t < G::nsub; ++t)
+                    if (last) {
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (more)
+                            bh[r] = ld_b(s + 1, r);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
 #pragma unroll
                 for (int c2 = 0; c2 < 2; ++c2) {
 #pragma unroll
@@ -524,6 +522,7 @@ struct MfWave {
                         xh[t][c2] = ld_x(0, s + 1, t, c2);
                     __builtin_amdgcn_sched_barrier(0);
                 }
+            }
             if (more) {
 #pragma unroll
                 for (int r = 0; r < kMfLo; ++r)
