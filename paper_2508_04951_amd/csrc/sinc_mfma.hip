@@ -74,9 +74,10 @@ struct MfGeom {
     static constexpr int node_iters = (ntap + 47) / 48;       // 12 taps x 5 nodes per wave
     static constexpr int bbytes = ksteps * kMfBlk * 1024;  // B fragments of one phase
     // main kernel LDS: B block, then per wave 4 fp16 arrays of `wspan` (re hi, re lo, im hi,
-    // im lo; 64-byte multiples, so every region stays 16-byte aligned)
+    // im lo; 64-byte multiples, so every region stays 16-byte aligned), sample e at a_pad(e)
     static constexpr int a_off = bbytes;
-    static constexpr int a_wave = 4 * wspan;                   // halves per wave region
+    static constexpr int pspan = wspan;                        // halves per array
+    static constexpr int a_wave = 4 * pspan;                   // halves per wave region
     static constexpr int bytes = a_off + nwaves * a_wave * 2;
     // table kernel LDS: coefficient rows [order][part][rowlen]
     static constexpr int rows_bytes = kMfOrders * 2 * rowlen * 2;
@@ -85,6 +86,13 @@ struct MfGeom {
 static_assert(MfGeom<64>::nwaves * MfGeom<64>::wout == kMfOut && MfGeom<128>::nwaves * MfGeom<128>::wout == kMfOut,
               "the waves' sub-tiles cover a tile");
 static_assert(MfGeom<64>::wspan % 32 == 0 && MfGeom<128>::wspan % 32 == 0, "wave regions stay aligned");
+
+// Position of span sample e in a staged array.  A fragment read serves eight lanes of a row at a
+// time, 16 bytes each at 32-byte steps, against 128 bytes of banks: lanes i and i + 4 would hit
+// the same banks.  Swapping the two 16-byte halves of every other 128 bytes separates them.
+// Runs of 8 samples that start at a multiple of 8 stay contiguous, and
+// a_pad(e + 256) = a_pad(e) + 256.
+__device__ __forceinline__ int a_pad(int e) { return e ^ (((e >> 6) & 1) << 3); }
 
 // The Kaiser series with a fixed number of terms NT >= kp.n (terms past kp.n are zero).
 constexpr int kMfKaiserTerms = 32;
@@ -370,9 +378,9 @@ struct MfWave {
         : bsm(smem), lane(lane_), wbase(wbase_)
     {
         a_rh = reinterpret_cast<_Float16 *>(smem + G::a_off) + region * G::a_wave;
-        a_rl = a_rh + G::wspan;
-        a_ih = a_rl + G::wspan;
-        a_il = a_ih + G::wspan;
+        a_rl = a_rh + G::pspan;
+        a_ih = a_rl + G::pspan;
+        a_il = a_ih + G::pspan;
     }
 
     // this wave has outputs in tile t (uniform over the wave)
@@ -445,10 +453,11 @@ struct MfWave {
                 const half2v ih = pkrtz(i0f, i1f);
                 const half2v rl = pkrtz(r0 - (float)rh[0], r1 - (float)rh[1]);
                 const half2v il = pkrtz(i0f - (float)ih[0], i1f - (float)ih[1]);
-                *reinterpret_cast<half2v *>(a_rh + e) = rh;
-                *reinterpret_cast<half2v *>(a_rl + e) = rl;
-                *reinterpret_cast<half2v *>(a_ih + e) = ih;
-                *reinterpret_cast<half2v *>(a_il + e) = il;
+                const int pe = a_pad(e);
+                *reinterpret_cast<half2v *>(a_rh + pe) = rh;
+                *reinterpret_cast<half2v *>(a_rl + pe) = rl;
+                *reinterpret_cast<half2v *>(a_ih + pe) = ih;
+                *reinterpret_cast<half2v *>(a_il + pe) = il;
             }
         }
         wave_lds_sync();  // and its lanes' stores are seen by its lanes' fragment loads
@@ -474,7 +483,7 @@ struct MfWave {
         const _Float16 *const xre[2] = {a_rh, a_rl}, *const xim[2] = {a_ih, a_il};
         auto ld_x = [&](int lo, int s, int t, int c2) {
             const _Float16 *const base = c2 ? xim[lo] : xre[lo];
-            return *reinterpret_cast<const half8 *>(base + arow + kSubTile * t + 32 * s);
+            return *reinterpret_cast<const half8 *>(base + a_pad(arow + 32 * s) + kSubTile * t);
         };
         auto ld_b = [&](int s, int j) {
             return reinterpret_cast<const half8 *>(bsm + s * kMfBlk * 1024)[64 * j + lane];
