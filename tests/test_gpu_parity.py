@@ -79,7 +79,8 @@ def test_doppler_integer_alpha_is_bit_exact(torch, ctx, alpha):
 
 
 ALPHAS = [alpha_exact(8000.0), alpha_exact(-8000.0), alpha_exact(7500.0), 1 + 1e-6, 1 - 3e-7, 1.3, 0.77]
-SINCS = [(64, "kaiser", 8.0), (8, "kaiser", 5.0), (16, "rect", 0.0), (20, "paper", 0.0), (0, "kaiser", 8.0)]
+SINCS = [(64, "kaiser", 8.0), (128, "kaiser", 8.0), (8, "kaiser", 5.0), (16, "rect", 0.0), (20, "paper", 0.0),
+         (0, "kaiser", 8.0)]
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 1000, 1025, 4096, 5000])
