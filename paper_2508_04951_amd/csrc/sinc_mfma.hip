@@ -24,8 +24,11 @@
 // Batches of many tiles run persistent workgroups over a tile list sorted by phase (built on the
 // device by k_mf_tile_phase, k_mf_tile_count and k_mf_tile_scatter): a workgroup walks a run of
 // that list, copies a phase's B block into LDS only when the phase changes, and prefetches the
-// next tile's input into registers while the matrix cores work on the current one.  Consecutive workgroup indices
-// are spread over the eight XCDs, so each XCD's L2 serves a contiguous range of phases.
+// next tile's input into registers while the matrix cores work on the current one.  Consecutive
+// workgroup indices are spread over the eight XCDs, so each XCD's L2 serves a contiguous range of
+// phases.  Each wave stages its own part of the tile's input (two sub-tiles at H = 64, one at
+// H = 128, so that a SIMD always runs two waves) into LDS with its own scale, in a bank swizzle
+// that keeps the Hankel fragment reads free of conflicts.
 #include <cmath>
 #include <vector>
 
