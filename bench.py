@@ -768,7 +768,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path (asked for "
+        print(f"bench.py runs on exactly one GPU: the library has no multi-GPU path (asked for "
               f"--gpus {args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
         sys.exit(2)
 

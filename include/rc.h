@@ -41,7 +41,7 @@ typedef struct {
 typedef enum {
     RC_OK = 0,
     RC_ERR_INVALID_ARG = 1,   /* bad pointer, size, parameter or overlap; nothing enqueued */
-    RC_ERR_UNSUPPORTED = 2,   /* a valid request this build cannot serve */
+    RC_ERR_UNSUPPORTED = 2,   /* a valid request the library cannot serve */
     RC_ERR_OUT_OF_MEMORY = 3, /* workspace or table allocation failed */
     RC_ERR_DEVICE = 4,        /* a HIP runtime call or a kernel failed */
     RC_ERR_BUSY = 5           /* reserved for admission control */
